@@ -1,0 +1,493 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms
+(moments of the equilibria, Fourier symbols of the stencils, the tanh identities of
+Sect. 2), invariants (conservation, symmetry), textbook limits (diffusion, shear
+wave, Couette, Laplace), a dense brute-force implementation on tiny grids, and the
+paper's qualitative claim about small drops.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import D2Q9, D3Q19, Model
+from oracle.model import derived_observables, observables_from_phi
+from tests.bruteforce import Dense2D
+
+RNG = np.random.default_rng(2505)
+
+
+# --------------------------------------------------------------------------- lattice
+@pytest.mark.parametrize("lat", [D2Q9, D3Q19], ids=["D2Q9", "D3Q19"])
+def test_lattice_isotropy(lat):
+    c = lat.c[:, : lat.D].astype(float)
+    w = lat.w
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.allclose(w @ c, 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, c, c), lat.cs2 * np.eye(lat.D), atol=1e-15)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, c, c, c), 0, atol=1e-16)
+    d = np.eye(lat.D)
+    iso4 = lat.cs2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+                           + np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c), iso4, atol=1e-15)
+    for i in range(lat.Q):
+        assert np.array_equal(lat.c[lat.opp[i]], -lat.c[i])
+
+
+def test_d2q9_velocities_match_eq19_table():
+    # Eq. 19 evaluated by hand: rest, E, N, W, S, NE, NW, SW, SE
+    want = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    assert [tuple(v) for v in D2Q9.c[:, :2]] == want
+    assert np.allclose(D2Q9.w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def test_d2q9_M_rows_are_their_polynomials_and_orthogonal():
+    c = D2Q9.c[:, :2].astype(float)
+    cx, cy = c[:, 0], c[:, 1]
+    c2 = cx ** 2 + cy ** 2
+    rows = [np.ones(9), -4 + 3 * c2, 4 - 10.5 * c2 + 4.5 * c2 ** 2, cx, (-5 + 3 * c2) * cx, cy,
+            (-5 + 3 * c2) * cy, cx ** 2 - cy ** 2, cx * cy]
+    assert np.array_equal(D2Q9.M, np.array(rows))
+    assert np.array_equal(D2Q9.M @ D2Q9.M.T, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]).astype(float))
+
+
+def test_d3q19_basis_orthogonal_and_conserved_rows():
+    M = D3Q19.M
+    G = M @ M.T
+    assert np.allclose(G, np.diag(np.diag(G)), atol=1e-12)
+    assert np.all(np.diag(G) > 0)
+    c = D3Q19.c.astype(float)
+    assert np.array_equal(M[0], np.ones(19))
+    for row, axis in ((3, 0), (5, 1), (7, 2)):
+        assert np.array_equal(M[row], c[:, axis])
+
+
+# --------------------------------------------------------------------------- equilibria and sources
+def _rand_fields(lat, n=7):
+    D = lat.D
+    phi = RNG.uniform(-0.1, 1.1, n)
+    mu = RNG.normal(0, 1e-2, n)
+    u = RNG.normal(0, 0.05, (D, n))
+    press = RNG.normal(0, 1e-3, n)
+    rho = RNG.uniform(0.01, 1.0, n)
+    return phi, mu, u, press, rho
+
+
+def _model_for(lat):
+    if lat.name == "D2Q9":
+        return Model(W.CaseParams(nx=4, ny=4, lam=0.5))
+    return Model(W.CaseParams(nx=4, ny=4, nz=4, lattice="D3Q19", lam=0.5))
+
+
+@pytest.mark.parametrize("lat", [D2Q9, D3Q19], ids=["D2Q9", "D3Q19"])
+def test_g_equilibrium_moments(lat):
+    m = _model_for(lat)
+    phi, mu, u, _, _ = _rand_fields(lat)
+    geq = m.g_equilibrium(phi, mu, u)
+    c = lat.c[:, : lat.D].astype(float)
+    H = mu + 0.5 * phi
+    assert np.allclose(geq.sum(0), phi, atol=1e-15)
+    assert np.allclose(np.einsum("ia,in->an", c, geq), phi * u, atol=1e-15)
+    second = np.einsum("ia,ib,in->abn", c, c, geq)
+    assert np.allclose(second, lat.cs2 * H[None, None, :] * np.eye(lat.D)[:, :, None], atol=1e-15)
+
+
+@pytest.mark.parametrize("lat", [D2Q9, D3Q19], ids=["D2Q9", "D3Q19"])
+def test_f_equilibrium_moments(lat):
+    m = _model_for(lat)
+    _, _, u, press, rho = _rand_fields(lat)
+    feq = m.f_equilibrium(press, rho, u)
+    c = lat.c[:, : lat.D].astype(float)
+    assert np.allclose(feq.sum(0), 0, atol=1e-16)
+    assert np.allclose(np.einsum("ia,in->an", c, feq), rho * u, atol=1e-15)
+    second = np.einsum("ia,ib,in->abn", c, c, feq)
+    want = press[None, None] * np.eye(lat.D)[:, :, None] + rho * np.einsum("an,bn->abn", u, u)
+    assert np.allclose(second, want, atol=1e-15)
+    # Eq. 29 inverts Eq. 22 at equilibrium: p = cs^2/(1-w0) [sum_{i!=0} f_eq + rho s0(u)]
+    s0 = m.s_i(u)[0]
+    assert np.allclose(lat.cs2 / (1 - lat.w[0]) * (feq[1:].sum(0) + rho * s0), press, atol=1e-15)
+
+
+@pytest.mark.parametrize("lat", [D2Q9, D3Q19], ids=["D2Q9", "D3Q19"])
+def test_forcing_moments_and_simplified_form(lat):
+    m = _model_for(lat)
+    _, _, u, _, _ = _rand_fields(lat)
+    grho = RNG.normal(0, 0.1, u.shape)
+    Fs = RNG.normal(0, 1e-3, u.shape)
+    Fi = m.f_forcing(u, grho, Fs)
+    c = lat.c[:, : lat.D].astype(float)
+    w = lat.w[:, None]
+    simple = w * (np.einsum("ia,an->in", c, Fs) + np.einsum("ia,an->in", c, u) * np.einsum("ia,an->in", c, grho)) / lat.cs2
+    assert np.allclose(Fi, simple, atol=1e-16)
+    assert np.allclose(Fi.sum(0), (u * grho).sum(0), atol=1e-16)
+    assert np.allclose(np.einsum("ia,in->an", c, Fi), Fs, atol=1e-16)
+
+
+def test_source_term_projects_onto_flux_moments_only():
+    m = _model_for(D2Q9)
+    V = RNG.normal(0, 1, (2, 5))
+    G = m.g_source(V)
+    Gbar = D2Q9.M @ G
+    assert np.allclose(Gbar[[0, 1, 2, 7, 8]], 0, atol=1e-15)
+    assert np.allclose(Gbar[3], V[0] / 3) and np.allclose(Gbar[4], -V[0] / 3)
+    assert np.allclose(Gbar[5], V[1] / 3) and np.allclose(Gbar[6], -V[1] / 3)
+
+
+# --------------------------------------------------------------------------- signed distance (Eqs. 12-16, 37)
+def test_psi_identities():
+    m = Model(W.CaseParams(nx=4, ny=4, W=4.0))
+    phi = np.linspace(-0.2, 1.2, 1401)
+    psi = m.psi_of(phi)
+    pc = np.clip(phi, 0, 1)
+    a, b = pc + 1e-10, 1 - pc + 1e-10
+    # 1 - tanh^2(2 psi / W) = 4ab / (a + b)^2   (Eq. 15 with the Eq. 37 regulariser)
+    assert np.max(np.abs((1 - np.tanh(2 * psi / 4.0) ** 2) - 4 * a * b / (a + b) ** 2)) < 1e-15
+    assert m.psi_of(np.array(0.5)) == 0.0
+    inner = (phi > 1e-6) & (phi < 1 - 1e-6)
+    assert np.allclose(m.psi_of(1 - phi[inner]), -psi[inner], atol=1e-12)
+    # Eq. 13 inverts Eq. 14 away from the regulariser
+    assert np.allclose(0.5 * (1 + np.tanh(2 * psi[inner] / 4.0)), phi[inner], atol=1e-9)
+    # clipping (after Eq. 37): constant outside [0, 1]
+    assert np.all(psi[phi <= 0] == psi[phi <= 0][0]) and np.all(psi[phi >= 1] == psi[phi >= 1][0])
+
+
+def test_surface_tension_relation():
+    # Sect. 2: beta = 12 gamma / W, kappa = 3 gamma W / 2 -> gamma = sqrt(2 kappa beta) / 6
+    for sigma, Wd in ((0.01, 4.0), (0.027, 3.0), (0.005, 5.0)):
+        m = Model(W.CaseParams(nx=4, ny=4, sigma=sigma, W=Wd))
+        assert abs(np.sqrt(2 * m.kappa * m.beta) / 6 - sigma) < 1e-16
+
+
+# --------------------------------------------------------------------------- stencils (Eqs. 39, 40)
+def test_stencils_exact_on_quadratics():
+    n = 12
+    m = Model(W.CaseParams(nx=n, ny=n))
+    y, x = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float), indexing="ij")
+    a, b, c_, d, e = 0.3, -0.7, 1.1, 0.25, -2.0
+    chi = (a * x * x + b * x * y + c_ * y * y + d * x + e * y)[None]
+    gx, gy = m.grad(chi)
+    lap = m.lap(chi)
+    sl = (0, slice(1, n - 1), slice(1, n - 1))
+    assert np.allclose(gx[sl], (2 * a * x + b * y + d)[1:-1, 1:-1], atol=1e-12)
+    assert np.allclose(gy[sl], (b * x + 2 * c_ * y + e)[1:-1, 1:-1], atol=1e-12)
+    assert np.allclose(lap[sl], 2 * a + 2 * c_, atol=1e-12)
+
+
+def test_stencil_fourier_symbols():
+    n = 16
+    m = Model(W.CaseParams(nx=n, ny=n))
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for kx, ky in ((1, 0), (2, 3), (5, 7)):
+        Kx, Ky = 2 * np.pi * kx / n, 2 * np.pi * ky / n
+        chi = np.exp(1j * (Kx * x + Ky * y))[None]
+        gx, gy = m.grad(chi)
+        lap = m.lap(chi)
+        sx = 1j * np.sin(Kx) * (2 / 3 + np.cos(Ky) / 3)
+        sy = 1j * np.sin(Ky) * (2 / 3 + np.cos(Kx) / 3)
+        sl = 4 / 3 * (np.cos(Kx) + np.cos(Ky) - 2) + 2 / 3 * (np.cos(Kx) * np.cos(Ky) - 1)
+        assert np.allclose(gx, sx * chi, atol=1e-13)
+        assert np.allclose(gy, sy * chi, atol=1e-13)
+        assert np.allclose(lap, sl * chi, atol=1e-13)
+
+
+def test_stencil_wall_mirror():
+    # zero normal gradient at a half-way wall: a field even about y = -1/2 has d/dy = 0 there
+    n = 6
+    p = W.CaseParams(nx=n, ny=n, wall_y=True)
+    m = Model(p)
+    y = np.arange(n, dtype=float)
+    chi = np.broadcast_to(((y + 0.5) ** 2)[None, :, None], (1, n, n)).copy()
+    gy = m.grad(chi)[1]
+    # mirrored ghost at y = -1 equals y = 0: central difference (chi(1) - chi(0)) * (1/3 + 2/12)
+    assert np.allclose(gy[0, 0], (chi[0, 1, 0] - chi[0, 0, 0]) * 0.5)
+
+
+# --------------------------------------------------------------------------- brute force
+def _dense_from(p):
+    return Dense2D(p.nx, p.ny, W=p.W, sigma=p.sigma, mobility=p.mobility, nu=p.nu, lam=p.lam, xi=p.xi,
+                   eps_n=p.eps_n, rho_h=p.rho_heavy, rho_l=p.rho_light, wall_y=p.wall_y,
+                   ub=p.wall_u_bottom[:2], ut=p.wall_u_top[:2], mode=p.mode, U0=p.U0, T=p.T)
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (5, 3)])
+@pytest.mark.parametrize("variant", ["periodic", "walls", "vortex"])
+def test_oracle_equals_dense_bruteforce(shape, variant):
+    nx, ny = shape
+    kw = dict(nx=nx, ny=ny, W=2.0, sigma=0.02, mobility=0.07, nu=0.13, rho_heavy=1.0, rho_light=0.2)
+    if variant == "walls":
+        kw.update(wall_y=True, wall_u_bottom=(-0.03, 0.0, 0.0), wall_u_top=(0.05, 0.0, 0.0))
+    if variant == "vortex":
+        kw.update(mode="vortex", U0=0.04, T=7.0)
+    p = W.CaseParams(**kw)
+    rng = np.random.default_rng(nx * 10 + ny)
+    phi0 = rng.uniform(-0.05, 1.05, (1, ny, nx))
+    u0 = rng.normal(0, 0.02, (2, 1, ny, nx))
+    orc = Model(p).init(phi0, u0)
+    dn = _dense_from(p)
+    u0d = u0.reshape(2, -1).T.copy()
+    if variant == "vortex":
+        u0d = dn.vortex_u(0)
+    g, f, J = dn.init(phi0.reshape(-1), u0d)
+    for t in range(3):
+        orc.step(1)
+        g, f, J = dn.step(g, f, J, t)
+        go = orc.g.reshape(9, -1).T
+        fo = orc.f.reshape(9, -1).T
+        assert np.max(np.abs(go - g)) < 1e-14, t
+        assert np.max(np.abs(fo - f)) < 1e-14, t
+        assert np.max(np.abs(orc.Jprev.reshape(2, -1).T - J)) < 1e-14, t
+
+
+# --------------------------------------------------------------------------- invariants
+@pytest.mark.parametrize("variant", ["periodic", "walls", "vortex"])
+def test_total_phi_conserved(variant):
+    if variant == "periodic":
+        p, phi0, u0 = W.two_droplets()
+        p = p.replace(nx=64, ny=64)
+        phi0 = W.drops_phi(p, [(20, 32, 0, 12), (48, 32, 0, 4)])
+    elif variant == "walls":
+        p, phi0, u0 = W.shear_droplet(nx=64, ny=32, R=8.0)
+    else:
+        p, phi0, u0 = W.single_vortex(L=64, T=400)
+    m = Model(p).init(phi0, u0)
+    V0 = m.phi().sum()
+    m.step(300)
+    assert abs(m.phi().sum() - V0) / V0 < 2e-13
+
+
+def test_centred_drop_keeps_its_symmetries():
+    n = 40
+    p = W.CaseParams(nx=n, ny=n, rho_light=0.1, sigma=0.01)
+    c = (n - 1) / 2
+    phi0 = W.drops_phi(p, [(c, c, 0, 9.3)])
+    # break the 90-degree symmetry but keep both mirrors with an ellipse-ish perturbation
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    phi0 = phi0 * (1 + 0.02 * np.cos(2 * np.pi * (x - c) / n))[None]
+    m = Model(p).init(phi0)
+    m.step(200)
+    F = m.fields()
+    ph, u = F["phi"][0], F["u"][:, 0]
+    assert np.max(np.abs(ph - ph[:, ::-1])) < 1e-13
+    assert np.max(np.abs(ph - ph[::-1, :])) < 1e-13
+    assert np.max(np.abs(u[0] + u[0][:, ::-1])) < 1e-15
+    assert np.max(np.abs(u[1] - u[1][::-1, :] * -1)) < 1e-15
+    # the 90-degree rotation symmetry of an unperturbed drop
+    m2 = Model(p).init(W.drops_phi(p, [(c, c, 0, 9.3)]))
+    m2.step(200)
+    ph2 = m2.phi()[0]
+    assert np.max(np.abs(ph2 - ph2.T)) < 1e-13
+    assert np.max(np.abs(ph - ph2)) > 1e-6          # the perturbation mattered
+
+
+# --------------------------------------------------------------------------- special cases
+def _bgk_step(m):
+    """Velocity-space BGK collision of Eqs. 20 and 30 (all MRT rates equal) built from the
+    oracle's nodal fields, followed by the oracle's streaming."""
+    p, lat, cs2 = m.p, m.lat, m.cs2
+    F = m.fields()
+    phi, u, mu = F["phi"], F["u"], F["mu"]
+    J = phi * u
+    dJ = J - m.Jprev
+    m.Jprev = J
+    V = dJ / cs2 + p.lam / p.W * F["sech2"] * m.unit_normal(F["gpsi"])
+    c = m.cvec
+    w = lat.w[:, None, None, None]
+    G = w * np.tensordot(c, V, axes=(1, 0))
+    H = mu + p.lam * phi
+    geq = w * H + w * np.tensordot(c, phi * u, axes=(1, 0)) / cs2
+    geq[0] = phi + (lat.w[0] - 1) * H
+    tg, tf = m.tau_g, m.tau_f
+    gs = m.g - (m.g - geq) / tg + (1 - 0.5 / tg) * G
+    cu = np.tensordot(c, u, axes=(1, 0))
+    uu = (u * u).sum(0)
+    s = w * (cu / cs2 + cu ** 2 / (2 * cs2 ** 2) - uu / (2 * cs2))
+    feq = w * F["p"] / cs2 + F["rho"] * s
+    feq[0] = (lat.w[0] - 1) * F["p"] / cs2 + F["rho"] * s[0]
+    Fi = w * (np.tensordot(c, F["Fs"], axes=(1, 0)) + cu * np.tensordot(c, F["grho"], axes=(1, 0))) / cs2
+    fs = m.f - (m.f - feq) / tf + (1 - 0.5 / tf) * Fi
+    m.f = m.stream(fs, rho=F["rho"], moving=True)
+    m.g = m.stream(gs)
+    m.t += 1
+
+
+def test_srt_mrt_equals_bgk():
+    p, phi0, _ = W.two_droplets()
+    p = p.replace(nx=32, ny=32)
+    phi0 = W.drops_phi(p, [(10, 16, 0, 6), (24, 16, 0, 3)])
+    tg, tf = 0.5 + 3 * p.mobility, 0.5 + 3 * p.nu
+    p = p.replace(s_g=tuple([1 / tg] * 9), s_f=tuple([1 / tf] * 9))
+    a = Model(p).init(phi0)
+    b = Model(p).init(phi0)
+    for _ in range(20):
+        a.step(1)
+        _bgk_step(b)
+    assert np.max(np.abs(a.g - b.g)) < 1e-14
+    assert np.max(np.abs(a.f - b.f)) < 1e-14
+
+
+def test_default_g_rates_make_eq30_and_eq33_agree():
+    # with the default S^g, the scalar (1 - 1/2 tau_g) factor of Eq. 30 equals (I - S/2) of Eq. 33
+    m = _model_for(D2Q9)
+    V = RNG.normal(0, 1, (2, 3))
+    G = m.g_source(V)
+    lhs = m.Minv @ (m.I - 0.5 * m.Sg) @ m.M @ G
+    assert np.allclose(lhs, (1 - 0.5 / m.tau_g) * G, atol=1e-15)
+
+
+def _fourier1(a):
+    return np.fft.rfft(a)[1]
+
+
+def test_diffusion_limit_decay_and_translation():
+    # sigma = 0, huge W (penalty flux ~ lambda / W -> 0): d_t phi = lambda M lap phi
+    n, steps = 64, 500
+    p = W.CaseParams(nx=n, ny=4, W=1e9, sigma=0.0, mobility=0.1, rho_light=1.0)
+    x = np.arange(n)
+    phi0 = np.broadcast_to((0.5 + 0.01 * np.sin(2 * np.pi * x / n))[None, None, :], (1, 4, n)).copy()
+    k = 2 * np.pi / n
+    m = Model(p).init(phi0)
+    a0 = _fourier1(m.phi()[0, 0])
+    m.step(steps)
+    a1 = _fourier1(m.phi()[0, 0])
+    rate = -np.log(abs(a1) / abs(a0)) / steps
+    assert abs(rate / (p.lam * p.mobility * k * k) - 1) < 5e-3
+    # uniform flow: the mode translates at u (phi u in Eq. 31 and d_t(phi u) in Eq. 32)
+    u0 = np.zeros((2, 1, 4, n))
+    u0[0] = 0.05
+    m = Model(p).init(phi0, u0)
+    m.step(steps)
+    a2 = _fourier1(m.phi()[0, 0])
+    shift = np.angle(a0 / a2) % (2 * np.pi)
+    assert abs(shift / (k * 0.05 * steps) - 1) < 2e-3
+
+
+def test_shear_wave_decay_matches_viscosity():
+    n, steps = 64, 500
+    p = W.CaseParams(nx=4, ny=n, rho_light=1.0, nu=0.1)
+    y = np.arange(n)
+    u0 = np.zeros((2, 1, n, 4))
+    u0[0] = (0.01 * np.sin(2 * np.pi * y / n))[None, :, None]
+    m = Model(p).init(np.zeros((1, n, 4)), u0)
+    c0 = _fourier1(m.fields()["u"][0, 0, :, 0])
+    m.step(steps)
+    c1 = _fourier1(m.fields()["u"][0, 0, :, 0])
+    k = 2 * np.pi / n
+    assert abs(-np.log(abs(c1) / abs(c0)) / steps / (p.nu * k * k) - 1) < 5e-3
+
+
+@pytest.mark.parametrize("srt", [True, False])
+def test_couette_profile(srt):
+    ny, U = 16, 0.01
+    p = W.CaseParams(nx=3, ny=ny, wall_y=True, wall_u_bottom=(-U, 0, 0), wall_u_top=(U, 0, 0),
+                     nu=0.5, rho_light=1.0)
+    if srt:
+        tf = 0.5 + 3 * p.nu
+        p = p.replace(s_f=tuple([1 / tf] * 9))
+    m = Model(p).init(np.zeros((1, ny, 3)))
+    m.step(3000)
+    u = m.fields()["u"][0, 0, :, 1]
+    y = np.arange(ny)
+    exact = -U + 2 * U * (y + 0.5) / ny
+    err = np.max(np.abs(u - exact)) / U
+    assert err < (1e-9 if srt else 2e-2)
+
+
+def test_laplace_law_classical_limit():
+    # lambda = 0 is the classical C-H model: dp = sigma / R in 2D
+    n, R = 64, 16
+    p = W.CaseParams(nx=n, ny=n, sigma=0.01, mobility=0.1, rho_light=0.1, nu=0.3, lam=0.0)
+    m = Model(p).init(W.drops_phi(p, [((n - 1) / 2, (n - 1) / 2, 0, R)]))
+    m.step(3000)
+    pr = m.fields()["p"][0]
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    r = np.hypot(x - (n - 1) / 2, y - (n - 1) / 2)
+    dp = pr[r < R / 2].mean() - pr[r > R + 8].mean()
+    assert abs(dp / (p.sigma / R) - 1) < 0.02
+
+
+def test_penalty_flux_vanishes_on_tanh_of_distance():
+    # Sect. 2: for phi = tanh profile of the distance, grad phi = (1/W)(1 - tanh^2(2 psi/W)) n,
+    # so the lambda terms of Eq. 17 cancel; discretely the residual is O(dx^2 / W^2).
+    n = 128
+    rel = {}
+    for Wd in (4.0, 8.0):
+        p = W.CaseParams(nx=n, ny=n, W=Wd)
+        m = Model(p)
+        phi = W.drops_phi(p, [((n - 1) / 2, (n - 1) / 2, 0, 40.0)])
+        psi = m.psi_of(phi)
+        sech2 = 1 - np.tanh(2 * psi / p.W) ** 2
+        flux = m.grad(phi) - sech2 / p.W * m.unit_normal(m.grad(psi))
+        rel[Wd] = np.max(np.abs(flux)) / np.max(np.abs(m.grad(phi)))
+        # a wrong sign of the normal would double the flux instead
+        bad = m.grad(phi) + sech2 / p.W * m.unit_normal(m.grad(psi))
+        assert np.max(np.abs(bad)) / np.max(np.abs(m.grad(phi))) > 1.5
+    assert rel[4.0] < 0.1
+    assert 3.5 < rel[4.0] / rel[8.0] < 4.5          # second order in dx / W
+
+
+def test_penalty_sharpens_a_too_wide_interface():
+    # sigma = 0: only the lambda terms act; a slab with width 2W relaxes to the width-W profile
+    n = 64
+    p = W.CaseParams(nx=4, ny=n, W=4.0, sigma=0.0, mobility=0.1, rho_light=1.0)
+    wide = W.slab_phi(p.replace(W=8.0), 16.0, 48.0)
+    m = Model(p).init(wide)
+    m.step(4000)
+    target = W.slab_phi(p, 16.0, 48.0)
+    assert np.max(np.abs(m.phi() - target)) < 0.02
+    assert np.max(np.abs(wide - target)) > 0.1
+
+
+def test_flat_interface_stays_at_equilibrium():
+    n = 64
+    p = W.CaseParams(nx=4, ny=n, W=4.0, sigma=0.01, rho_light=0.1)
+    phi0 = W.slab_phi(p, 16.0, 48.0)
+    m = Model(p).init(phi0)
+    m.step(500)
+    ph = m.phi()[0, :, 0]
+    assert np.max(np.abs(ph - phi0[0, :, 0])) < 5e-3
+    # the phi = 1/2 crossings stay put (linear interpolation)
+    def crossing(a, lo, hi):
+        for j in range(lo, hi):
+            if (a[j] - 0.5) * (a[j + 1] - 0.5) <= 0:
+                return j + (0.5 - a[j]) / (a[j + 1] - a[j])
+    assert abs(crossing(ph, 10, 22) - 16.0) < 1e-2
+    assert abs(crossing(ph, 42, 54) - 48.0) < 1e-2
+
+
+@pytest.mark.slow
+def test_paper_claim_small_drop_keeps_volume_better():
+    # Sect. 4.1 (qualitative): the R = 8-type small drop shrinks under the classical model
+    # (lambda = 0) and keeps its phi >= 1/2 area better under the modified one.
+    n = 40
+    res = {}
+    for lam in (0.0, 0.5):
+        p = W.CaseParams(nx=n, ny=n, W=4.0, sigma=0.01, mobility=0.1, rho_light=1.0, lam=lam)
+        phi0 = W.drops_phi(p, [((n - 1) / 2, (n - 1) / 2, 0, 5.0)])
+        m = Model(p).init(phi0)
+        c0 = (m.phi() >= 0.5).sum()
+        m.step(3000)
+        res[lam] = abs((m.phi() >= 0.5).sum() - c0) / c0
+    assert res[0.5] < res[0.0]
+
+
+def test_observables_on_known_field():
+    p = W.CaseParams(nx=8, ny=6, label_centres=[(1.0, 2.0, 0.0), (6.0, 2.0, 0.0)])
+    phi = np.zeros((1, 6, 8))
+    phi[0, 2, 1] = 1.0       # label 0, at its centre
+    phi[0, 3, 7] = 0.5       # label 1, displacement (1, 1)
+    phi[0, 2, 0] = 0.25      # label 0, displacement (-1, 0)
+    o = observables_from_phi(p, phi)
+    assert np.allclose(o["sum_phi"], [1.25, 0.5])
+    assert list(o["count_half"]) == [1, 1]
+    assert np.allclose(o["sum_phi_d"][1], [0.5, 0.5, 0])
+    assert np.allclose(o["sum_phi_d"][0], [-0.25, 0, 0])
+    assert np.allclose(o["sum_phi_dd"][1], [0.5, 0.5, 0, 0.5, 0, 0])
+    # periodic minimum image: node x = 7 is at displacement -2 from x = 1 wrapped? no: label 1 is nearer
+    d = derived_observables(o)
+    assert np.allclose(d["volume"], [1.25, 0.5])
+    # an ellipse has D = (a - b) / (a + b)
+    q = W.CaseParams(nx=200, ny=200)
+    y, x = np.meshgrid(np.arange(200), np.arange(200), indexing="ij")
+    ell = (((x - 99.5) / 40.0) ** 2 + ((y - 99.5) / 20.0) ** 2 <= 1).astype(float)[None]
+    dd = derived_observables(observables_from_phi(q, ell))
+    assert abs(dd["D"][0] - (40 - 20) / 60) < 5e-3
