@@ -1,0 +1,196 @@
+/*
+ * vclb -- volume-conserving phase-field lattice Boltzmann on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the HIP library libvclb.so.  The library implements one time step of the
+ * lattice Boltzmann model of Xiong, Wang & Liu, "Local volume-conserving lattice
+ * Boltzmann model for incompressible multiphase flows" (arXiv 2505.10899):
+ *   - phase-field populations g_i for the modified Cahn-Hilliard equation (Sect. 2,
+ *     Eq. 17), with equilibrium Eq. 31, profile-correction/level-set source Eq. 32 and
+ *     moment-space collision Eq. 33, order parameter Eq. 35, signed distance Eq. 37,
+ *     backward time difference of phi u (Sect. 3.2);
+ *   - hydrodynamic populations f_i for the incompressible Navier-Stokes equations
+ *     (Eq. 18), with forcing Eq. 21, equilibrium Eqs. 22-23, collision Eq. 25,
+ *     velocity Eq. 28 and pressure Eq. 29;
+ *   - isotropic gradient and Laplacian stencils (Eqs. 39-40), chemical potential Eq. 2
+ *     and surface tension force F_s = mu grad phi (Sect. 2);
+ *   - per-step FP64 volume reductions of phi (observables only: the correction term
+ *     of Eq. 32 is local and needs no global quantity).
+ *
+ * Conventions (all entry points):
+ *   - Return 0 on success or a negative VCLB_E* code.  No exception crosses the ABI.
+ *     vclb_strerror() names a code; vclb_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - Parameters are validated before any HIP call: invalid parameters return
+ *     VCLB_EINVAL without touching the GPU.
+ *   - Units are lattice units (dx = dt = 1, c_s^2 = 1/3).
+ *   - Fields are row-major with x fastest: node (x, y, z) has index x + nx (y + ny z).
+ *     Vector fields are structure-of-arrays: component d of node n at [d * N + n].
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *     Work is enqueued asynchronously on it; functions that return data to the host
+ *     synchronise that stream before returning.
+ *   - ptr_kind says whether a caller pointer is host (VCLB_HOST) or device
+ *     (VCLB_DEVICE) memory.  The caller owns every buffer it passes; the library owns
+ *     the case handle and the device state (or borrows a caller workspace, see
+ *     vclb_case_create).
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef VCLB_H
+#define VCLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- error codes */
+#define VCLB_OK          0
+#define VCLB_EINVAL     -1   /* invalid argument or unsupported combination          */
+#define VCLB_ENOMEM     -2   /* device allocation failed or workspace too small      */
+#define VCLB_EHIP       -3   /* a HIP runtime call failed                             */
+#define VCLB_ENONFINITE -4   /* a NaN/Inf was found in phi by the volume reductions   */
+#define VCLB_ESTATE     -5   /* call out of order (e.g. step before init), bad checkpoint */
+
+/* ---------------------------------------------------------------- enums */
+#define VCLB_D2Q9   0
+#define VCLB_D3Q19  1
+
+#define VCLB_FP64   0   /* populations stored and updated in double                         */
+#define VCLB_FP32   1   /* populations stored and updated in float                          */
+#define VCLB_FP16S  2   /* populations stored in half as deviations from the rest
+                           equilibrium (g: phi-dependent, f: 0); arithmetic in float        */
+
+#define VCLB_COUPLED           0   /* g and f coupled through u (Eq. 28) and F_s           */
+#define VCLB_PRESCRIBED_VORTEX 1   /* phase field only, velocity from Eqs. 43-44           */
+
+#define VCLB_PERIODIC 0
+#define VCLB_WALL     1   /* half-way bounce-back, wall half a node outside the first/last node */
+
+#define VCLB_HOST   0
+#define VCLB_DEVICE 1
+
+/* field mask bits for vclb_observe, written in this order, N doubles per scalar
+   field and D * N for u */
+#define VCLB_FIELD_PHI 0x01u   /* order parameter, Eq. 35                         */
+#define VCLB_FIELD_RHO 0x02u   /* density rho_light + phi (rho_heavy - rho_light)  */
+#define VCLB_FIELD_U   0x04u   /* velocity, Eq. 28 (or Eqs. 43-44)                 */
+#define VCLB_FIELD_P   0x08u   /* pressure, Eq. 29 (0 in prescribed-velocity mode) */
+#define VCLB_FIELD_MU  0x10u   /* chemical potential, Eq. 2                        */
+#define VCLB_FIELD_PSI 0x20u   /* signed distance, Eq. 37                          */
+
+#define VCLB_MAX_LABELS 2       /* observation regions per case                     */
+#define VCLB_HISTORY    4096    /* per-step observations kept (ring)                */
+
+/* ---------------------------------------------------------------- parameters */
+typedef struct {
+  int32_t lattice;          /* VCLB_D2Q9 | VCLB_D3Q19                                     */
+  int32_t storage;          /* VCLB_FP64 | VCLB_FP32 | VCLB_FP16S                          */
+  int32_t mode;             /* VCLB_COUPLED | VCLB_PRESCRIBED_VORTEX (D2Q9 only)           */
+  int32_t nx, ny, nz;       /* nodes per axis; nz = 1 for D2Q9                             */
+  int32_t bc_y;             /* VCLB_PERIODIC | VCLB_WALL (x and z are always periodic)     */
+  int32_t nlabels;          /* 0: one label covering the domain; else 1..VCLB_MAX_LABELS   */
+  double  wall_u_bottom[3]; /* velocity of the wall below y = 0 (VCLB_WALL)                */
+  double  wall_u_top[3];    /* velocity of the wall above y = ny - 1                       */
+  double  W;                /* interface width (Eq. 4), > 0                                 */
+  double  sigma;            /* surface tension, >= 0 (beta = 12 sigma / W, kappa = 3 sigma W / 2) */
+  double  mobility;         /* M > 0; tau_g = 1/2 + M / c_s^2 (Eq. 34)                      */
+  double  lambda;           /* penalty constant (0.5 in the paper); 0 gives the classical model */
+  double  xi;               /* regulariser of Eq. 37 (1e-10 in the paper), > 0              */
+  double  eps_n;            /* unit normal n = grad psi / sqrt(|grad psi|^2 + eps_n^2), >= 0 */
+  double  rho_heavy;        /* density at phi = 1, > 0                                      */
+  double  rho_light;        /* density at phi = 0, > 0                                      */
+  double  nu;               /* kinematic viscosity > 0; tau_f = 1/2 + nu / c_s^2 (Eq. 27)   */
+  double  s_g[19];          /* MRT rates of g in (0, 2); 0 selects the default              */
+  double  s_f[19];          /* MRT rates of f in (0, 2); 0 selects the default              */
+  double  U0;               /* vortex amplitude (Eqs. 43-44)                                 */
+  double  T;                /* vortex period in steps, > 0 in vortex mode                    */
+  double  label_centre[VCLB_MAX_LABELS][3]; /* nearest-centre (minimum image) regions   */
+} vclb_params;
+
+/* Per-label volume reductions of phi at one time step, accumulated in FP64.
+   d is the displacement of a node from its label's centre (minimum image along
+   periodic axes); second moments are ordered xx, yy, zz, xy, xz, yz. */
+typedef struct {
+  double  sum_phi;
+  double  count_half;       /* number of nodes with phi >= 1/2 */
+  double  sum_phi_d[3];
+  double  sum_phi_dd[6];
+  int64_t step;             /* time step the observation belongs to */
+  int32_t nonfinite;        /* 1 if phi was NaN/Inf at some node of the label */
+  int32_t label;
+} vclb_obs;
+
+typedef struct vclb_case vclb_case;
+
+/* ---------------------------------------------------------------- meta */
+const char* vclb_strerror(int code);
+/* Message of the calling thread's last failed call (empty string if none). */
+const char* vclb_last_error(void);
+/* Library version as MAJOR * 10000 + MINOR * 100 + PATCH. */
+int vclb_version(void);
+
+/* Check parameters without any HIP call.  Fills the defaults of zero rates. */
+int vclb_params_validate(const vclb_params* p);
+
+/* ---------------------------------------------------------------- single case */
+/* Device bytes the case needs (populations A/B, previous phi u, FP16S phi buffers,
+   reduction partials, observation history, scratch for observe).  No HIP call. */
+int vclb_case_workspace_bytes(const vclb_params* p, size_t* bytes);
+
+/* Validate, then create a case.  `workspace` (device memory, at least
+   vclb_case_workspace_bytes, 256-byte aligned) is borrowed for the life of the case;
+   NULL makes the library allocate and own it.  Launch configuration (tile shape) is
+   chosen by the library's built-in heuristic; vclb_case_set_tile overrides it. */
+int vclb_case_create(const vclb_params* p, void* workspace, size_t workspace_bytes,
+                     vclb_case** out);
+void vclb_case_destroy(vclb_case* c);
+
+/* Tile of the fused step kernel: bx threads (lanes = x columns, a multiple of 64,
+   64..1024) marching over ty rows (y for D2Q9, z for D3Q19; >= 1), by3 rows of y per
+   block for D3Q19 (ignored for D2Q9).  Returns EINVAL for shapes outside the limits. */
+int vclb_case_set_tile(vclb_case* c, int32_t bx, int32_t ty, int32_t by3);
+int vclb_case_get_tile(const vclb_case* c, int32_t* bx, int32_t* ty, int32_t* by3);
+
+/* Initial state from phi0 (N doubles) and u0 (D*N doubles, NULL for u = 0; ignored in
+   vortex mode): g = g_eq(phi0, mu0, u0) (Eq. 31), f = f_eq(p = 0, rho(phi0), u0) (Eq. 22),
+   previous phi u = phi0 u0; step counter 0. */
+int vclb_case_init(vclb_case* c, const double* phi0, const double* u0, int ptr_kind,
+                   void* stream);
+
+/* Advance nsteps >= 0 time steps with the fused single-kernel step (pull streaming,
+   LDS-staged phi/psi halo tiles, fused reductions).  Asynchronous. */
+int vclb_step(vclb_case* c, int64_t nsteps, void* stream);
+
+/* Same update with the plain two-kernel path (phi/psi pass, then stencil + collision
+   from global memory); bitwise equal to vclb_step.  Asynchronous. */
+int vclb_step_plain(vclb_case* c, int64_t nsteps, void* stream);
+
+/* Record the per-step reductions every `every` steps (0 turns them off; default 1). */
+int vclb_case_set_reduce_every(vclb_case* c, int32_t every);
+
+/* Current step counter (synchronises the stream). */
+int vclb_case_time(vclb_case* c, int64_t* t, void* stream);
+
+/* Macroscopic fields of the current state, in FP64, in VCLB_FIELD_* bit order. */
+int vclb_observe(vclb_case* c, uint32_t field_mask, double* out, int ptr_kind, void* stream);
+
+/* Volume reductions of the current state into out[nlabels] (host memory).
+   Returns VCLB_ENONFINITE (after filling out) if any label saw a NaN/Inf. */
+int vclb_reduce(vclb_case* c, vclb_obs* out, void* stream);
+
+/* Copy the recorded per-step reductions of steps [t_first, t_first + count) into
+   out[count * nlabels] (host).  Steps older than VCLB_HISTORY or never recorded give
+   VCLB_ESTATE. */
+int vclb_history(vclb_case* c, int64_t t_first, int32_t count, vclb_obs* out, void* stream);
+
+/* Checkpoint: populations (storage precision), previous phi u, FP16S phi buffer and
+   the step counter, with a parameter fingerprint and a checksum. */
+int vclb_state_bytes(const vclb_case* c, size_t* bytes);
+int vclb_state_save(vclb_case* c, void* host_buf, size_t bytes, void* stream);
+int vclb_state_load(vclb_case* c, const void* host_buf, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VCLB_H */

@@ -1,0 +1,251 @@
+// Device-side description of one case and the helpers every kernel shares:
+// pull streaming with bounce-back walls and storage decoding, fixed-order block
+// reductions, and the end-of-step "last block" that finishes the volume reductions
+// and advances the step counter.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "node.hpp"
+
+namespace vclb {
+
+constexpr int kMaxLabels = 2;
+constexpr int kObsFields = 13;   // sum, count, d[3], dd[6], nonfinite, step
+constexpr int kHistory = 4096;
+
+template <class L, class St>
+struct DevCase {
+  using S = typename St::S;
+  using R = typename St::R;
+  int nx, ny, nz;
+  long n;                       // nx * ny * nz
+  int wall;                     // bounce-back walls bound y
+  int nl;                       // labels (1..kMaxLabels)
+  double cen[kMaxLabels][3];    // label centres
+  S* pop[2][2];                 // [g = 0, f = 1][buffer]; f is null in vortex mode
+  R* J;                         // previous phi u, D * n
+  float* phis[2];               // FP16S: phi of the node that wrote each buffer entry
+  unsigned long long* tick;     // [0] step counter, [1] block ticket
+  double* partials;             // [block][label][kObsFields]
+  double* hist;                 // [kHistory][label][kObsFields]
+  double* cur;                  // [label][kObsFields] reductions of the current state
+  R* tmp_phi;                   // scratch N: phi (plain path and observe)
+  R* tmp_psi;                   // scratch N: psi
+  NodeParams<L, R> np;
+};
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ double min_image(double d, int n, bool periodic) {
+  if (!periodic) return d;
+  const double dn = double(n);
+  return d - dn * floor((d + 0.5 * dn) / dn);
+}
+
+// Pull the Q populations of one set arriving at node (x, y, z):
+// pop_i(x) = post_i(x - c_i), or the node's own opposite post-collision value when
+// x - c_i lies behind a wall.  Decodes the FP16S deviation storage.
+template <class L, class St, class Case>
+__device__ __forceinline__ void pull(const Case& c, const typename St::S* __restrict__ src,
+                                     const float* __restrict__ phis, int x, int y, int z,
+                                     typename St::R (&out)[L::Q], bool shifted_set) {
+  using R = typename St::R;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    int xs = x - L::cx[i], ys = y - L::cy[i], zs = z - L::cz[i];
+    int pi = i;
+    if (L::cy[i] != 0 && (ys < 0 || ys >= c.ny)) {
+      if (c.wall) {
+        xs = x;
+        ys = y;
+        zs = z;
+        pi = L::opp[i];
+      } else {
+        ys = wrapi(ys, c.ny);
+      }
+    }
+    if (L::cx[i] != 0) xs = wrapi(xs, c.nx);
+    if (L::cz[i] != 0) zs = wrapi(zs, c.nz);
+    const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
+    R v = St::load(src, long(pi) * c.n + s);
+    if constexpr (St::shifted) {
+      if (shifted_set) v += phis[s] * c.np.rest[pi];
+    }
+    out[i] = v;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ R sum_pops(const R* g, int Q) {
+  R s = R(0);
+  for (int i = 0; i < Q; ++i) s += g[i];
+  return s;
+}
+
+// ---------------------------------------------------------------- reductions
+// Per-thread accumulators of the volume reductions (FP64), for up to kMaxLabels labels.
+struct Acc {
+  double v[kMaxLabels][12];
+  __device__ void zero() {
+#pragma unroll
+    for (int k = 0; k < kMaxLabels; ++k)
+#pragma unroll
+      for (int f = 0; f < 12; ++f) v[k][f] = 0.0;
+  }
+};
+
+template <class Case>
+__device__ __forceinline__ void accumulate(const Case& c, Acc& a, double phi, int x, int y, int z) {
+  double d[kMaxLabels][3];
+  const bool py = !c.wall;
+#pragma unroll
+  for (int k = 0; k < kMaxLabels; ++k) {
+    d[k][0] = min_image(double(x) - c.cen[k][0], c.nx, true);
+    d[k][1] = min_image(double(y) - c.cen[k][1], c.ny, py);
+    d[k][2] = min_image(double(z) - c.cen[k][2], c.nz, true);
+  }
+  int lab = 0;
+  if (c.nl > 1) {
+    const double r0 = d[0][0] * d[0][0] + d[0][1] * d[0][1] + d[0][2] * d[0][2];
+    const double r1 = d[1][0] * d[1][0] + d[1][1] * d[1][1] + d[1][2] * d[1][2];
+    lab = (r1 < r0) ? 1 : 0;
+  }
+  const bool fin = isfinite(phi);
+  // branch-free on the label so that the accumulators keep static register indices
+#pragma unroll
+  for (int k = 0; k < kMaxLabels; ++k) {
+    const double w = (k == lab) ? phi : 0.0;
+    const double dx = d[k][0], dy = d[k][1], dz = d[k][2];
+    a.v[k][0] += w;
+    a.v[k][1] += (k == lab && phi >= 0.5) ? 1.0 : 0.0;
+    a.v[k][2] += w * dx;
+    a.v[k][3] += w * dy;
+    a.v[k][4] += w * dz;
+    a.v[k][5] += w * dx * dx;
+    a.v[k][6] += w * dy * dy;
+    a.v[k][7] += w * dz * dz;
+    a.v[k][8] += w * dx * dy;
+    a.v[k][9] += w * dx * dz;
+    a.v[k][10] += w * dy * dz;
+    a.v[k][11] += (k == lab && !fin) ? 1.0 : 0.0;
+  }
+}
+
+// Sum one value over the block in a fixed order; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += red[w];
+  }
+  return s;
+}
+
+// End of a step kernel: optional block partials of the reductions, then the block
+// ticket; the last block to arrive sums the partials in block order into `dest`
+// (deterministic) and, if `advance`, increments the step counter.
+template <class Case>
+__device__ __forceinline__ void finish_block(const Case& c, Acc& a, bool reduce, double* dest, bool advance,
+                             long step) {
+  __shared__ double red[16];
+  __shared__ unsigned long long ticket;
+  const int nf = c.nl * 12;
+  if (reduce) {
+#pragma unroll
+    for (int k = 0; k < kMaxLabels; ++k) {
+      if (k < c.nl) {
+#pragma unroll
+        for (int f = 0; f < 12; ++f) {
+          const double s = block_sum(a.v[k][f], red);
+          if (threadIdx.x == 0) c.partials[long(blockIdx.x) * nf + k * 12 + f] = s;
+        }
+      }
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) ticket = atomicAdd(&c.tick[1], 1ULL);
+  __syncthreads();
+  if (ticket != gridDim.x - 1) return;
+  __threadfence();
+  if (reduce) {
+    for (int fi = 0; fi < nf; ++fi) {
+      double s = 0.0;
+      for (int b = threadIdx.x; b < int(gridDim.x); b += blockDim.x)
+        s += __builtin_nontemporal_load(&c.partials[long(b) * nf + fi]);
+      s = block_sum(s, red);
+      if (threadIdx.x == 0) {
+        const int k = fi / 12, f = fi % 12;
+        dest[k * kObsFields + f] = s;
+        if (f == 0) dest[k * kObsFields + 12] = double(step);
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    atomicExch(&c.tick[1], 0ULL);
+    if (advance) atomicAdd(&c.tick[0], 1ULL);
+  }
+}
+
+// store one node's post-collision state (with the moving-wall term on f for the
+// directions that leave through a wall, read back by the bounce-back pull)
+template <class L, class St, bool COUPLED>
+__device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, long n, int y,
+                                           typename St::R phi, typename St::R rho,
+                                           const typename St::R (&g)[L::Q], typename St::R (&f)[L::Q],
+                                           const typename St::R (&J)[L::D]) {
+  using R = typename St::R;
+  const int dst = par ^ 1;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    R v = g[i];
+    if constexpr (St::shifted) v -= phi * c.np.rest[i];
+    St::store(c.pop[0][dst], long(i) * c.n + n, v);
+  }
+  if constexpr (COUPLED) {
+    if (c.wall) {
+      if (y == 0) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+          if (L::cy[i] < 0) f[i] += c.np.wb[i] * rho;
+      }
+      if (y == c.ny - 1) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+          if (L::cy[i] > 0) f[i] += c.np.wt[i] * rho;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) St::store(c.pop[1][dst], long(i) * c.n + n, f[i]);
+  }
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) c.J[d * c.n + n] = J[d];
+  if constexpr (St::shifted) c.phis[dst][n] = float(phi);
+}
+
+template <class L, class St, bool COUPLED>
+__device__ __forceinline__ void prescribed(const DevCase<L, St>& c, int x, int y, long t,
+                                           NodeIn<L, typename St::R>& in) {
+  if constexpr (!COUPLED) {
+    typename St::R ux, uy;
+    vortex_u<typename St::R>(c.np.U0, c.np.T, x, y, c.nx, c.ny, t, ux, uy);
+    in.u[0] = ux;
+    in.u[1] = uy;
+  }
+}
+
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs, so
+// block b runs on XCD b % 8.  Give each XCD a contiguous range of tiles so that
+// neighbouring tiles (which re-read each other's halo rows) share one L2.
+__device__ __forceinline__ int xcd_tile(int b, int B) {
+  const int q = B >> 3, r = B & 7, x = b & 7, i = b >> 3;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+}  // namespace vclb

@@ -1,0 +1,351 @@
+// Step, init, observe and reduction kernels of the phase-field lattice Boltzmann model
+// for gfx950, and their host-side launchers.
+//
+// Layout in HBM (per case, structure of arrays): population set s (g or f), buffer b
+// (A/B, swapped every step) and direction i at node n: pop[s][b][i * N + n], with
+// n = x + nx (y + ny z), x fastest.  Buffers hold post-collision values; a step pulls
+// pop_i(x) = post_i(x - c_i) from the buffer the previous step wrote.
+#include <hip/hip_runtime.h>
+
+#include "devcase.hpp"
+#include "launch.hpp"
+
+namespace vclb {
+
+// ---------------------------------------------------------------- init (A13)
+// g = g_eq(phi0, mu0, u0), f = f_eq(p = 0, rho(phi0), u0), previous phi u = phi0 u0.
+// Values are written where the first pull will look for them (inverse streaming).
+template <class L, class St, bool COUPLED>
+__global__ void __launch_bounds__(256) k_init(DevCase<L, St> c, const double* __restrict__ phi0,
+                                              const double* __restrict__ u0) {
+  using R = typename St::R;
+  constexpr int Q = L::Q, D = L::D;
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  if (n >= c.n) return;
+  const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
+  // Laplacian of phi0 (Eq. 40), mirror ghosts at walls
+  R nb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int xn = wrapi(x + L::cx[i], c.nx), yn = y + L::cy[i], zn = wrapi(z + L::cz[i], c.nz);
+    yn = c.wall ? (yn < 0 ? 0 : (yn >= c.ny ? c.ny - 1 : yn)) : wrapi(yn, c.ny);
+    nb[i] = R(phi0[xn + long(c.nx) * (yn + long(c.ny) * zn)]);
+  }
+  const R phi = nb[0];
+  const R lphi = stencil_lap<L, R>(nb);
+  const R mu = c.np.beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - c.np.kappa * lphi;
+  R u[D];
+  if constexpr (COUPLED) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) u[d] = u0 ? R(u0[d * c.n + n]) : R(0);
+  } else {
+    R ux, uy;
+    vortex_u<R>(c.np.U0, c.np.T, x, y, c.nx, c.ny, 0, ux, uy);
+    u[0] = ux;
+    u[1] = uy;
+  }
+  const R H = mu + c.np.lam * phi;
+  const R rho = c.np.rho_l + phi * c.np.drho;
+  R uu = R(0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) uu += u[d] * u[d];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cc[3] = {L::cx[i], L::cy[i], L::cz[i]};
+    R cJ = R(0), cu = R(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (cc[d] == 1) { cJ += phi * u[d]; cu += u[d]; }
+      else if (cc[d] == -1) { cJ -= phi * u[d]; cu -= u[d]; }
+    }
+    const R wi = R(L::w[i]);
+    const R geq = (i == 0) ? phi + R(L::w[0] - 1.0) * H : wi * H + wi * (R(3) * cJ);
+    const R si = wi * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+    const R feq = rho * si;   // p = 0
+    // where the first pull of direction i at this node reads
+    int xs = x - L::cx[i], ys = y - L::cy[i], zs = z - L::cz[i], pi = i;
+    if (L::cy[i] != 0 && (ys < 0 || ys >= c.ny)) {
+      if (c.wall) { xs = x; ys = y; zs = z; pi = L::opp[i]; }
+      else ys = wrapi(ys, c.ny);
+    }
+    xs = wrapi(xs, c.nx);
+    zs = wrapi(zs, c.nz);
+    const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
+    R gv = geq;
+    if constexpr (St::shifted) gv -= R(float(phi0[s])) * c.np.rest[pi];
+    St::store(c.pop[0][0], long(pi) * c.n + s, gv);
+    if constexpr (COUPLED) St::store(c.pop[1][0], long(pi) * c.n + s, feq);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) c.J[d * c.n + n] = phi * u[d];
+  if constexpr (St::shifted) c.phis[0][n] = float(phi0[n]);
+  if (n == 0) {
+    c.tick[0] = 0;
+    c.tick[1] = 0;
+  }
+}
+
+// ---------------------------------------------------------------- plain path, pass 1
+// phi = sum g (Eq. 35) and psi (Eq. 37) of every node into scratch arrays.
+template <class L, class St>
+__global__ void __launch_bounds__(256) k_phi_psi(DevCase<L, St> c) {
+  using R = typename St::R;
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  if (n >= c.n) return;
+  const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
+  const int par = int(c.tick[0] & 1ULL);
+  R g[L::Q];
+  pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, true);
+  R phi = R(0);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) phi += g[i];
+  c.tmp_phi[n] = phi;
+  c.tmp_psi[n] = psi_of<R>(phi, c.np.W4, c.np.xi);
+}
+
+// gather a scratch field at x + c_i with periodic wrap / wall mirror
+template <class L, class St>
+__device__ __forceinline__ void gather(const DevCase<L, St>& c, const typename St::R* __restrict__ a, int x,
+                                       int y, int z, typename St::R (&nb)[L::Q]) {
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    int xn = wrapi(x + L::cx[i], c.nx), yn = y + L::cy[i], zn = wrapi(z + L::cz[i], c.nz);
+    yn = c.wall ? (yn < 0 ? 0 : (yn >= c.ny ? c.ny - 1 : yn)) : wrapi(yn, c.ny);
+    nb[i] = a[xn + long(c.nx) * (yn + long(c.ny) * zn)];
+  }
+}
+
+// ---------------------------------------------------------------- plain path, pass 2
+template <class L, class St, bool COUPLED>
+__global__ void __launch_bounds__(256) k_collide_plain(DevCase<L, St> c, int reduce) {
+  using R = typename St::R;
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  const long t = long(c.tick[0]);
+  const int par = int(t & 1);
+  Acc acc;
+  acc.zero();
+  if (n < c.n) {
+    const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
+    NodeIn<L, R> in;
+    gather<L, St>(c, c.tmp_phi, x, y, z, in.nphi);
+    gather<L, St>(c, c.tmp_psi, x, y, z, in.npsi);
+    prescribed<L, St, COUPLED>(c, x, y, t, in);
+    R g[L::Q], f[L::Q], J[L::D];
+    pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, true);
+    if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, false);
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
+    NodeOut<L, R> out;
+    node_update<L, R, COUPLED>(c.np, in, g, f, J, out);
+    store_node<L, St, COUPLED>(c, par, n, y, in.nphi[0], out.rho, g, f, J);
+    if (reduce) accumulate(c, acc, double(in.nphi[0]), x, y, z);
+  }
+  finish_block(c, acc, reduce != 0, c.hist + (t % kHistory) * c.nl * kObsFields, true, t);
+}
+
+// ---------------------------------------------------------------- observe
+template <class L, class St, bool COUPLED>
+__global__ void __launch_bounds__(256) k_fields(DevCase<L, St> c, unsigned mask, double* __restrict__ out) {
+  using R = typename St::R;
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  if (n >= c.n) return;
+  const long t = long(c.tick[0]);
+  const int par = int(t & 1);
+  const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
+  NodeIn<L, R> in;
+  gather<L, St>(c, c.tmp_phi, x, y, z, in.nphi);
+  gather<L, St>(c, c.tmp_psi, x, y, z, in.npsi);
+  prescribed<L, St, COUPLED>(c, x, y, t, in);
+  R g[L::Q], f[L::Q], J[L::D];
+  pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, true);
+  if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, false);
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
+  NodeOut<L, R> o;
+  node_update<L, R, COUPLED>(c.np, in, g, f, J, o);
+  long off = 0;
+  if (mask & 0x01u) { out[off + n] = double(in.nphi[0]); off += c.n; }
+  if (mask & 0x02u) { out[off + n] = double(o.rho); off += c.n; }
+  if (mask & 0x04u) {
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) out[off + d * c.n + n] = double(o.u[d]);
+    off += L::D * c.n;
+  }
+  if (mask & 0x08u) { out[off + n] = double(o.press); off += c.n; }
+  if (mask & 0x10u) { out[off + n] = double(o.mu); off += c.n; }
+  if (mask & 0x20u) { out[off + n] = double(in.npsi[0]); off += c.n; }
+}
+
+// reductions of the current state (phi from scratch), into c.cur
+template <class L, class St>
+__global__ void __launch_bounds__(256) k_reduce_state(DevCase<L, St> c) {
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  Acc acc;
+  acc.zero();
+  if (n < c.n) {
+    const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
+    accumulate(c, acc, double(c.tmp_phi[n]), x, y, z);
+  }
+  finish_block(c, acc, true, c.cur, false, long(c.tick[0]));
+}
+
+// ---------------------------------------------------------------- fused 2D step (A1-A11)
+// One workgroup owns bx consecutive x columns (one per lane) and marches up ty rows.
+// For each row it pulls the next row's g, forms phi and psi into a 4-row LDS ring
+// (plus one halo column on each side, computed by lanes 0 and 1), then applies the
+// stencils from LDS and updates the current row: every population is read from HBM
+// once, except the two halo columns and the two halo rows of the tile.
+template <class St, bool COUPLED>
+__global__ void __launch_bounds__(256) k_step2d(DevCase<D2Q9, St> c, int TY, int nseg, int reduce) {
+  using L = D2Q9;
+  using R = typename St::R;
+  constexpr int Q = L::Q;
+  extern __shared__ unsigned char smem_raw[];
+  const int BX = blockDim.x;
+  const int W = BX + 2;
+  R* sphi = reinterpret_cast<R*>(smem_raw);
+  R* spsi = sphi + 4 * W;
+  const int lane = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int strip = tile / nseg, seg = tile - strip * nseg;
+  const int x0 = strip * BX;
+  const int xg = x0 + lane;
+  const bool active_x = xg < c.nx;
+  const int xw = xg % c.nx;
+  const int y0 = seg * TY;
+  const int y1 = min(y0 + TY, c.ny);
+  const long t = long(c.tick[0]);
+  const int par = int(t & 1);
+  const typename St::S* gsrc = c.pop[0][par];
+  const typename St::S* fsrc = c.pop[1][par];
+  const float* phis = c.phis[par];
+  const bool halo_lane = lane < 2;
+  const int xh = (lane == 0) ? wrapi(x0 - 1, c.nx) : (x0 + BX) % c.nx;
+  const int hidx = (lane == 0) ? 0 : W - 1;
+  auto row_of = [&](int r) -> int {
+    if (r < 0) return c.wall ? 0 : r + c.ny;
+    if (r >= c.ny) return c.wall ? c.ny - 1 : r - c.ny;
+    return r;
+  };
+  auto slot = [](int r) -> int { return (r + 4) & 3; };
+  auto phi_row = [&](int r, R (&g)[Q]) {
+    const int yr = row_of(r);
+    pull<L, St>(c, gsrc, phis, xw, yr, 0, g, true);
+    R ph = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) ph += g[i];
+    sphi[slot(r) * W + lane + 1] = ph;
+    spsi[slot(r) * W + lane + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
+    if (halo_lane) {
+      R gh[Q];
+      pull<L, St>(c, gsrc, phis, xh, yr, 0, gh, true);
+      R hp = R(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) hp += gh[i];
+      sphi[slot(r) * W + hidx] = hp;
+      spsi[slot(r) * W + hidx] = psi_of<R>(hp, c.np.W4, c.np.xi);
+    }
+  };
+  Acc acc;
+  acc.zero();
+  R gcur[Q], gnext[Q];
+  phi_row(y0 - 1, gnext);
+  phi_row(y0, gcur);
+  for (int y = y0; y < y1; ++y) {
+    phi_row(y + 1, gnext);
+    __syncthreads();
+    if (active_x) {
+      NodeIn<L, R> in;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int si = slot(y + L::cy[i]);
+        in.nphi[i] = sphi[si * W + lane + 1 + L::cx[i]];
+        in.npsi[i] = spsi[si * W + lane + 1 + L::cx[i]];
+      }
+      prescribed<L, St, COUPLED>(c, xw, y, t, in);
+      const long n = xw + long(c.nx) * y;
+      R f[Q], J[L::D];
+      if constexpr (COUPLED) pull<L, St>(c, fsrc, phis, xw, y, 0, f, false);
+#pragma unroll
+      for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
+      NodeOut<L, R> out;
+      node_update<L, R, COUPLED>(c.np, in, gcur, f, J, out);
+      store_node<L, St, COUPLED>(c, par, n, y, in.nphi[0], out.rho, gcur, f, J);
+      if (reduce) accumulate(c, acc, double(in.nphi[0]), xw, y, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
+  }
+  finish_block(c, acc, reduce != 0, c.hist + (t % kHistory) * c.nl * kObsFields, true, t);
+}
+
+// ---------------------------------------------------------------- launchers
+template <class L, class St, bool COUPLED>
+int launch_init(const DevCase<L, St>& c, const double* phi0, const double* u0, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_init<L, St, COUPLED>), dim3(nb), dim3(256), 0, s, c, phi0, u0);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class L, class St, bool COUPLED>
+int launch_step_plain(const DevCase<L, St>& c, int reduce, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
+  hipLaunchKernelGGL((k_collide_plain<L, St, COUPLED>), dim3(nb), dim3(256), 0, s, c, reduce);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class L, class St, bool COUPLED>
+int launch_step_fused(const DevCase<L, St>& c, const Tile& tile, int reduce, hipStream_t s) {
+  if constexpr (L::D == 2) {
+    const int nstrips = (c.nx + tile.bx - 1) / tile.bx;
+    const int nseg = (c.ny + tile.ty - 1) / tile.ty;
+    const size_t lds = size_t(2) * 4 * (tile.bx + 2) * sizeof(typename St::R);
+    hipLaunchKernelGGL((k_step2d<St, COUPLED>), dim3(nstrips * nseg), dim3(tile.bx), lds, s, c, tile.ty,
+                       nseg, reduce);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  } else {
+    return launch_step3d<St>(c, tile, reduce, s);
+  }
+}
+
+template <class L, class St, bool COUPLED>
+int launch_observe(const DevCase<L, St>& c, unsigned mask, double* out, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
+  hipLaunchKernelGGL((k_fields<L, St, COUPLED>), dim3(nb), dim3(256), 0, s, c, mask, out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class L, class St>
+int launch_reduce_state(const DevCase<L, St>& c, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
+  hipLaunchKernelGGL((k_reduce_state<L, St>), dim3(nb), dim3(256), 0, s, c);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+#define VCLB_INSTANTIATE(L, St, C)                                                              \
+  template int launch_init<L, St, C>(const DevCase<L, St>&, const double*, const double*,      \
+                                     hipStream_t);                                             \
+  template int launch_step_plain<L, St, C>(const DevCase<L, St>&, int, hipStream_t);           \
+  template int launch_step_fused<L, St, C>(const DevCase<L, St>&, const Tile&, int, hipStream_t); \
+  template int launch_observe<L, St, C>(const DevCase<L, St>&, unsigned, double*, hipStream_t);
+
+VCLB_INSTANTIATE(D2Q9, StoreF64, true)
+VCLB_INSTANTIATE(D2Q9, StoreF64, false)
+VCLB_INSTANTIATE(D2Q9, StoreF32, true)
+VCLB_INSTANTIATE(D2Q9, StoreF32, false)
+VCLB_INSTANTIATE(D2Q9, StoreF16S, true)
+VCLB_INSTANTIATE(D2Q9, StoreF16S, false)
+VCLB_INSTANTIATE(D3Q19, StoreF64, true)
+VCLB_INSTANTIATE(D3Q19, StoreF32, true)
+VCLB_INSTANTIATE(D3Q19, StoreF16S, true)
+template int launch_reduce_state<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
+template int launch_reduce_state<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
+template int launch_reduce_state<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);
+template int launch_reduce_state<D3Q19, StoreF64>(const DevCase<D3Q19, StoreF64>&, hipStream_t);
+template int launch_reduce_state<D3Q19, StoreF32>(const DevCase<D3Q19, StoreF32>&, hipStream_t);
+template int launch_reduce_state<D3Q19, StoreF16S>(const DevCase<D3Q19, StoreF16S>&, hipStream_t);
+
+}  // namespace vclb

@@ -1,0 +1,117 @@
+// Fused D3Q19 step for gfx950 (3D workloads, periodic on every axis).
+//
+// A workgroup of bx * by threads owns a bx x by column tile of the (x, y) plane and
+// marches over tz planes of z.  For each plane it pulls the next plane's g, forms
+// phi and psi into a 4-plane LDS ring padded by one halo node on every side (the
+// ring of halo nodes is shared out over the threads), then applies the 18-neighbour
+// stencils from LDS and updates the current plane.
+#include <hip/hip_runtime.h>
+
+#include "devcase.hpp"
+#include "launch.hpp"
+
+namespace vclb {
+
+template <class St>
+__global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, int BY, int TZ, int nby,
+                                                 int nbz, int reduce) {
+  using L = D3Q19;
+  using R = typename St::R;
+  constexpr int Q = L::Q;
+  extern __shared__ unsigned char smem_raw[];
+  const int PW = BX + 2, PH = BY + 2, PS = PW * PH;
+  R* sphi = reinterpret_cast<R*>(smem_raw);
+  R* spsi = sphi + 4 * PS;
+  const int nthr = BX * BY;
+  const int tid = threadIdx.x;
+  const int tx = tid % BX, ty = tid / BX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int bz = tile % nbz;
+  const int rest = tile / nbz;
+  const int byi = rest % nby, bxi = rest / nby;
+  const int x0 = bxi * BX, y0 = byi * BY, z0 = bz * TZ;
+  const int z1 = min(z0 + TZ, c.nz);
+  const int xg = x0 + tx, yg = y0 + ty;
+  const bool active = xg < c.nx && yg < c.ny;
+  const int xw = xg % c.nx, yw = yg % c.ny;
+  const long t = long(c.tick[0]);
+  const int par = int(t & 1);
+  const typename St::S* gsrc = c.pop[0][par];
+  const typename St::S* fsrc = c.pop[1][par];
+  const float* phis = c.phis[par];
+  const int ring = 2 * PW + 2 * BY;
+  auto slot = [](int r) -> int { return (r + 4) & 3; };
+  auto plane = [&](int z, R (&g)[Q]) {
+    const int zr = wrapi(z, c.nz);
+    const int s = slot(z) * PS;
+    pull<L, St>(c, gsrc, phis, xw, yw, zr, g, true);
+    R ph = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) ph += g[i];
+    sphi[s + (ty + 1) * PW + tx + 1] = ph;
+    spsi[s + (ty + 1) * PW + tx + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
+    for (int k = tid; k < ring; k += nthr) {
+      int px, py;
+      if (k < PW) { px = k; py = 0; }
+      else if (k < 2 * PW) { px = k - PW; py = PH - 1; }
+      else if (k < 2 * PW + BY) { px = 0; py = 1 + k - 2 * PW; }
+      else { px = PW - 1; py = 1 + k - 2 * PW - BY; }
+      const int hx = ((x0 - 1 + px) % c.nx + c.nx) % c.nx;
+      const int hy = ((y0 - 1 + py) % c.ny + c.ny) % c.ny;
+      R gh[Q];
+      pull<L, St>(c, gsrc, phis, hx, hy, zr, gh, true);
+      R hp = R(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) hp += gh[i];
+      sphi[s + py * PW + px] = hp;
+      spsi[s + py * PW + px] = psi_of<R>(hp, c.np.W4, c.np.xi);
+    }
+  };
+  Acc acc;
+  acc.zero();
+  R gcur[Q], gnext[Q];
+  plane(z0 - 1, gnext);
+  plane(z0, gcur);
+  for (int z = z0; z < z1; ++z) {
+    plane(z + 1, gnext);
+    __syncthreads();
+    if (active) {
+      NodeIn<L, R> in;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int s = slot(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
+        in.nphi[i] = sphi[s];
+        in.npsi[i] = spsi[s];
+      }
+      const long n = xw + long(c.nx) * (yw + long(c.ny) * z);
+      R f[Q], J[L::D];
+      pull<L, St>(c, fsrc, phis, xw, yw, z, f, false);
+#pragma unroll
+      for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
+      NodeOut<L, R> out;
+      node_update<L, R, true>(c.np, in, gcur, f, J, out);
+      store_node<L, St, true>(c, par, n, yw, in.nphi[0], out.rho, gcur, f, J);
+      if (reduce) accumulate(c, acc, double(in.nphi[0]), xw, yw, z);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
+  }
+  finish_block(c, acc, reduce != 0, c.hist + (t % kHistory) * c.nl * kObsFields, true, t);
+}
+
+template <class St>
+int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hipStream_t s) {
+  const int nbx = (c.nx + tile.bx - 1) / tile.bx;
+  const int nby = (c.ny + tile.by3 - 1) / tile.by3;
+  const int nbz = (c.nz + tile.ty - 1) / tile.ty;
+  const size_t lds = size_t(2) * 4 * (tile.bx + 2) * (tile.by3 + 2) * sizeof(typename St::R);
+  hipLaunchKernelGGL((k_step3d<St>), dim3(nbx * nby * nbz), dim3(tile.bx * tile.by3), lds, s, c, tile.bx,
+                     tile.by3, tile.ty, nby, nbz, reduce);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template int launch_step3d<StoreF64>(const DevCase<D3Q19, StoreF64>&, const Tile&, int, hipStream_t);
+template int launch_step3d<StoreF32>(const DevCase<D3Q19, StoreF32>&, const Tile&, int, hipStream_t);
+template int launch_step3d<StoreF16S>(const DevCase<D3Q19, StoreF16S>&, const Tile&, int, hipStream_t);
+
+}  // namespace vclb

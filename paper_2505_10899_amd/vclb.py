@@ -1,0 +1,289 @@
+"""Python binding of libvclb.so: argument marshalling only.
+
+Every step of the model runs in the HIP library; this module converts case
+parameters to the C struct of include/vclb.h, gives the library a device workspace
+allocated by torch, and passes torch's current HIP stream.  It raises if the library
+is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+import torch  # noqa: F401  (loads the HIP runtime the library links against, first)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvclb.so")
+
+VCLB_OK, VCLB_EINVAL, VCLB_ENOMEM, VCLB_EHIP, VCLB_ENONFINITE, VCLB_ESTATE = 0, -1, -2, -3, -4, -5
+D2Q9, D3Q19 = 0, 1
+FP64, FP32, FP16S = 0, 1, 2
+COUPLED, PRESCRIBED_VORTEX = 0, 1
+PERIODIC, WALL = 0, 1
+HOST, DEVICE = 0, 1
+FIELD_PHI, FIELD_RHO, FIELD_U, FIELD_P, FIELD_MU, FIELD_PSI = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
+MAX_LABELS = 2
+HISTORY = 4096
+
+
+class VclbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vclb error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc_y", ctypes.c_int32), ("nlabels", ctypes.c_int32),
+        ("wall_u_bottom", ctypes.c_double * 3), ("wall_u_top", ctypes.c_double * 3),
+        ("W", ctypes.c_double), ("sigma", ctypes.c_double), ("mobility", ctypes.c_double),
+        ("lam", ctypes.c_double), ("xi", ctypes.c_double), ("eps_n", ctypes.c_double),
+        ("rho_heavy", ctypes.c_double), ("rho_light", ctypes.c_double), ("nu", ctypes.c_double),
+        ("s_g", ctypes.c_double * 19), ("s_f", ctypes.c_double * 19),
+        ("U0", ctypes.c_double), ("T", ctypes.c_double),
+        ("label_centre", (ctypes.c_double * 3) * MAX_LABELS),
+    ]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [
+        ("sum_phi", ctypes.c_double), ("count_half", ctypes.c_double),
+        ("sum_phi_d", ctypes.c_double * 3), ("sum_phi_dd", ctypes.c_double * 6),
+        ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int32), ("label", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every entry point of include/vclb.h
+_P = ctypes.POINTER
+_SIGS = [
+    ("vclb_strerror", ctypes.c_char_p, [ctypes.c_int]),
+    ("vclb_last_error", ctypes.c_char_p, []),
+    ("vclb_version", ctypes.c_int, []),
+    ("vclb_params_validate", ctypes.c_int, [_P(Params)]),
+    ("vclb_case_workspace_bytes", ctypes.c_int, [_P(Params), _P(ctypes.c_size_t)]),
+    ("vclb_case_create", ctypes.c_int, [_P(Params), ctypes.c_void_p, ctypes.c_size_t, _P(ctypes.c_void_p)]),
+    ("vclb_case_destroy", None, [ctypes.c_void_p]),
+    ("vclb_case_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    ("vclb_case_get_tile", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    ("vclb_case_init", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    ("vclb_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    ("vclb_step_plain", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    ("vclb_case_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("vclb_case_time", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64), ctypes.c_void_p]),
+    ("vclb_observe", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    ("vclb_reduce", ctypes.c_int, [ctypes.c_void_p, _P(Obs), ctypes.c_void_p]),
+    ("vclb_history", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
+    ("vclb_state_bytes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_size_t)]),
+    ("vclb_state_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("vclb_state_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+]
+
+
+def lib():
+    """Load libvclb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_10899_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [s[0] for s in _SIGS]
+
+
+def check(rc: int):
+    if rc != VCLB_OK:
+        L = lib()
+        raise VclbError(rc, f"{L.vclb_strerror(rc).decode()}: {L.vclb_last_error().decode()}")
+
+
+def to_cparams(p) -> Params:
+    """CaseParams (workloads.CaseParams or any object with the same fields) -> C struct."""
+    c = Params()
+    c.lattice = {"D2Q9": D2Q9, "D3Q19": D3Q19}[p.lattice]
+    c.storage = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}[p.storage]
+    c.mode = {"coupled": COUPLED, "vortex": PRESCRIBED_VORTEX}[p.mode]
+    c.nx, c.ny, c.nz = int(p.nx), int(p.ny), int(p.nz)
+    c.bc_y = WALL if p.wall_y else PERIODIC
+    c.nlabels = len(p.label_centres)
+    for a in range(3):
+        c.wall_u_bottom[a] = float(p.wall_u_bottom[a])
+        c.wall_u_top[a] = float(p.wall_u_top[a])
+    c.W, c.sigma, c.mobility = float(p.W), float(p.sigma), float(p.mobility)
+    c.lam, c.xi, c.eps_n = float(p.lam), float(p.xi), float(p.eps_n)
+    c.rho_heavy, c.rho_light, c.nu = float(p.rho_heavy), float(p.rho_light), float(p.nu)
+    for k, v in enumerate(p.s_g or ()):
+        c.s_g[k] = float(v)
+    for k, v in enumerate(p.s_f or ()):
+        c.s_f[k] = float(v)
+    c.U0, c.T = float(p.U0), float(p.T)
+    for k, cen in enumerate(p.label_centres[:MAX_LABELS]):
+        for a in range(3):
+            c.label_centre[k][a] = float(cen[a])
+    return c
+
+
+def validate(p) -> None:
+    check(lib().vclb_params_validate(ctypes.byref(to_cparams(p))))
+
+
+def workspace_bytes(p) -> int:
+    n = ctypes.c_size_t()
+    check(lib().vclb_case_workspace_bytes(ctypes.byref(to_cparams(p)), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Case:
+    """One simulation case living on the GPU.
+
+    Device state is a torch uint8 workspace handed to the library; calls are enqueued
+    on torch's current stream (or ``stream``)."""
+
+    def __init__(self, p, device="cuda", tile=None):
+        self.p = p
+        self.cp = to_cparams(p)
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(p)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        check(lib().vclb_case_create(ctypes.byref(self.cp), ctypes.c_void_p(aligned), nbytes, ctypes.byref(h)))
+        self.h = h
+        self.n = p.nx * p.ny * p.nz
+        self.D = 2 if p.lattice == "D2Q9" else 3
+        self.nlabels = max(1, len(p.label_centres))
+        if tile is not None:
+            self.set_tile(*tile)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                torch.cuda.synchronize(self.device)
+                lib().vclb_case_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- config
+    def set_tile(self, bx, ty, by3=1):
+        check(lib().vclb_case_set_tile(self.h, int(bx), int(ty), int(by3)))
+
+    def tile(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().vclb_case_get_tile(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_reduce_every(self, every: int):
+        check(lib().vclb_case_set_reduce_every(self.h, int(every)))
+
+    # ---------------------------------------------------------------- run
+    def init(self, phi0, u0=None, stream=None):
+        phi = torch.as_tensor(np.ascontiguousarray(phi0, dtype=np.float64).reshape(-1)).to(self.device)
+        u = None
+        if u0 is not None:
+            u = torch.as_tensor(np.ascontiguousarray(u0, dtype=np.float64).reshape(-1)).to(self.device)
+        if not torch.isfinite(phi).all():
+            raise VclbError(VCLB_ENONFINITE, "phi0 has a NaN/Inf")
+        check(lib().vclb_case_init(self.h, ctypes.c_void_p(phi.data_ptr()),
+                                   ctypes.c_void_p(u.data_ptr() if u is not None else 0), DEVICE,
+                                   _stream_handle(stream)))
+        torch.cuda.current_stream().synchronize()
+        return self
+
+    def step(self, n: int = 1, stream=None):
+        check(lib().vclb_step(self.h, int(n), _stream_handle(stream)))
+        return self
+
+    def step_plain(self, n: int = 1, stream=None):
+        check(lib().vclb_step_plain(self.h, int(n), _stream_handle(stream)))
+        return self
+
+    def time(self, stream=None) -> int:
+        t = ctypes.c_int64()
+        check(lib().vclb_case_time(self.h, ctypes.byref(t), _stream_handle(stream)))
+        return t.value
+
+    # ---------------------------------------------------------------- observe
+    def observe(self, mask: int = FIELD_PHI | FIELD_RHO | FIELD_U | FIELD_P | FIELD_MU | FIELD_PSI,
+                stream=None) -> dict:
+        """Fields of the current state as float64 numpy arrays shaped (nz, ny, nx) / (D, nz, ny, nx)."""
+        sizes = [(FIELD_PHI, "phi", 1), (FIELD_RHO, "rho", 1), (FIELD_U, "u", self.D), (FIELD_P, "p", 1),
+                 (FIELD_MU, "mu", 1), (FIELD_PSI, "psi", 1)]
+        total = sum(k for b, _, k in sizes if mask & b) * self.n
+        out = torch.empty(total, dtype=torch.float64, device=self.device)
+        check(lib().vclb_observe(self.h, mask, ctypes.c_void_p(out.data_ptr()), DEVICE, _stream_handle(stream)))
+        torch.cuda.current_stream().synchronize()
+        a = out.cpu().numpy()
+        shape = (self.p.nz, self.p.ny, self.p.nx)
+        res, off = {}, 0
+        for b, name, k in sizes:
+            if mask & b:
+                v = a[off: off + k * self.n]
+                res[name] = v.reshape((k,) + shape) if k > 1 else v.reshape(shape)
+                off += k * self.n
+        return res
+
+    def reduce(self, stream=None) -> dict:
+        arr = (Obs * self.nlabels)()
+        rc = lib().vclb_reduce(self.h, arr, _stream_handle(stream))
+        if rc not in (VCLB_OK, VCLB_ENONFINITE):
+            check(rc)
+        out = _obs_to_dict(arr, self.nlabels)
+        out["rc"] = rc
+        return out
+
+    def history(self, t_first: int, count: int, stream=None) -> dict:
+        arr = (Obs * (self.nlabels * count))()
+        rc = lib().vclb_history(self.h, int(t_first), int(count), arr, _stream_handle(stream))
+        if rc not in (VCLB_OK, VCLB_ENONFINITE):
+            check(rc)
+        d = _obs_to_dict(arr, self.nlabels * count)
+        return {k: v.reshape((count, self.nlabels) + v.shape[1:]) for k, v in d.items()}
+
+    # ---------------------------------------------------------------- checkpoints
+    def state_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        check(lib().vclb_state_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def save(self, stream=None) -> bytes:
+        n = self.state_bytes()
+        buf = ctypes.create_string_buffer(n)
+        check(lib().vclb_state_save(self.h, buf, n, _stream_handle(stream)))
+        return buf.raw
+
+    def load(self, blob: bytes, stream=None):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().vclb_state_load(self.h, buf, len(blob), _stream_handle(stream)))
+        return self
+
+
+def _obs_to_dict(arr, n) -> dict:
+    return {
+        "sum_phi": np.array([arr[k].sum_phi for k in range(n)]),
+        "count_half": np.array([arr[k].count_half for k in range(n)]),
+        "sum_phi_d": np.array([list(arr[k].sum_phi_d) for k in range(n)]),
+        "sum_phi_dd": np.array([list(arr[k].sum_phi_dd) for k in range(n)]),
+        "nonfinite": np.array([arr[k].nonfinite for k in range(n)]),
+        "step": np.array([arr[k].step for k in range(n)]),
+    }

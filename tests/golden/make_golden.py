@@ -1,0 +1,41 @@
+"""Write the stored expected values used by the GPU parity tests.
+
+Every value here comes from the CPU oracle (``oracle/``) run on the seeded inputs
+of ``workloads``; nothing comes from the HIP library.  Re-run after any change to
+the oracle's arithmetic:
+
+    python tests/golden/make_golden.py
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import Model  # noqa: E402
+
+
+def two_droplets_1000():
+    """Two static drops, 128 x 128 periodic, FP64, 1000 steps: phi, rho, u at t = 1000 and
+    the per-droplet phi sums at t = 0, 500, 1000."""
+    p, phi0, u0 = W.two_droplets("fp64")
+    m = Model(p).init(phi0, u0)
+    sums = {0: m.observables()["sum_phi"]}
+    m.step(500)
+    sums[500] = m.observables()["sum_phi"]
+    m.step(500)
+    sums[1000] = m.observables()["sum_phi"]
+    F = m.fields()
+    obs = m.observables()
+    np.savez_compressed(os.path.join(HERE, "two_droplets_fp64_t1000.npz"),
+                        phi=F["phi"], rho=F["rho"], u=F["u"], p=F["p"],
+                        sum_phi_t0=sums[0], sum_phi_t500=sums[500], sum_phi_t1000=sums[1000],
+                        count_half=obs["count_half"], sum_phi_d=obs["sum_phi_d"], sum_phi_dd=obs["sum_phi_dd"])
+
+
+if __name__ == "__main__":
+    two_droplets_1000()
+    print("wrote", HERE)

@@ -1,0 +1,134 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+symbol include/vclb.h declares, and rejects invalid input before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _vclb():
+    from paper_2505_10899_amd import vclb
+    return vclb
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "vclb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vclb_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    v = _vclb()
+    L = v.lib()
+    names = header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    # the binding wraps exactly the declared entry points
+    assert sorted(v.exported_symbols()) == names
+
+
+def test_strerror_and_version():
+    v = _vclb()
+    L = v.lib()
+    assert L.vclb_strerror(-1) == b"invalid argument"
+    assert L.vclb_strerror(-4) == b"non-finite phi"
+    assert L.vclb_version() >= 10000
+
+
+def _valid():
+    p, _, _ = W.two_droplets()
+    return p
+
+
+def test_valid_params_pass():
+    v = _vclb()
+    for p in (_valid(), W.single_vortex()[0], W.shear_droplet()[0], W.rayleigh_plateau()[0]):
+        v.validate(p)
+        assert v.workspace_bytes(p) > 0
+
+
+@pytest.mark.parametrize("change", [
+    dict(W=0.0), dict(W=float("nan")), dict(sigma=-1.0), dict(mobility=0.0), dict(nu=-0.1),
+    dict(rho_light=0.0), dict(rho_heavy=float("inf")), dict(xi=0.0), dict(lam=-0.5),
+    dict(nx=0), dict(nz=2), dict(s_g=(0, 0, 0, 2.5)), dict(s_f=(0, 0, 0, 0, 0, 0, 0, -0.1)),
+    dict(s_g=tuple([0.0] * 9 + [1.0])),          # rate for a moment D2Q9 does not have
+    dict(mode="vortex", T=0.0), dict(lattice="D3Q19", wall_y=True, nz=4),
+    dict(lattice="D3Q19", mode="vortex", nz=4), dict(wall_y=True, ny=1),
+    dict(label_centres=[(0, 0, 0)] * 3),
+])
+def test_invalid_params_rejected_without_gpu(change):
+    v = _vclb()
+    p = _valid().replace(**change)
+    with pytest.raises(v.VclbError) as e:
+        v.validate(p)
+    assert e.value.code == v.VCLB_EINVAL
+    # case creation validates first, before touching HIP
+    h = ctypes.c_void_p()
+    rc = v.lib().vclb_case_create(ctypes.byref(v.to_cparams(p)), None, 0, ctypes.byref(h))
+    assert rc == v.VCLB_EINVAL and not h.value
+    assert len(v.lib().vclb_last_error()) > 0
+
+
+def test_workspace_grows_with_storage_precision():
+    v = _vclb()
+    b = {s: v.workspace_bytes(_valid().replace(storage=s)) for s in ("fp16s", "fp32", "fp64")}
+    assert b["fp16s"] < b["fp32"] < b["fp64"]
+
+
+def _fake_case(v, p):
+    """A case on a borrowed workspace pointer: creation then makes no HIP call."""
+    nbytes = v.workspace_bytes(p)
+    h = ctypes.c_void_p()
+    rc = v.lib().vclb_case_create(ctypes.byref(v.to_cparams(p)), ctypes.c_void_p(1 << 20), nbytes, ctypes.byref(h))
+    assert rc == 0
+    return h
+
+
+def test_borrowed_workspace_checks():
+    v = _vclb()
+    p = _valid()
+    h = ctypes.c_void_p()
+    nbytes = v.workspace_bytes(p)
+    assert v.lib().vclb_case_create(ctypes.byref(v.to_cparams(p)), ctypes.c_void_p(1 << 20), nbytes - 1,
+                                    ctypes.byref(h)) == v.VCLB_ENOMEM
+    assert v.lib().vclb_case_create(ctypes.byref(v.to_cparams(p)), ctypes.c_void_p((1 << 20) + 8), nbytes,
+                                    ctypes.byref(h)) == v.VCLB_EINVAL
+
+
+def test_step_before_init_and_bad_tiles():
+    v = _vclb()
+    L = v.lib()
+    h = _fake_case(v, _valid())
+    assert L.vclb_step(h, 1, None) == v.VCLB_ESTATE
+    assert L.vclb_step(h, -1, None) == v.VCLB_EINVAL
+    assert L.vclb_case_set_tile(h, 100, 8, 1) == v.VCLB_EINVAL     # not whole waves
+    assert L.vclb_case_set_tile(h, 512, 8, 1) == v.VCLB_EINVAL     # above the launch bound
+    assert L.vclb_case_set_tile(h, 64, 0, 1) == v.VCLB_EINVAL
+    assert L.vclb_case_set_tile(h, 128, 16, 1) == 0
+    bx, ty, by = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.vclb_case_get_tile(h, ctypes.byref(bx), ctypes.byref(ty), ctypes.byref(by)) == 0
+    assert (bx.value, ty.value) == (128, 16)
+    L.vclb_case_destroy(h)
+
+
+def test_corrupt_checkpoints_rejected_before_any_copy():
+    v = _vclb()
+    L = v.lib()
+    p = _valid()
+    h = _fake_case(v, p)
+    n = ctypes.c_size_t()
+    assert L.vclb_state_bytes(h, ctypes.byref(n)) == 0
+    good_len = n.value
+    blob = ctypes.create_string_buffer(good_len)
+    # truncated
+    assert L.vclb_state_load(h, blob, good_len - 1, None) == v.VCLB_EINVAL
+    # wrong magic
+    assert L.vclb_state_load(h, blob, good_len, None) == v.VCLB_EINVAL
+    assert b"checkpoint" in L.vclb_last_error()
+    L.vclb_case_destroy(h)
