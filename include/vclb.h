@@ -158,6 +158,16 @@ int vclb_case_get_tile(const vclb_case* c, int32_t* bx, int32_t* ty, int32_t* by
 int vclb_case_init(vclb_case* c, const double* phi0, const double* u0, int ptr_kind,
                    void* stream);
 
+/* Replace the state by a given time-t state: post-streaming populations g and f
+   (Q * N doubles each, direction-major [i * N + n]; f ignored in vortex mode), the
+   previous step's phi u (D * N doubles) and the step counter t >= 0.  Values are
+   rounded to the storage precision. */
+int vclb_case_set_state(vclb_case* c, const double* g, const double* f, const double* J, int64_t t,
+                        int ptr_kind, void* stream);
+
+/* The current state in the layout of vclb_case_set_state, decoded to FP64. */
+int vclb_case_get_state(vclb_case* c, double* g, double* f, double* J, int ptr_kind, void* stream);
+
 /* Advance nsteps >= 0 time steps with the fused single-kernel step (pull streaming,
    LDS-staged phi/psi halo tiles, fused reductions).  Asynchronous. */
 int vclb_step(vclb_case* c, int64_t nsteps, void* stream);

@@ -133,7 +133,7 @@ Layout layout_for(const vclb_params& p) {
       L.pop[s][b] = need ? take(size_t(Q) * n * sb) : SIZE_MAX;
     }
   L.J = take(size_t(D) * n * rb);
-  for (int b = 0; b < 2; ++b) L.phis[b] = p.storage == VCLB_FP16S ? take(n * 4) : SIZE_MAX;
+  for (int b = 0; b < 2; ++b) L.phis[b] = p.storage != VCLB_FP64 ? take(n * 4) : SIZE_MAX;
   L.tick = take(64);
   // every launch shape uses at least 64 nodes per workgroup, plus one partial row per
   // (y, z) line for tiles that are ragged in x
@@ -432,6 +432,85 @@ int vclb_case_init(vclb_case* c, const double* phi0, const double* u0, int ptr_k
   return VCLB_OK;
 }
 
+int vclb_case_set_state(vclb_case* c, const double* g, const double* f, const double* J, int64_t t,
+                        int ptr_kind, void* stream) {
+  if (!c || !g || !J || t < 0) return fail(VCLB_EINVAL, "bad argument");
+  if (c->p.mode == VCLB_COUPLED && !f) return fail(VCLB_EINVAL, "f is NULL in coupled mode");
+  if (ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
+  hipStream_t s = as_stream(stream);
+  const size_t n = size_t(c->p.nx) * c->p.ny * c->p.nz;
+  const int Q = lattice_q(c->p.lattice), D = lattice_d(c->p.lattice);
+  const bool coupled = c->p.mode == VCLB_COUPLED;
+  const double *dg = g, *df = f, *dJ = J;
+  void* staging = nullptr;
+  if (ptr_kind == VCLB_HOST) {
+    const size_t cnt = n * (size_t(Q) * (coupled ? 2 : 1) + D);
+    HIP_TRY(hipMalloc(&staging, cnt * sizeof(double)));
+    double* st = static_cast<double*>(staging);
+    hipError_t e = hipMemcpyAsync(st, g, n * Q * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && coupled) e = hipMemcpyAsync(st + n * Q, f, n * Q * sizeof(double), hipMemcpyHostToDevice, s);
+    const size_t jo = n * Q * (coupled ? 2 : 1);
+    if (e == hipSuccess) e = hipMemcpyAsync(st + jo, J, n * D * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      (void)hipFree(staging);
+      return hip_fail(e, "hipMemcpyAsync of the state");
+    }
+    dg = st;
+    df = coupled ? st + n * Q : nullptr;
+    dJ = st + jo;
+  }
+  int rc = dispatch(*c, [&](auto dc, auto cp) {
+    using DC = decltype(dc);
+    return vclb::launch_set_state<typename DevTraits<DC>::L, typename DevTraits<DC>::St, decltype(cp)::value>(
+        dc, dg, df, dJ, long(t), s);
+  });
+  hipError_t e = hipStreamSynchronize(s);
+  if (staging) (void)hipFree(staging);
+  if (rc) return fail(VCLB_EHIP, "set_state launch failed");
+  if (e != hipSuccess) return hip_fail(e, "set_state");
+  c->t_host = t;
+  std::fill(c->recorded.begin(), c->recorded.end(), -1);
+  c->inited = true;
+  return VCLB_OK;
+}
+
+int vclb_case_get_state(vclb_case* c, double* g, double* f, double* J, int ptr_kind, void* stream) {
+  if (!c || !g || !J) return fail(VCLB_EINVAL, "bad argument");
+  if (!c->inited) return fail(VCLB_ESTATE, "get_state before init");
+  const bool coupled = c->p.mode == VCLB_COUPLED;
+  if (coupled && !f) return fail(VCLB_EINVAL, "f is NULL in coupled mode");
+  if (ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
+  hipStream_t s = as_stream(stream);
+  const size_t n = size_t(c->p.nx) * c->p.ny * c->p.nz;
+  const int Q = lattice_q(c->p.lattice), D = lattice_d(c->p.lattice);
+  double *dg = g, *df = f, *dJ = J;
+  void* staging = nullptr;
+  const size_t jo = n * Q * (coupled ? 2 : 1);
+  if (ptr_kind == VCLB_HOST) {
+    HIP_TRY(hipMalloc(&staging, (jo + n * D) * sizeof(double)));
+    double* st = static_cast<double*>(staging);
+    dg = st;
+    df = coupled ? st + n * Q : nullptr;
+    dJ = st + jo;
+  }
+  int rc = dispatch(*c, [&](auto dc, auto cp) {
+    using DC = decltype(dc);
+    return vclb::launch_get_state<typename DevTraits<DC>::L, typename DevTraits<DC>::St, decltype(cp)::value>(
+        dc, dg, df, dJ, s);
+  });
+  hipError_t e = hipSuccess;
+  if (!rc && staging) {
+    e = hipMemcpyAsync(g, dg, n * Q * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && coupled) e = hipMemcpyAsync(f, df, n * Q * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(J, dJ, n * D * sizeof(double), hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (staging) (void)hipFree(staging);
+  if (rc) return fail(VCLB_EHIP, "get_state launch failed");
+  if (e != hipSuccess) return hip_fail(e, "get_state");
+  return VCLB_OK;
+}
+
 static int do_steps(vclb_case* c, int64_t nsteps, void* stream, bool fused) {
   if (!c) return fail(VCLB_EINVAL, "case is NULL");
   if (nsteps < 0) return fail(VCLB_EINVAL, "nsteps < 0");
@@ -587,7 +666,7 @@ std::vector<Span> state_spans(const vclb_case* c, int par) {
   v.push_back({c->lay.pop[0][par], size_t(Q) * n * storage_bytes(c->p.storage)});
   if (c->p.mode == VCLB_COUPLED) v.push_back({c->lay.pop[1][par], size_t(Q) * n * storage_bytes(c->p.storage)});
   v.push_back({c->lay.J, size_t(D) * n * arith_bytes(c->p.storage)});
-  if (c->p.storage == VCLB_FP16S) v.push_back({c->lay.phis[par], n * 4});
+  if (c->p.storage != VCLB_FP64) v.push_back({c->lay.phis[par], n * 4});
   return v;
 }
 

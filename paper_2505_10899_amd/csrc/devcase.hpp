@@ -44,11 +44,12 @@ __device__ __forceinline__ double min_image(double d, int n, bool periodic) {
 
 // Pull the Q populations of one set arriving at node (x, y, z):
 // pop_i(x) = post_i(x - c_i), or the node's own opposite post-collision value when
-// x - c_i lies behind a wall.  Decodes the FP16S deviation storage.
+// x - c_i lies behind a wall.  For shifted storage (g set) `out` receives the stored
+// deviations d_i and `ps` the phi of the node that wrote them (see phi_of_pulled).
 template <class L, class St, class Case>
 __device__ __forceinline__ void pull(const Case& c, const typename St::S* __restrict__ src,
                                      const float* __restrict__ phis, int x, int y, int z,
-                                     typename St::R (&out)[L::Q], bool shifted_set) {
+                                     typename St::R (&out)[L::Q], typename St::R* ps) {
   using R = typename St::R;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
@@ -67,12 +68,31 @@ __device__ __forceinline__ void pull(const Case& c, const typename St::S* __rest
     if (L::cx[i] != 0) xs = wrapi(xs, c.nx);
     if (L::cz[i] != 0) zs = wrapi(zs, c.nz);
     const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
-    R v = St::load(src, long(pi) * c.n + s);
+    out[i] = St::load(src, long(pi) * c.n + s);
     if constexpr (St::shifted) {
-      if (shifted_set) v += phis[s] * c.np.rest[pi];
+      if (ps) ps[i] = R(phis[s]);
     }
-    out[i] = v;
   }
+}
+
+// phi = sum_i g_i (Eq. 35) of a pulled g set.  For shifted storage g_i = d_i + r_i phi_s,
+// and on return v holds e_i = g_i - r_i phi = d_i + r_i (phi_s - phi): the deviation
+// from this node's own rest state, formed without rounding at the magnitude of g.
+template <class L, class St>
+__device__ __forceinline__ typename St::R phi_of_pulled(typename St::R (&v)[L::Q], const typename St::R (&ps)[L::Q],
+                                                        const typename St::R (&rest)[L::Q]) {
+  using R = typename St::R;
+  R phi = R(0);
+  if constexpr (St::shifted) {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) phi += v[i] + rest[i] * ps[i];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) v[i] = v[i] + rest[i] * (ps[i] - phi);
+  } else {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) phi += v[i];
+  }
+  return phi;
 }
 
 template <class R>
@@ -203,11 +223,7 @@ __device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, lon
   using R = typename St::R;
   const int dst = par ^ 1;
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    R v = g[i];
-    if constexpr (St::shifted) v -= phi * c.np.rest[i];
-    St::store(c.pop[0][dst], long(i) * c.n + n, v);
-  }
+  for (int i = 0; i < L::Q; ++i) St::store(c.pop[0][dst], long(i) * c.n + n, g[i]);
   if constexpr (COUPLED) {
     if (c.wall) {
       if (y == 0) {

@@ -85,6 +85,77 @@ __global__ void __launch_bounds__(256) k_init(DevCase<L, St> c, const double* __
   }
 }
 
+// ---------------------------------------------------------------- explicit state
+// Store a given time-t state (post-streaming populations in FP64) where the next pull
+// looks for it.  FP16S: the phi of node s that encodes entry s is sum_i g_i(s).
+template <class L, class St, bool COUPLED>
+__global__ void __launch_bounds__(256) k_set_state(DevCase<L, St> c, const double* __restrict__ g,
+                                                   const double* __restrict__ f, const double* __restrict__ J,
+                                                   int par) {
+  using R = typename St::R;
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  if (n >= c.n) return;
+  const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    int xs = x - L::cx[i], ys = y - L::cy[i], zs = z - L::cz[i], pi = i;
+    if (L::cy[i] != 0 && (ys < 0 || ys >= c.ny)) {
+      if (c.wall) { xs = x; ys = y; zs = z; pi = L::opp[i]; }
+      else ys = wrapi(ys, c.ny);
+    }
+    xs = wrapi(xs, c.nx);
+    zs = wrapi(zs, c.nz);
+    const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
+    R gv = R(g[long(i) * c.n + n]);
+    if constexpr (St::shifted) {
+      double ps = 0.0;
+      for (int k = 0; k < L::Q; ++k) ps += g[long(k) * c.n + s];
+      gv -= R(float(ps)) * c.np.rest[pi];
+    }
+    St::store(c.pop[0][par], long(pi) * c.n + s, gv);
+    if constexpr (COUPLED) St::store(c.pop[1][par], long(pi) * c.n + s, R(f[long(i) * c.n + n]));
+  }
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) c.J[d * c.n + n] = R(J[d * c.n + n]);
+  if constexpr (St::shifted) {
+    double ps = 0.0;
+    for (int k = 0; k < L::Q; ++k) ps += g[long(k) * c.n + n];
+    c.phis[par][n] = float(ps);
+  }
+}
+
+// The time-t state (pulled, decoded populations and previous phi u) in FP64.
+template <class L, class St, bool COUPLED>
+__global__ void __launch_bounds__(256) k_get_state(DevCase<L, St> c, double* __restrict__ g,
+                                                   double* __restrict__ f, double* __restrict__ J) {
+  using R = typename St::R;
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  if (n >= c.n) return;
+  const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
+  const int par = int(c.tick[0] & 1ULL);
+  R v[L::Q], ps[L::Q];
+  pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, v, ps);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    R gi = v[i];
+    if constexpr (St::shifted) gi += c.np.rest[i] * ps[i];
+    g[long(i) * c.n + n] = double(gi);
+  }
+  if constexpr (COUPLED) {
+    pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, v, nullptr);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) f[long(i) * c.n + n] = double(v[i]);
+  }
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) J[d * c.n + n] = double(c.J[d * c.n + n]);
+}
+
+template <class L, class St>
+__global__ void k_set_tick(DevCase<L, St> c, unsigned long long t) {
+  c.tick[0] = t;
+  c.tick[1] = 0;
+}
+
 // ---------------------------------------------------------------- plain path, pass 1
 // phi = sum g (Eq. 35) and psi (Eq. 37) of every node into scratch arrays.
 template <class L, class St>
@@ -94,11 +165,9 @@ __global__ void __launch_bounds__(256) k_phi_psi(DevCase<L, St> c) {
   if (n >= c.n) return;
   const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
   const int par = int(c.tick[0] & 1ULL);
-  R g[L::Q];
-  pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, true);
-  R phi = R(0);
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i) phi += g[i];
+  R g[L::Q], ps[L::Q];
+  pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, ps);
+  const R phi = phi_of_pulled<L, St>(g, ps, c.np.rest);
   c.tmp_phi[n] = phi;
   c.tmp_psi[n] = psi_of<R>(phi, c.np.W4, c.np.xi);
 }
@@ -130,13 +199,14 @@ __global__ void __launch_bounds__(256) k_collide_plain(DevCase<L, St> c, int red
     gather<L, St>(c, c.tmp_phi, x, y, z, in.nphi);
     gather<L, St>(c, c.tmp_psi, x, y, z, in.npsi);
     prescribed<L, St, COUPLED>(c, x, y, t, in);
-    R g[L::Q], f[L::Q], J[L::D];
-    pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, true);
-    if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, false);
+    R g[L::Q], ps[L::Q], f[L::Q], J[L::D];
+    pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, ps);
+    (void)phi_of_pulled<L, St>(g, ps, c.np.rest);
+    if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, nullptr);
 #pragma unroll
     for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
     NodeOut<L, R> out;
-    node_update<L, R, COUPLED>(c.np, in, g, f, J, out);
+    node_update<L, R, COUPLED, St::shifted>(c.np, in, g, f, J, out);
     store_node<L, St, COUPLED>(c, par, n, y, in.nphi[0], out.rho, g, f, J);
     if (reduce) accumulate(c, acc, double(in.nphi[0]), x, y, z);
   }
@@ -156,13 +226,14 @@ __global__ void __launch_bounds__(256) k_fields(DevCase<L, St> c, unsigned mask,
   gather<L, St>(c, c.tmp_phi, x, y, z, in.nphi);
   gather<L, St>(c, c.tmp_psi, x, y, z, in.npsi);
   prescribed<L, St, COUPLED>(c, x, y, t, in);
-  R g[L::Q], f[L::Q], J[L::D];
-  pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, true);
-  if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, false);
+  R g[L::Q], ps[L::Q], f[L::Q], J[L::D];
+  pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, ps);
+  (void)phi_of_pulled<L, St>(g, ps, c.np.rest);
+  if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, nullptr);
 #pragma unroll
   for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
   NodeOut<L, R> o;
-  node_update<L, R, COUPLED>(c.np, in, g, f, J, o);
+  node_update<L, R, COUPLED, St::shifted>(c.np, in, g, f, J, o);
   long off = 0;
   if (mask & 0x01u) { out[off + n] = double(in.nphi[0]); off += c.n; }
   if (mask & 0x02u) { out[off + n] = double(o.rho); off += c.n; }
@@ -230,18 +301,15 @@ __global__ void __launch_bounds__(256) k_step2d(DevCase<D2Q9, St> c, int TY, int
   auto slot = [](int r) -> int { return (r + 4) & 3; };
   auto phi_row = [&](int r, R (&g)[Q]) {
     const int yr = row_of(r);
-    pull<L, St>(c, gsrc, phis, xw, yr, 0, g, true);
-    R ph = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) ph += g[i];
+    R ps[Q];
+    pull<L, St>(c, gsrc, phis, xw, yr, 0, g, ps);
+    const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     sphi[slot(r) * W + lane + 1] = ph;
     spsi[slot(r) * W + lane + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
     if (halo_lane) {
-      R gh[Q];
-      pull<L, St>(c, gsrc, phis, xh, yr, 0, gh, true);
-      R hp = R(0);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) hp += gh[i];
+      R gh[Q], hps[Q];
+      pull<L, St>(c, gsrc, phis, xh, yr, 0, gh, hps);
+      const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       sphi[slot(r) * W + hidx] = hp;
       spsi[slot(r) * W + hidx] = psi_of<R>(hp, c.np.W4, c.np.xi);
     }
@@ -265,11 +333,11 @@ __global__ void __launch_bounds__(256) k_step2d(DevCase<D2Q9, St> c, int TY, int
       prescribed<L, St, COUPLED>(c, xw, y, t, in);
       const long n = xw + long(c.nx) * y;
       R f[Q], J[L::D];
-      if constexpr (COUPLED) pull<L, St>(c, fsrc, phis, xw, y, 0, f, false);
+      if constexpr (COUPLED) pull<L, St>(c, fsrc, phis, xw, y, 0, f, nullptr);
 #pragma unroll
       for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
       NodeOut<L, R> out;
-      node_update<L, R, COUPLED>(c.np, in, gcur, f, J, out);
+      node_update<L, R, COUPLED, St::shifted>(c.np, in, gcur, f, J, out);
       store_node<L, St, COUPLED>(c, par, n, y, in.nphi[0], out.rho, gcur, f, J);
       if (reduce) accumulate(c, acc, double(in.nphi[0]), xw, y, 0);
     }
@@ -325,7 +393,27 @@ int launch_reduce_state(const DevCase<L, St>& c, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+template <class L, class St, bool COUPLED>
+int launch_set_state(const DevCase<L, St>& c, const double* g, const double* f, const double* J, long t,
+                     hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_set_state<L, St, COUPLED>), dim3(nb), dim3(256), 0, s, c, g, f, J, int(t & 1));
+  hipLaunchKernelGGL((k_set_tick<L, St>), dim3(1), dim3(1), 0, s, c, (unsigned long long)t);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class L, class St, bool COUPLED>
+int launch_get_state(const DevCase<L, St>& c, double* g, double* f, double* J, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_get_state<L, St, COUPLED>), dim3(nb), dim3(256), 0, s, c, g, f, J);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 #define VCLB_INSTANTIATE(L, St, C)                                                              \
+  template int launch_set_state<L, St, C>(const DevCase<L, St>&, const double*, const double*, \
+                                          const double*, long, hipStream_t);                   \
+  template int launch_get_state<L, St, C>(const DevCase<L, St>&, double*, double*, double*,    \
+                                          hipStream_t);                                        \
   template int launch_init<L, St, C>(const DevCase<L, St>&, const double*, const double*,      \
                                      hipStream_t);                                             \
   template int launch_step_plain<L, St, C>(const DevCase<L, St>&, int, hipStream_t);           \

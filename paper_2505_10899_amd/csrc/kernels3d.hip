@@ -44,10 +44,9 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
   auto plane = [&](int z, R (&g)[Q]) {
     const int zr = wrapi(z, c.nz);
     const int s = slot(z) * PS;
-    pull<L, St>(c, gsrc, phis, xw, yw, zr, g, true);
-    R ph = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) ph += g[i];
+    R ps[Q];
+    pull<L, St>(c, gsrc, phis, xw, yw, zr, g, ps);
+    const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     sphi[s + (ty + 1) * PW + tx + 1] = ph;
     spsi[s + (ty + 1) * PW + tx + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
     for (int k = tid; k < ring; k += nthr) {
@@ -58,11 +57,9 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       else { px = PW - 1; py = 1 + k - 2 * PW - BY; }
       const int hx = ((x0 - 1 + px) % c.nx + c.nx) % c.nx;
       const int hy = ((y0 - 1 + py) % c.ny + c.ny) % c.ny;
-      R gh[Q];
-      pull<L, St>(c, gsrc, phis, hx, hy, zr, gh, true);
-      R hp = R(0);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) hp += gh[i];
+      R gh[Q], hps[Q];
+      pull<L, St>(c, gsrc, phis, hx, hy, zr, gh, hps);
+      const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       sphi[s + py * PW + px] = hp;
       spsi[s + py * PW + px] = psi_of<R>(hp, c.np.W4, c.np.xi);
     }
@@ -85,11 +82,11 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       }
       const long n = xw + long(c.nx) * (yw + long(c.ny) * z);
       R f[Q], J[L::D];
-      pull<L, St>(c, fsrc, phis, xw, yw, z, f, false);
+      pull<L, St>(c, fsrc, phis, xw, yw, z, f, nullptr);
 #pragma unroll
       for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
       NodeOut<L, R> out;
-      node_update<L, R, true>(c.np, in, gcur, f, J, out);
+      node_update<L, R, true, St::shifted>(c.np, in, gcur, f, J, out);
       store_node<L, St, true>(c, par, n, yw, in.nphi[0], out.rho, gcur, f, J);
       if (reduce) accumulate(c, acc, double(in.nphi[0]), xw, yw, z);
     }

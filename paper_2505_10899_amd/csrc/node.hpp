@@ -26,17 +26,21 @@ struct StoreF64 {
   __device__ static R load(const S* p, long i) { return p[i]; }
   __device__ static void store(S* p, long i, R v) { p[i] = v; }
 };
+// FP32 storage uses the same deviation representation as FP16S (see below): the g
+// arithmetic then never rounds at the magnitude of the rest populations (~0.7), which
+// keeps the total of phi conserved to the rounding of small quantities.
 struct StoreF32 {
   using S = float;
   using R = float;
-  static constexpr bool shifted = false;
+  static constexpr bool shifted = true;
   __device__ static R load(const S* p, long i) { return p[i]; }
   __device__ static void store(S* p, long i, R v) { p[i] = v; }
 };
 // FP16 storage of deviations from the rest equilibrium: g_i - phi r_i with
 // r_0 = 1 + (w_0 - 1) lambda, r_i = w_i lambda (g_eq at u = 0, mu = 0); f is stored
 // as is (its rest equilibrium, f_eq at p = 0 and u = 0, vanishes).  phi of the node
-// that wrote the value travels beside it in FP32.
+// that wrote the value travels beside it in FP32.  Shifted storage also switches the
+// g collision to deviation variables e_i = g_i - r_i phi (node_update, SH = true).
 struct StoreF16S {
   using S = __half;
   using R = float;
@@ -101,8 +105,9 @@ __device__ __forceinline__ R stencil_lap(const R (&nb)[L::Q]) {
   return s;
 }
 
-// pop <- pop + src - M^T diag(srate) M (pop - eq + src/2)
-template <class L, class R>
+// pop <- pop + src - M^T diag(srate) M (pop - eq + src/2); with CONSERVE the zeroth
+// moment (sum of the populations, equal to that of the equilibrium) is not relaxed.
+template <class L, class R, bool CONSERVE>
 __device__ __forceinline__ void mrt_collide(R (&pop)[L::Q], const R (&eq)[L::Q], const R (&src)[L::Q],
                                             const R (&srate)[L::Q]) {
   R h[L::Q];
@@ -119,7 +124,7 @@ __device__ __forceinline__ void mrt_collide(R (&pop)[L::Q], const R (&eq)[L::Q],
       else if (m == -1) acc -= h[i];
       else if (m != 0) acc += R(m) * h[i];
     }
-    y[k] = acc * srate[k];
+    y[k] = (CONSERVE && k == 0) ? R(0) : acc * srate[k];
   }
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
@@ -150,8 +155,11 @@ struct NodeOut {
 };
 
 // One node of one time step.  g, f: pulled (time-t) populations in, post-collision out;
-// J: previous phi u in, this step's phi u out.
-template <class L, class R, bool COUPLED>
+// J: previous phi u in, this step's phi u out.  With SH, g holds the deviations
+// e_i = g_i - r_i phi from the node's rest state (in and out): the equilibrium enters as
+// g_eq - r phi, and the relaxation of the conserved moment sum_i g_i (zero in exact
+// arithmetic) is dropped, so no operation rounds at the magnitude of phi.
+template <class L, class R, bool COUPLED, bool SH = false>
 __device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const NodeIn<L, R>& in,
                                             R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D],
                                             NodeOut<L, R>& out) {
@@ -232,10 +240,11 @@ __device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const Nod
         else if (cc[d] == -1) { cJ -= J[d]; cV -= V[d]; }
       }
       const R wi = R(L::w[i]);
-      geq[i] = (i == 0) ? phi + R(L::w[0] - 1.0) * H : wi * H + wi * (R(3) * cJ);
+      if constexpr (SH) geq[i] = (i == 0) ? R(L::w[0] - 1.0) * mu : wi * mu + wi * (R(3) * cJ);
+      else geq[i] = (i == 0) ? phi + R(L::w[0] - 1.0) * H : wi * H + wi * (R(3) * cJ);
       G[i] = wi * cV;
     }
-    mrt_collide<L, R>(g, geq, G, p.sg);
+    mrt_collide<L, R, SH>(g, geq, G, p.sg);
   }
   // f: equilibrium Eqs. 22-23, forcing Eq. 21 (in the exactly equivalent form
   // w_i [c_i.F + (c_i.u)(c_i.grad rho)] / cs^2) and collision Eq. 25
@@ -258,7 +267,7 @@ __device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const Nod
       feq[i] = (i == 0) ? R(3.0 * (L::w[0] - 1.0)) * press + rho * si : R(3.0 * L::w[i]) * press + rho * si;
       Fi[i] = R(3.0 * L::w[i]) * (cF + cu * cg);
     }
-    mrt_collide<L, R>(f, feq, Fi, p.sf);
+    mrt_collide<L, R, false>(f, feq, Fi, p.sf);
   }
   out.rho = rho;
   out.mu = mu;

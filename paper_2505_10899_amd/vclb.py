@@ -73,6 +73,10 @@ _SIGS = [
     ("vclb_case_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("vclb_case_get_tile", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     ("vclb_case_init", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    ("vclb_case_set_state", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]),
+    ("vclb_case_get_state", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int, ctypes.c_void_p]),
     ("vclb_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("vclb_step_plain", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("vclb_case_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -209,6 +213,32 @@ class Case:
                                    _stream_handle(stream)))
         torch.cuda.current_stream().synchronize()
         return self
+
+    def set_state(self, g, f, J, t: int, stream=None):
+        """Load a time-t state: g, f of shape (Q, nz, ny, nx), J of shape (D, nz, ny, nx)."""
+        dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to(self.device)
+        tg, tJ = dev(g), dev(J)
+        tf = dev(f) if self.p.mode == "coupled" else None
+        check(lib().vclb_case_set_state(self.h, ctypes.c_void_p(tg.data_ptr()),
+                                        ctypes.c_void_p(tf.data_ptr() if tf is not None else 0),
+                                        ctypes.c_void_p(tJ.data_ptr()), int(t), DEVICE, _stream_handle(stream)))
+        return self
+
+    def get_state(self, stream=None):
+        """(g, f, J) of the current state as float64 numpy arrays (f is None in vortex mode)."""
+        Q = 9 if self.D == 2 else 19
+        shape = (self.p.nz, self.p.ny, self.p.nx)
+        g = torch.empty(Q * self.n, dtype=torch.float64, device=self.device)
+        J = torch.empty(self.D * self.n, dtype=torch.float64, device=self.device)
+        f = torch.empty(Q * self.n, dtype=torch.float64, device=self.device) if self.p.mode == "coupled" else None
+        check(lib().vclb_case_get_state(self.h, ctypes.c_void_p(g.data_ptr()),
+                                        ctypes.c_void_p(f.data_ptr() if f is not None else 0),
+                                        ctypes.c_void_p(J.data_ptr()), DEVICE, _stream_handle(stream)))
+        torch.cuda.current_stream().synchronize()
+        g = g.cpu().numpy().reshape((Q,) + shape)
+        J = J.cpu().numpy().reshape((self.D,) + shape)
+        f = f.cpu().numpy().reshape((Q,) + shape) if f is not None else None
+        return g, f, J
 
     def step(self, n: int = 1, stream=None):
         check(lib().vclb_step(self.h, int(n), _stream_handle(stream)))

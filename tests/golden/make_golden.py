@@ -19,8 +19,10 @@ from oracle import Model  # noqa: E402
 
 
 def two_droplets_1000():
-    """Two static drops, 128 x 128 periodic, FP64, 1000 steps: phi, rho, u at t = 1000 and
-    the per-droplet phi sums at t = 0, 500, 1000."""
+    """Two static drops, 128 x 128 periodic, FP64, 1000 steps: phi, rho, u, p at t = 1000,
+    the per-droplet reductions at t = 0, 500, 1000, and the oracle's own round-off
+    envelope: the largest change of each field at t = 1000 when phi0 is perturbed by a
+    relative 1e-15 (seeded normal noise)."""
     p, phi0, u0 = W.two_droplets("fp64")
     m = Model(p).init(phi0, u0)
     sums = {0: m.observables()["sum_phi"]}
@@ -30,10 +32,21 @@ def two_droplets_1000():
     sums[1000] = m.observables()["sum_phi"]
     F = m.fields()
     obs = m.observables()
+    rng = np.random.default_rng(1)
+    q = Model(p).init(phi0 * (1.0 + 1e-15 * rng.standard_normal(phi0.shape)), u0)
+    q.step(1000)
+    G = q.fields()
+    env = {k: float(np.max(np.abs(F[k] - G[k]))) for k in ("phi", "rho", "u", "p")}
+    oq = q.observables()
+    env_sum = np.abs(oq["sum_phi"] - obs["sum_phi"])
+    env_count = np.abs(oq["count_half"] - obs["count_half"])
     np.savez_compressed(os.path.join(HERE, "two_droplets_fp64_t1000.npz"),
                         phi=F["phi"], rho=F["rho"], u=F["u"], p=F["p"],
                         sum_phi_t0=sums[0], sum_phi_t500=sums[500], sum_phi_t1000=sums[1000],
-                        count_half=obs["count_half"], sum_phi_d=obs["sum_phi_d"], sum_phi_dd=obs["sum_phi_dd"])
+                        count_half=obs["count_half"], sum_phi_d=obs["sum_phi_d"], sum_phi_dd=obs["sum_phi_dd"],
+                        env_phi=env["phi"], env_rho=env["rho"], env_u=env["u"], env_p=env["p"],
+                        env_sum_phi=env_sum, env_count_half=env_count)
+    print("round-off envelope at t = 1000:", env, "per-drop sums", env_sum, "counts", env_count)
 
 
 if __name__ == "__main__":
