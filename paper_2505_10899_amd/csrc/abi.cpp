@@ -111,7 +111,7 @@ int validate(const vclb_params* p) {
 }
 
 struct Layout {
-  size_t pop[2][2], J, phis[2], tick, partials, hist, cur, tmp_phi, tmp_psi, total;
+  size_t pop[2][2], J, phis[2], partials, hist, cur, tmp_phi, tmp_psi, total;
   long partial_blocks;
 };
 
@@ -134,7 +134,6 @@ Layout layout_for(const vclb_params& p) {
     }
   L.J = take(size_t(D) * n * rb);
   for (int b = 0; b < 2; ++b) L.phis[b] = p.storage != VCLB_FP64 ? take(n * 4) : SIZE_MAX;
-  L.tick = take(64);
   // every launch shape uses at least 64 nodes per workgroup, plus one partial row per
   // (y, z) line for tiles that are ragged in x
   L.partial_blocks = long(n / 64) + long(p.ny) * p.nz + 64;
@@ -190,6 +189,11 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
       double v;
       if (p.nlabels == 0) v = a == 0 ? (p.nx - 1) / 2.0 : (a == 1 ? (p.ny - 1) / 2.0 : (p.nz - 1) / 2.0);
       else v = p.label_centre[std::min(k, p.nlabels - 1)][a];
+      // periodic axes: the minimum-image displacement is periodic in the centre, so the
+      // centre is moved into [0, n) (the kernels rely on it to wrap without a division)
+      const int na = a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
+      const bool periodic = !(a == 1 && p.bc_y == VCLB_WALL);
+      if (periodic) v = v - na * std::floor(v / na);
       d.cen[k][a] = v;
     }
   for (int s = 0; s < 2; ++s)
@@ -198,7 +202,7 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   d.J = reinterpret_cast<R*>(c.ws + c.lay.J);
   for (int b = 0; b < 2; ++b)
     d.phis[b] = c.lay.phis[b] == SIZE_MAX ? nullptr : reinterpret_cast<float*>(c.ws + c.lay.phis[b]);
-  d.tick = reinterpret_cast<unsigned long long*>(c.ws + c.lay.tick);
+  d.t = long(c.t_host);
   d.partials = reinterpret_cast<double*>(c.ws + c.lay.partials);
   d.hist = reinterpret_cast<double*>(c.ws + c.lay.hist);
   d.cur = reinterpret_cast<double*>(c.ws + c.lay.cur);
@@ -218,6 +222,8 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   for (int k = 0; k < L::Q; ++k) {
     np.sg[k] = R(c.sg[k] / vclb::row_norm<L>(k));
     np.sf[k] = R(c.sf[k] / vclb::row_norm<L>(k));
+    np.sgr[k] = R(c.sg[k]);
+    np.sfr[k] = R(c.sf[k]);
     np.rest[k] = R(k == 0 ? 1.0 + (L::w[0] - 1.0) * p.lambda : L::w[k] * p.lambda);
     // moving-wall term 2 w_i rho (c_i . u_wall) / cs^2 of the incoming direction i = opp(k),
     // stored on the outgoing direction k at the first (bottom) / last (top) y row
@@ -268,9 +274,10 @@ vclb::Tile default_tile(const vclb_params& p) {
     int bx = std::min(256, (p.nx + 63) / 64 * 64);
     t.bx = bx;
     const long strips = (p.nx + bx - 1) / bx;
-    // aim for >= 2048 workgroups when the grid allows, with 8..64 rows each
-    long ty = (long(p.ny) * strips) / 2048;
-    t.ty = int(std::max(4L, std::min(64L, ty)));
+    // long marches amortise the two halo rows; keep >= 1024 workgroups (four per CU)
+    // when the grid allows, with 8..64 rows each
+    long ty = (long(p.ny) * strips) / 1024;
+    t.ty = int(std::max(8L, std::min(64L, ty)));
     t.by3 = 1;
   } else {
     t.bx = std::min(64, (p.nx + 31) / 32 * 32);
@@ -542,11 +549,8 @@ int vclb_step_plain(vclb_case* c, int64_t nsteps, void* stream) { return do_step
 
 int vclb_case_time(vclb_case* c, int64_t* t, void* stream) {
   if (!c || !t) return fail(VCLB_EINVAL, "NULL argument");
-  unsigned long long v = 0;
-  hipStream_t s = as_stream(stream);
-  HIP_TRY(hipMemcpyAsync(&v, c->ws + c->lay.tick, sizeof(v), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *t = int64_t(v);
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+  *t = c->t_host;
   return VCLB_OK;
 }
 
@@ -729,8 +733,6 @@ int vclb_state_load(vclb_case* c, const void* host_buf, size_t bytes, void* stre
     HIP_TRY(hipMemcpyAsync(c->ws + sp.off, src + off, sp.bytes, hipMemcpyHostToDevice, s));
     off += sp.bytes;
   }
-  unsigned long long tick[2] = {static_cast<unsigned long long>(h.step), 0ULL};
-  HIP_TRY(hipMemcpyAsync(c->ws + c->lay.tick, tick, sizeof(tick), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   c->t_host = h.step;
   std::fill(c->recorded.begin(), c->recorded.end(), -1);

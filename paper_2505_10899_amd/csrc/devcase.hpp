@@ -25,7 +25,7 @@ struct DevCase {
   S* pop[2][2];                 // [g = 0, f = 1][buffer]; f is null in vortex mode
   R* J;                         // previous phi u, D * n
   float* phis[2];               // FP16S: phi of the node that wrote each buffer entry
-  unsigned long long* tick;     // [0] step counter, [1] block ticket
+  long t;                       // step index of the state this launch reads
   double* partials;             // [block][label][kObsFields]
   double* hist;                 // [kHistory][label][kObsFields]
   double* cur;                  // [label][kObsFields] reductions of the current state
@@ -36,10 +36,12 @@ struct DevCase {
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Displacement wrapped to [-n/2, n/2) along a periodic axis; valid for node and centre
+// both in [0, n) (the host moves label centres there), so no division is needed.
 __device__ __forceinline__ double min_image(double d, int n, bool periodic) {
   if (!periodic) return d;
-  const double dn = double(n);
-  return d - dn * floor((d + 0.5 * dn) / dn);
+  const double h = 0.5 * double(n);
+  return d < -h ? d + double(n) : (d >= h ? d - double(n) : d);
 }
 
 // Pull the Q populations of one set arriving at node (x, y, z):
@@ -151,66 +153,45 @@ __device__ __forceinline__ void accumulate(const Case& c, Acc& a, double phi, in
   }
 }
 
-// Sum one value over the block in a fixed order; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sum nf <= 24 values over the workgroup in a fixed order (deterministic): butterfly
+// within each wave, then wave results in wave order.  Thread f < nf returns field f.
+template <int NF>
+__device__ __forceinline__ double block_sum_fields(const double (&v)[NF], int nf, double* red) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int w = 0; w < nw; ++w) s += red[w];
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    if (f < nf) {
+      double s = v[f];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) red[wave * NF + f] = s;
+    }
   }
-  return s;
+  __syncthreads();
+  double out = 0.0;
+  if (int(threadIdx.x) < nf)
+    for (int w = 0; w < nw; ++w) out += red[w * NF + threadIdx.x];
+  return out;
 }
 
-// End of a step kernel: optional block partials of the reductions, then the block
-// ticket; the last block to arrive sums the partials in block order into `dest`
-// (deterministic) and, if `advance`, increments the step counter.
+// End of a step kernel: this workgroup's partial volume reductions, written to its own
+// slot; k_finalize sums the slots in workgroup order after the kernel has finished
+// (no device-scope fence inside the step: on gfx950 it would write back and invalidate
+// the XCD's whole L2, which the neighbouring tiles are still reading).
 template <class Case>
-__device__ __forceinline__ void finish_block(const Case& c, Acc& a, bool reduce, double* dest, bool advance,
-                             long step) {
-  __shared__ double red[16];
-  __shared__ unsigned long long ticket;
+__device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool reduce) {
+  if (!reduce) return;
+  __shared__ double red[16 * kMaxLabels * 12];
+  constexpr int NF = kMaxLabels * 12;
   const int nf = c.nl * 12;
-  if (reduce) {
+  double v[NF];
 #pragma unroll
-    for (int k = 0; k < kMaxLabels; ++k) {
-      if (k < c.nl) {
+  for (int k = 0; k < kMaxLabels; ++k)
 #pragma unroll
-        for (int f = 0; f < 12; ++f) {
-          const double s = block_sum(a.v[k][f], red);
-          if (threadIdx.x == 0) c.partials[long(blockIdx.x) * nf + k * 12 + f] = s;
-        }
-      }
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) ticket = atomicAdd(&c.tick[1], 1ULL);
-  __syncthreads();
-  if (ticket != gridDim.x - 1) return;
-  __threadfence();
-  if (reduce) {
-    for (int fi = 0; fi < nf; ++fi) {
-      double s = 0.0;
-      for (int b = threadIdx.x; b < int(gridDim.x); b += blockDim.x)
-        s += __builtin_nontemporal_load(&c.partials[long(b) * nf + fi]);
-      s = block_sum(s, red);
-      if (threadIdx.x == 0) {
-        const int k = fi / 12, f = fi % 12;
-        dest[k * kObsFields + f] = s;
-        if (f == 0) dest[k * kObsFields + 12] = double(step);
-      }
-    }
-  }
-  if (threadIdx.x == 0) {
-    atomicExch(&c.tick[1], 0ULL);
-    if (advance) atomicAdd(&c.tick[0], 1ULL);
-  }
+    for (int f = 0; f < 12; ++f) v[k * 12 + f] = a.v[k][f];
+  const double s = block_sum_fields<NF>(v, nf, red);
+  if (int(threadIdx.x) < nf) c.partials[long(blockIdx.x) * nf + threadIdx.x] = s;
 }
 
 // store one node's post-collision state (with the moving-wall term on f for the

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
   const int xg = x0 + tx, yg = y0 + ty;
   const bool active = xg < c.nx && yg < c.ny;
   const int xw = xg % c.nx, yw = yg % c.ny;
-  const long t = long(c.tick[0]);
+  const long t = c.t;
   const int par = int(t & 1);
   const typename St::S* gsrc = c.pop[0][par];
   const typename St::S* fsrc = c.pop[1][par];
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
 #pragma unroll
     for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
   }
-  finish_block(c, acc, reduce != 0, c.hist + (t % kHistory) * c.nl * kObsFields, true, t);
+  finish_block(c, acc, reduce != 0);
 }
 
 template <class St>

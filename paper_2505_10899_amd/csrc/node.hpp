@@ -66,6 +66,8 @@ struct NodeParams {
   R wb[L::Q];    // moving-wall term for outgoing direction o at the first y row (times rho)
   R wt[L::Q];    // same at the last y row
   R rest[L::Q];  // FP16S rest-equilibrium coefficients r_i
+  R sgr[L::Q];   // s_k^g (unscaled)
+  R sfr[L::Q];   // s_k^f (unscaled)
   R U0;          // vortex amplitude
   double T;      // vortex period (steps)
 };
@@ -160,7 +162,7 @@ struct NodeOut {
 // g_eq - r phi, and the relaxation of the conserved moment sum_i g_i (zero in exact
 // arithmetic) is dropped, so no operation rounds at the magnitude of phi.
 template <class L, class R, bool COUPLED, bool SH = false>
-__device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const NodeIn<L, R>& in,
+__device__ __forceinline__ void node_update_generic(const NodeParams<L, R>& p, const NodeIn<L, R>& in,
                                             R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D],
                                             NodeOut<L, R>& out) {
   constexpr int Q = L::Q, D = L::D;
@@ -274,6 +276,143 @@ __device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const Nod
   out.press = press;
 #pragma unroll
   for (int d = 0; d < D; ++d) out.u[d] = u[d];
+}
+
+// ---------------------------------------------------------------- D2Q9 in closed form
+// m = M g with the shared partial sums of the rows of Eq. 24
+template <class R>
+__device__ __forceinline__ void d2q9_moments(const R (&v)[9], R (&m)[9]) {
+  const R a14 = (v[1] + v[3]) + (v[2] + v[4]);
+  const R a58 = (v[5] + v[7]) + (v[6] + v[8]);
+  m[0] = v[0] + a14 + a58;
+  m[1] = R(-4) * v[0] - a14 + R(2) * a58;
+  m[2] = R(4) * v[0] - R(2) * a14 + a58;
+  const R d13 = v[1] - v[3], d24 = v[2] - v[4];
+  const R x58 = (v[5] - v[7]) + (v[8] - v[6]);
+  const R y58 = (v[5] - v[7]) + (v[6] - v[8]);
+  m[3] = d13 + x58;
+  m[4] = R(-2) * d13 + x58;
+  m[5] = d24 + y58;
+  m[6] = R(-2) * d24 + y58;
+  m[7] = (v[1] + v[3]) - (v[2] + v[4]);
+  m[8] = (v[5] + v[7]) - (v[6] + v[8]);
+}
+
+// v = M^{-1} m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m
+template <class R>
+__device__ __forceinline__ void d2q9_from_moments(const R (&m)[9], R (&v)[9]) {
+  const R a0 = m[0] * R(1.0 / 9.0), a1 = m[1] * R(1.0 / 36.0), a2 = m[2] * R(1.0 / 36.0);
+  const R a3 = m[3] * R(1.0 / 6.0), a4 = m[4] * R(1.0 / 12.0), a5 = m[5] * R(1.0 / 6.0);
+  const R a6 = m[6] * R(1.0 / 12.0), a7 = m[7] * R(0.25), a8 = m[8] * R(0.25);
+  const R A = a0 - a1 - R(2) * a2, B = a0 + R(2) * a1 + a2;
+  const R X1 = a3 - R(2) * a4, Y1 = a5 - R(2) * a6, X2 = a3 + a4, Y2 = a5 + a6;
+  v[0] = a0 - R(4) * a1 + R(4) * a2;
+  v[1] = A + X1 + a7;
+  v[3] = A - X1 + a7;
+  v[2] = A + Y1 - a7;
+  v[4] = A - Y1 - a7;
+  v[5] = B + X2 + Y2 + a8;
+  v[7] = B - X2 - Y2 + a8;
+  v[6] = B - X2 + Y2 - a8;
+  v[8] = B + X2 - Y2 - a8;
+}
+
+// One D2Q9 node: the same time step as node_update_generic with the moments of the
+// equilibria and sources in closed form (M g_eq, M f_eq, M G and M F evaluated from
+// Eqs. 21-24, 31-32), so that each population set costs one forward and one inverse
+// moment transform.
+template <class R, bool COUPLED, bool SH>
+__device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, const NodeIn<D2Q9, R>& in,
+                                                 R (&g)[9], R (&f)[9], R (&J)[2], NodeOut<D2Q9, R>& out) {
+  const R* q = in.nphi;
+  const R* s = in.npsi;
+  const R phi = q[0];
+  const R rho = p.rho_l + phi * p.drho;
+  const R pc = clamp01(phi);
+  const R a = pc + p.xi, b = (R(1) - pc) + p.xi;
+  const R An = p.lamW * (R(4) * a * b) / ((a + b) * (a + b));
+  // Eqs. 39-40 on D2Q9: 3 w_i c_i = 1/3 (axes), 1/12 (diagonals); 6 w_i = 2/3, 1/6
+  const R gpx = R(1.0 / 3.0) * (q[1] - q[3]) + R(1.0 / 12.0) * ((q[5] - q[7]) + (q[8] - q[6]));
+  const R gpy = R(1.0 / 3.0) * (q[2] - q[4]) + R(1.0 / 12.0) * ((q[5] - q[7]) + (q[6] - q[8]));
+  const R lap = R(2.0 / 3.0) * (((q[1] + q[3]) + (q[2] + q[4])) - R(4) * q[0]) +
+                R(1.0 / 6.0) * (((q[5] + q[7]) + (q[6] + q[8])) - R(4) * q[0]);
+  const R gsx = R(1.0 / 3.0) * (s[1] - s[3]) + R(1.0 / 12.0) * ((s[5] - s[7]) + (s[8] - s[6]));
+  const R gsy = R(1.0 / 3.0) * (s[2] - s[4]) + R(1.0 / 12.0) * ((s[5] - s[7]) + (s[6] - s[8]));
+  const R mu = p.beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - p.kappa * lap;   // Eq. 2
+  const R Fx = mu * gpx, Fy = mu * gpy;                                          // F_s = mu grad phi
+  const R grx = p.drho * gpx, gry = p.drho * gpy;
+  R ux, uy, press = R(0);
+  R fm[9];
+  if constexpr (COUPLED) {
+    d2q9_moments<R>(f, fm);
+    ux = (fm[3] + R(0.5) * Fx) / rho;                                            // Eq. 28
+    uy = (fm[5] + R(0.5) * Fy) / rho;
+    const R P = fm[0] - f[0];
+    const R uu = ux * ux + uy * uy, ug = ux * grx + uy * gry;
+    press = R(0.6) * (P + R(0.5) * ug - R(2.0 / 3.0) * rho * uu);               // Eq. 29
+  } else {
+    ux = in.u[0];
+    uy = in.u[1];
+  }
+  const R Jx = phi * ux, Jy = phi * uy;
+  const R dJx = Jx - J[0], dJy = Jy - J[1];
+  J[0] = Jx;
+  J[1] = Jy;
+  const R inv = R(1) / sqrt(gsx * gsx + gsy * gsy + p.eps2);
+  const R Vx = R(3) * dJx + An * (gsx * inv), Vy = R(3) * dJy + An * (gsy * inv);  // Eq. 32: G_i = w_i c_i . V
+  // g (Eq. 33): equilibrium moments (phi, -4 phi + 2H, 4 phi - 3H, Jx, -Jx, Jy, -Jy, 0, 0), H = mu + lambda phi;
+  // in deviation variables (subtract M r phi) they are (0, 2 mu, -3 mu, Jx, -Jx, Jy, -Jy, 0, 0).
+  // source moments (0, 0, 0, Vx/3, -Vx/3, Vy/3, -Vy/3, 0, 0).
+  {
+    R m[9];
+    d2q9_moments<R>(g, m);
+    R eq[9];
+    if constexpr (SH) {
+      eq[0] = m[0];
+      eq[1] = R(2) * mu;
+      eq[2] = R(-3) * mu;
+    } else {
+      const R H = mu + p.lam * phi;
+      eq[0] = phi;
+      eq[1] = R(-4) * phi + R(2) * H;
+      eq[2] = R(4) * phi - R(3) * H;
+    }
+    eq[3] = Jx; eq[4] = -Jx; eq[5] = Jy; eq[6] = -Jy; eq[7] = R(0); eq[8] = R(0);
+    const R Gx = Vx * R(1.0 / 3.0), Gy = Vy * R(1.0 / 3.0);
+    const R src[9] = {R(0), R(0), R(0), Gx, -Gx, Gy, -Gy, R(0), R(0)};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (SH && k == 0) continue;
+      m[k] = m[k] - p.sgr[k] * (m[k] - eq[k]) + (R(1) - R(0.5) * p.sgr[k]) * src[k];
+    }
+    d2q9_from_moments<R>(m, g);
+  }
+  // f (Eq. 25): equilibrium moments (0, 6p + 3 rho u.u, -9p - 3 rho u.u, rho ux, -rho ux, rho uy,
+  // -rho uy, rho (ux^2 - uy^2), rho ux uy); forcing moments (u.grad rho, 0, -u.grad rho, Fx, -Fx,
+  // Fy, -Fy, 2/3 (ux gx - uy gy), 1/3 (ux gy + uy gx))
+  if constexpr (COUPLED) {
+    const R uu = ux * ux + uy * uy, ug = ux * grx + uy * gry;
+    const R eq[9] = {R(0), R(6) * press + R(3) * rho * uu, R(-9) * press - R(3) * rho * uu,
+                     rho * ux, -rho * ux, rho * uy, -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy};
+    const R src[9] = {ug, R(0), -ug, Fx, -Fx, Fy, -Fy, R(2.0 / 3.0) * (ux * grx - uy * gry),
+                      R(1.0 / 3.0) * (ux * gry + uy * grx)};
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      fm[k] = fm[k] - p.sfr[k] * (fm[k] - eq[k]) + (R(1) - R(0.5) * p.sfr[k]) * src[k];
+    d2q9_from_moments<R>(fm, f);
+  }
+  out.rho = rho;
+  out.mu = mu;
+  out.press = press;
+  out.u[0] = ux;
+  out.u[1] = uy;
+}
+
+template <class L, class R, bool COUPLED, bool SH = false>
+__device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const NodeIn<L, R>& in, R (&g)[L::Q],
+                                            R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
+  if constexpr (L::Q == 9) node_update_d2q9<R, COUPLED, SH>(p, in, g, f, J, out);
+  else node_update_generic<L, R, COUPLED, SH>(p, in, g, f, J, out);
 }
 
 // Velocity of the prescribed single vortex, Eqs. 43-44, at node (x, y) and step t.
