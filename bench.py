@@ -56,10 +56,10 @@ def workload(name: str, storage: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_case(p, phi0, u0, steps: int, warmup: int):
+def time_case(p, phi0, u0, steps: int, warmup: int, tile=None):
     import torch
     from paper_2505_10899_amd import vclb
-    case = vclb.Case(p).init(phi0, u0)
+    case = vclb.Case(p, tile=tile).init(phi0, u0)
     case.step(warmup)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
@@ -121,6 +121,10 @@ def main(argv=None):
     ap.add_argument("--workload", default="two_droplets_x32")
     ap.add_argument("--storages", default="fp32,fp64,fp16s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default=None, help="bx,ty[,by3]: launch shape of the fused step")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (a known-size reference "
+                         "for the HBM byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,7 +139,8 @@ def main(argv=None):
         p, phi0, u0, meta = workload(a.workload, st)
         print(f"[bench] {a.workload} {st}: {p.n_nodes} nodes, {a.warmup} warmup + {a.steps} timed steps",
               file=sys.stderr, flush=True)
-        r = time_case(p, phi0, u0, a.steps, a.warmup)
+        tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
+        r = time_case(p, phi0, u0, a.steps, a.warmup, tile)
         coupled = p.mode == "coupled"
         bpn = BYTES_PER_NODE[(p.lattice, coupled)][st]
         ms = r["total_ms"] / a.steps
@@ -163,6 +168,13 @@ def main(argv=None):
                           "speedup_vs_fp64": (round(v["mlups"] / res["fp64"]["mlups"], 3) if "fp64" in res else None)}
                      for st, v in res.items()},
     }
+    if a.copy_probe:
+        nbytes = a.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
     if not a.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

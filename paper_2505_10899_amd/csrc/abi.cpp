@@ -111,7 +111,7 @@ int validate(const vclb_params* p) {
 }
 
 struct Layout {
-  size_t pop[2][2], J, phis[2], partials, hist, cur, tmp_phi, tmp_psi, total;
+  size_t pop[2][2], J, phis[2], partials[2], hist, cur, tmp_phi, tmp_psi, total;
   long partial_blocks;
 };
 
@@ -137,7 +137,7 @@ Layout layout_for(const vclb_params& p) {
   // every launch shape uses at least 64 nodes per workgroup, plus one partial row per
   // (y, z) line for tiles that are ragged in x
   L.partial_blocks = long(n / 64) + long(p.ny) * p.nz + 64;
-  L.partials = take(size_t(L.partial_blocks) * nl * 12 * sizeof(double));
+  for (int b = 0; b < 2; ++b) L.partials[b] = take(size_t(L.partial_blocks) * nl * 12 * sizeof(double));
   L.hist = take(size_t(vclb::kHistory) * nl * vclb::kObsFields * sizeof(double));
   L.cur = take(size_t(nl) * vclb::kObsFields * sizeof(double));
   L.tmp_phi = take(n * rb);
@@ -168,6 +168,11 @@ struct vclb_case {
   int64_t t_host = 0;
   bool inited = false;
   std::vector<int64_t> recorded;   // step recorded in each history slot (-1: none)
+  // reductions of a fused step whose second pass has not run yet: the next fused step
+  // folds them in its first workgroup, anything that reads results flushes them first
+  bool pending = false;
+  int pend_nb = 0, pend_buf = 0;
+  int64_t pend_step = 0;
 };
 
 namespace {
@@ -203,7 +208,18 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   for (int b = 0; b < 2; ++b)
     d.phis[b] = c.lay.phis[b] == SIZE_MAX ? nullptr : reinterpret_cast<float*>(c.ws + c.lay.phis[b]);
   d.t = long(c.t_host);
-  d.partials = reinterpret_cast<double*>(c.ws + c.lay.partials);
+  d.part_w = reinterpret_cast<double*>(c.ws + c.lay.partials[c.t_host & 1]);
+  d.part_r = nullptr;
+  d.pend_nb = 0;
+  d.pend_dest = nullptr;
+  d.pend_step = 0;
+  if (c.pending) {
+    d.part_r = reinterpret_cast<const double*>(c.ws + c.lay.partials[c.pend_buf]);
+    d.pend_nb = c.pend_nb;
+    d.pend_dest = reinterpret_cast<double*>(c.ws + c.lay.hist) +
+                  size_t(c.pend_step % vclb::kHistory) * std::max(1, p.nlabels) * vclb::kObsFields;
+    d.pend_step = long(c.pend_step);
+  }
   d.hist = reinterpret_cast<double*>(c.ws + c.lay.hist);
   d.cur = reinterpret_cast<double*>(c.ws + c.lay.cur);
   d.tmp_phi = reinterpret_cast<R*>(c.ws + c.lay.tmp_phi);
@@ -266,6 +282,17 @@ struct DevTraits<vclb::DevCase<L_, St_>> {
   using L = L_;
   using St = St_;
 };
+
+// run the second reduction pass of a pending fused step now
+int flush_pending(vclb_case* c, hipStream_t s) {
+  if (!c->pending) return VCLB_OK;
+  int rc = dispatch(*c, [&](auto dc, auto) {
+    using DC = decltype(dc);
+    return vclb::launch_finalize<typename DevTraits<DC>::L, typename DevTraits<DC>::St>(dc, s);
+  });
+  c->pending = false;
+  return rc ? fail(VCLB_EHIP, "finalize launch failed") : VCLB_OK;
+}
 
 vclb::Tile default_tile(const vclb_params& p) {
   vclb::Tile t;
@@ -435,6 +462,7 @@ int vclb_case_init(vclb_case* c, const double* phi0, const double* u0, int ptr_k
   if (rc) return fail(VCLB_EHIP, "init kernel launch failed");
   c->t_host = 0;
   std::fill(c->recorded.begin(), c->recorded.end(), -1);
+  c->pending = false;
   c->inited = true;
   return VCLB_OK;
 }
@@ -477,6 +505,7 @@ int vclb_case_set_state(vclb_case* c, const double* g, const double* f, const do
   if (e != hipSuccess) return hip_fail(e, "set_state");
   c->t_host = t;
   std::fill(c->recorded.begin(), c->recorded.end(), -1);
+  c->pending = false;
   c->inited = true;
   return VCLB_OK;
 }
@@ -526,6 +555,10 @@ static int do_steps(vclb_case* c, int64_t nsteps, void* stream, bool fused) {
                             : long((size_t(c->p.nx) * c->p.ny * c->p.nz + 255) / 256);
   if (blocks > c->lay.partial_blocks) return fail(VCLB_EINVAL, "launch shape exceeds the reduction buffer");
   hipStream_t s = as_stream(stream);
+  if (!fused) {
+    int rc = flush_pending(c, s);
+    if (rc) return rc;
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
     const int64_t t = c->t_host;
     const int reduce = (c->reduce_every > 0 && t % c->reduce_every == 0) ? 1 : 0;
@@ -538,6 +571,11 @@ static int do_steps(vclb_case* c, int64_t nsteps, void* stream, bool fused) {
                    : vclb::launch_step_plain<L, St, C>(dc, reduce, s);
     });
     if (rc) return fail(VCLB_EHIP, std::string("step kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+    // the fused kernel has folded the previous pending reductions; its own are pending
+    c->pending = fused && reduce;
+    c->pend_nb = int(blocks);
+    c->pend_buf = int(t & 1);
+    c->pend_step = t;
     if (reduce) c->recorded[size_t(t % vclb::kHistory)] = t;
     c->t_host = t + 1;
   }
@@ -560,6 +598,7 @@ int vclb_observe(vclb_case* c, uint32_t mask, double* out, int ptr_kind, void* s
   if (mask == 0 || (mask & ~0x3Fu)) return fail(VCLB_EINVAL, "bad field mask");
   if (ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
   hipStream_t s = as_stream(stream);
+  if (int rc0 = flush_pending(c, s)) return rc0;
   const size_t n = size_t(c->p.nx) * c->p.ny * c->p.nz;
   const int D = lattice_d(c->p.lattice);
   size_t count = 0;
@@ -606,6 +645,7 @@ int vclb_reduce(vclb_case* c, vclb_obs* out, void* stream) {
   if (!c || !out) return fail(VCLB_EINVAL, "NULL argument");
   if (!c->inited) return fail(VCLB_ESTATE, "reduce before init");
   hipStream_t s = as_stream(stream);
+  if (int rc0 = flush_pending(c, s)) return rc0;
   int rc = dispatch(*c, [&](auto dc, auto) {
     using DC = decltype(dc);
     using L = typename DevTraits<DC>::L;
@@ -630,6 +670,7 @@ int vclb_history(vclb_case* c, int64_t t_first, int32_t count, vclb_obs* out, vo
   for (int64_t t = t_first; t < t_first + count; ++t)
     if (c->recorded[size_t(t % vclb::kHistory)] != t) return fail(VCLB_ESTATE, "step not in the history");
   hipStream_t s = as_stream(stream);
+  if (int rc0 = flush_pending(c, s)) return rc0;
   const int nl = std::max(1, c->p.nlabels);
   const size_t row = size_t(nl) * vclb::kObsFields;
   std::vector<double> all(size_t(vclb::kHistory) * row);
@@ -736,6 +777,7 @@ int vclb_state_load(vclb_case* c, const void* host_buf, size_t bytes, void* stre
   HIP_TRY(hipStreamSynchronize(s));
   c->t_host = h.step;
   std::fill(c->recorded.begin(), c->recorded.end(), -1);
+  c->pending = false;
   c->inited = true;
   return VCLB_OK;
 }

@@ -26,7 +26,11 @@ struct DevCase {
   R* J;                         // previous phi u, D * n
   float* phis[2];               // FP16S: phi of the node that wrote each buffer entry
   long t;                       // step index of the state this launch reads
-  double* partials;             // [block][label][kObsFields]
+  double* part_w;               // this launch's workgroup partials, [label * 12 + field][workgroup]
+  const double* part_r;         // partials of an earlier launch still to be summed (pend_nb > 0)
+  int pend_nb;                  // workgroups of that launch, 0 if none pending
+  double* pend_dest;            // where its sums go: [label][kObsFields]
+  long pend_step;               // the step it belongs to
   double* hist;                 // [kHistory][label][kObsFields]
   double* cur;                  // [label][kObsFields] reductions of the current state
   R* tmp_phi;                   // scratch N: phi (plain path and observe)
@@ -191,7 +195,8 @@ __device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool r
 #pragma unroll
     for (int f = 0; f < 12; ++f) v[k * 12 + f] = a.v[k][f];
   const double s = block_sum_fields<NF>(v, nf, red);
-  if (int(threadIdx.x) < nf) c.partials[long(blockIdx.x) * nf + threadIdx.x] = s;
+  // field-major [field][workgroup]: the second pass reads each field coalesced
+  if (int(threadIdx.x) < nf) c.part_w[long(threadIdx.x) * gridDim.x + blockIdx.x] = s;
 }
 
 // store one node's post-collision state (with the moving-wall term on f for the
@@ -235,6 +240,31 @@ __device__ __forceinline__ void prescribed(const DevCase<L, St>& c, int x, int y
     in.u[0] = ux;
     in.u[1] = uy;
   }
+}
+
+// Second pass of the volume reductions: sum the pending partials of an earlier launch
+// in a fixed order (deterministic) into c.pend_dest.  Run by one whole workgroup.
+template <class Case>
+__device__ __forceinline__ void fold_pending(const Case& c) {
+  constexpr int NF = kMaxLabels * 12;
+  __shared__ double red[16 * NF];
+  const int nf = c.nl * 12;
+  const int nb = c.pend_nb;
+  double v[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      if (f < nf) v[f] += c.part_r[long(f) * nb + b];
+  }
+  const double s = block_sum_fields<NF>(v, nf, red);
+  if (int(threadIdx.x) < nf) {
+    const int k = threadIdx.x / 12, f = threadIdx.x % 12;
+    c.pend_dest[k * kObsFields + f] = s;
+    if (f == 0) c.pend_dest[k * kObsFields + 12] = double(c.pend_step);
+  }
+  __syncthreads();
 }
 
 // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs, so

@@ -311,8 +311,11 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4) k_st
   R* spsi = sphi + 4 * W;
   const int nx = c.nx, ny = c.ny, n = int(c.n);
   const int lane = threadIdx.x;
+  // tiles of one row band (all strips) are consecutive, so that an XCD runs the strips
+  // whose halo columns it shares (and the next band, whose halo rows it shares)
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int strip = tile / nseg, seg = tile - strip * nseg;
+  const int nstrips = gridDim.x / nseg;
+  const int seg = tile / nstrips, strip = tile - seg * nstrips;
   const int x0 = strip * BX;
   const int xg = x0 + lane;
   const bool active_x = xg < nx;
@@ -369,6 +372,7 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4) k_st
   double dxl[kMaxLabels];
 #pragma unroll
   for (int k = 0; k < kMaxLabels; ++k) dxl[k] = min_image(double(xw) - c.cen[k][0], nx, true);
+  if (blockIdx.x == 0 && c.pend_nb > 0) fold_pending(c);
   Acc2 acc;
 #pragma unroll
   for (int k = 0; k < kMaxLabels; ++k) {
@@ -379,6 +383,13 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4) k_st
   phi_row(y0 - 1, gnext);
   phi_row(y0, gcur);
   for (int y = y0; y < y1; ++y) {
+    // this row's f and previous phi u are requested together with the next row's g,
+    // so that one memory round trip per row covers both
+    const int nn = xw + nx * y;
+    R f[Q], J[2];
+    if constexpr (COUPLED) pull9<St>(fsrc, phis, col, row3(y), f, nullptr);
+    J[0] = c.J[nn];
+    J[1] = c.J[n + nn];
     phi_row(y + 1, gnext);
     __syncthreads();
     if (active_x) {
@@ -395,11 +406,6 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4) k_st
         in.u[0] = ux;
         in.u[1] = uy;
       }
-      const int nn = xw + nx * y;
-      R f[Q], J[2];
-      if constexpr (COUPLED) pull9<St>(fsrc, phis, col, row3(y), f, nullptr);
-      J[0] = c.J[nn];
-      J[1] = c.J[n + nn];
       NodeOut<L, R> out;
       node_update<L, R, COUPLED, St::shifted>(c.np, in, gcur, f, J, out);
 #pragma unroll
@@ -464,33 +470,27 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4) k_st
 }
 
 // ---------------------------------------------------------------- second reduction pass
-// Sum the workgroup partials of one launch in a fixed order into dest[label][kObsFields].
+// Stand-alone second pass (the fused steps instead fold the previous launch's partials
+// in their first workgroup).
 template <class L, class St>
-__global__ void __launch_bounds__(256) k_finalize(DevCase<L, St> c, int nblocks, double* __restrict__ dest,
-                                                  long step) {
-  constexpr int NF = kMaxLabels * 12;
-  __shared__ double red[4 * NF];
-  const int nf = c.nl * 12;
-  double v[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) v[f] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-      if (f < nf) v[f] += c.partials[long(b) * nf + f];
-  }
-  const double s = block_sum_fields<NF>(v, nf, red);
-  if (int(threadIdx.x) < nf) {
-    const int k = threadIdx.x / 12, f = threadIdx.x % 12;
-    dest[k * kObsFields + f] = s;
-    if (f == 0) dest[k * kObsFields + 12] = double(step);
-  }
+__global__ void __launch_bounds__(256) k_finalize(DevCase<L, St> c) {
+  fold_pending(c);
 }
 
 template <class L, class St>
-static int finalize(const DevCase<L, St>& c, int nblocks, double* dest, hipStream_t s) {
-  hipLaunchKernelGGL((k_finalize<L, St>), dim3(1), dim3(256), 0, s, c, nblocks, dest, c.t);
-  return 0;
+int launch_finalize(const DevCase<L, St>& c, hipStream_t s) {
+  hipLaunchKernelGGL((k_finalize<L, St>), dim3(1), dim3(256), 0, s, c);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// the pending pass that reads this launch's own partials
+template <class L, class St>
+static DevCase<L, St> self_pending(DevCase<L, St> c, int nblocks, double* dest) {
+  c.part_r = c.part_w;
+  c.pend_nb = nblocks;
+  c.pend_dest = dest;
+  c.pend_step = c.t;
+  return c;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -506,7 +506,7 @@ int launch_step_plain(const DevCase<L, St>& c, int reduce, hipStream_t s) {
   const unsigned nb = unsigned((c.n + 255) / 256);
   hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_collide_plain<L, St, COUPLED>), dim3(nb), dim3(256), 0, s, c, reduce);
-  if (reduce) finalize(c, int(nb), c.hist + (c.t % kHistory) * c.nl * kObsFields, s);
+  if (reduce) launch_finalize(self_pending(c, int(nb), c.hist + (c.t % kHistory) * c.nl * kObsFields), s);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -518,12 +518,9 @@ int launch_step_fused(const DevCase<L, St>& c, const Tile& tile, int reduce, hip
     const size_t lds = size_t(2) * 4 * (tile.bx + 2) * sizeof(typename St::R);
     hipLaunchKernelGGL((k_step2d<St, COUPLED>), dim3(nstrips * nseg), dim3(tile.bx), lds, s, c, tile.ty,
                        nseg, reduce);
-    if (reduce) finalize(c, nstrips * nseg, c.hist + (c.t % kHistory) * c.nl * kObsFields, s);
     return hipGetLastError() == hipSuccess ? 0 : -3;
   } else {
-    const int rc = launch_step3d<St>(c, tile, reduce, s);
-    if (reduce) finalize(c, int(fused_blocks(3, c.nx, c.ny, c.nz, tile)), c.hist + (c.t % kHistory) * c.nl * kObsFields, s);
-    return rc;
+    return launch_step3d<St>(c, tile, reduce, s);
   }
 }
 
@@ -540,7 +537,7 @@ int launch_reduce_state(const DevCase<L, St>& c, hipStream_t s) {
   const unsigned nb = unsigned((c.n + 255) / 256);
   hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
   hipLaunchKernelGGL((k_reduce_state<L, St>), dim3(nb), dim3(256), 0, s, c);
-  finalize(c, int(nb), c.cur, s);
+  launch_finalize(self_pending(c, int(nb), c.cur), s);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -580,6 +577,12 @@ VCLB_INSTANTIATE(D3Q19, StoreF64, true)
 VCLB_INSTANTIATE(D3Q19, StoreF32, true)
 VCLB_INSTANTIATE(D3Q19, StoreF16S, true)
 template int launch_reduce_state<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
+template int launch_finalize<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
+template int launch_finalize<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
+template int launch_finalize<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);
+template int launch_finalize<D3Q19, StoreF64>(const DevCase<D3Q19, StoreF64>&, hipStream_t);
+template int launch_finalize<D3Q19, StoreF32>(const DevCase<D3Q19, StoreF32>&, hipStream_t);
+template int launch_finalize<D3Q19, StoreF16S>(const DevCase<D3Q19, StoreF16S>&, hipStream_t);
 template int launch_reduce_state<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
 template int launch_reduce_state<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);
 template int launch_reduce_state<D3Q19, StoreF64>(const DevCase<D3Q19, StoreF64>&, hipStream_t);

@@ -64,6 +64,7 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       spsi[s + py * PW + px] = psi_of<R>(hp, c.np.W4, c.np.xi);
     }
   };
+  if (blockIdx.x == 0 && c.pend_nb > 0) fold_pending(c);
   Acc acc;
   acc.zero();
   R gcur[Q], gnext[Q];

@@ -29,6 +29,8 @@ int launch_set_state(const DevCase<L, St>& c, const double* g, const double* f, 
                      hipStream_t s);
 template <class L, class St, bool COUPLED>
 int launch_get_state(const DevCase<L, St>& c, double* g, double* f, double* J, hipStream_t s);
+template <class L, class St>
+int launch_finalize(const DevCase<L, St>& c, hipStream_t s);
 template <class St>
 int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hipStream_t s);
 
