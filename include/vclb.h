@@ -200,6 +200,43 @@ int vclb_state_bytes(const vclb_case* c, size_t* bytes);
 int vclb_state_save(vclb_case* c, void* host_buf, size_t bytes, void* stream);
 int vclb_state_load(vclb_case* c, const void* host_buf, size_t bytes, void* stream);
 
+/* ---------------------------------------------------------------- batches of cases */
+/* Many independent coupled D2Q9 cases of uneven sizes (one storage precision), advanced
+   together: each step is one work-list kernel over the tiles of every case, and a call
+   of vclb_batch_step captures its steps in one hipGraph replayed as one launch.  The
+   batch owns one device allocation holding every case. */
+typedef struct vclb_batch vclb_batch;
+
+/* Validate every case (all VCLB_D2Q9, VCLB_COUPLED, one storage, nlabels <= 1) and
+   allocate the batch. */
+int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out);
+void vclb_batch_destroy(vclb_batch* b);
+
+/* Handle of case k, owned by the batch: vclb_case_init / set_state / observe / reduce /
+   history / get_state work on it.  Do not destroy it or call vclb_step on it. */
+int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out);
+
+/* Total nodes of all cases. */
+int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
+
+/* Tile of the batched step: bx in {64, 128, 256} columns, ty >= 8 rows per work item.
+   get_tile also returns the number of resident workgroups launched per step. */
+int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty);
+int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks);
+
+/* Record each case's volume reductions every `every` steps (0: off; default 1). */
+int vclb_batch_set_reduce_every(vclb_batch* b, int32_t every);
+
+/* Advance every case by nsteps (all cases must be initialised and at the same step).
+   use_graph != 0: the launches are captured into one hipGraph on a library stream
+   ordered after `stream`.  Asynchronous with respect to the host. */
+int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stream);
+
+/* Pick the batched tile by timing `steps` steps of every candidate on the current state
+   (saved and restored), or take it from the JSON-lines file cache_path when that holds
+   an entry for this batch; a measured choice is appended to cache_path (NULL: no file). */
+int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -779,6 +781,408 @@ int vclb_state_load(vclb_case* c, const void* host_buf, size_t bytes, void* stre
   std::fill(c->recorded.begin(), c->recorded.end(), -1);
   c->pending = false;
   c->inited = true;
+  return VCLB_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ batches
+struct vclb_batch {
+  int n = 0;
+  int storage = 0;
+  std::vector<vclb_case*> cases;
+  char* ws = nullptr;
+  size_t dcase_stride = 0;            // bytes per DevCase in the device table
+  void* d_cases = nullptr;
+  int4* d_items = nullptr;
+  int2* d_case_items = nullptr;
+  double* part[2] = {nullptr, nullptr};
+  size_t items_cap = 0;
+  std::vector<int4> items;
+  std::vector<int2> case_items;
+  int bx = 128, ty = 32, blocks = 0;
+  int reduce_every = 1;
+  int64_t nodes = 0;
+  bool pend = false;
+  int pend_buf = 0;
+  int64_t pend_step = 0;
+  hipStream_t own = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+template <class Fn>
+int dispatch_storage(int storage, Fn&& fn) {
+  switch (storage) {
+    case VCLB_FP64: return fn(vclb::StoreF64{});
+    case VCLB_FP32: return fn(vclb::StoreF32{});
+    default: return fn(vclb::StoreF16S{});
+  }
+}
+
+// work items of a tile shape: per case, bands of ty rows, x strips of bx columns fastest
+void build_items(vclb_batch* b, int bx, int ty, std::vector<int4>& items, std::vector<int2>& ci) {
+  items.clear();
+  ci.assign(size_t(b->n), int2{0, 0});
+  for (int k = 0; k < b->n; ++k) {
+    const vclb_params& p = b->cases[size_t(k)]->p;
+    const int first = int(items.size());
+    for (int y0 = 0; y0 < p.ny; y0 += ty)
+      for (int x0 = 0; x0 < p.nx; x0 += bx) items.push_back(int4{k, x0, y0, std::min(y0 + ty, p.ny)});
+    ci[size_t(k)] = int2{first, int(items.size()) - first};
+  }
+}
+
+int batch_set_tile(vclb_batch* b, int bx, int ty) {
+  if (bx < 64 || bx > 256 || bx % 64 != 0 || ty < 8) return fail(VCLB_EINVAL, "bad batch tile (bx in 64..256, multiple of 64; ty >= 8)");
+  std::vector<int4> items;
+  std::vector<int2> ci;
+  build_items(b, bx, ty, items, ci);
+  if (items.size() > b->items_cap) return fail(VCLB_EINVAL, "too many work items");
+  HIP_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_case_items, ci.data(), ci.size() * sizeof(int2), hipMemcpyHostToDevice));
+  int per_cu = dispatch_storage(b->storage, [&](auto st) { return vclb::batch_max_blocks_per_cu<decltype(st)>(bx); });
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (per_cu < 1) per_cu = 1;
+  b->blocks = int(std::min<long>(long(items.size()), long(per_cu) * ncu));
+  b->bx = bx;
+  b->ty = ty;
+  b->items = std::move(items);
+  b->case_items = std::move(ci);
+  return VCLB_OK;
+}
+
+vclb::BatchArgs batch_args(const vclb_batch* b, int64_t t, int reduce) {
+  vclb::BatchArgs a{};
+  a.items = b->d_items;
+  a.nitems = int(b->items.size());
+  a.case_items = b->d_case_items;
+  a.ncases = b->n;
+  a.part_w = b->part[t & 1];
+  a.part_r = b->part[b->pend_buf];
+  a.pend = b->pend ? 1 : 0;
+  a.pend_step = long(b->pend_step);
+  a.t = long(t);
+  a.reduce = reduce;
+  return a;
+}
+
+// enqueue nsteps batched steps (and the closing fold) on stream s
+int batch_enqueue(vclb_batch* b, int64_t nsteps, bool reduce_on, hipStream_t s) {
+  const int64_t t0 = b->cases[0]->t_host;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t t = t0 + k;
+    const int reduce = (reduce_on && b->reduce_every > 0 && t % b->reduce_every == 0) ? 1 : 0;
+    const vclb::BatchArgs a = batch_args(b, t, reduce);
+    int rc = dispatch_storage(b->storage, [&](auto st) {
+      return vclb::launch_batch_step<decltype(st)>(b->d_cases, a, b->blocks, b->bx, s);
+    });
+    if (rc) return fail(VCLB_EHIP, "batched step launch failed");
+    b->pend = reduce != 0;
+    b->pend_buf = int(t & 1);
+    b->pend_step = t;
+  }
+  if (b->pend) {
+    const vclb::BatchArgs a = batch_args(b, t0 + nsteps, 0);
+    int rc = dispatch_storage(b->storage, [&](auto st) { return vclb::launch_batch_fold<decltype(st)>(b->d_cases, a, s); });
+    if (rc) return fail(VCLB_EHIP, "batched fold launch failed");
+    b->pend = false;
+  }
+  return VCLB_OK;
+}
+
+void batch_release_graph(vclb_batch* b) {
+  if (b->gexec) {
+    (void)hipEventSynchronize(b->ev_out);
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out) {
+  if (!cases || !out || ncases < 1) return fail(VCLB_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  for (int k = 0; k < ncases; ++k) {
+    int rc = validate(&cases[k]);
+    if (rc) return fail(rc, "case " + std::to_string(k) + ": " + g_last_error);
+    if (cases[k].lattice != VCLB_D2Q9 || cases[k].mode != VCLB_COUPLED)
+      return fail(VCLB_EINVAL, "batches hold coupled D2Q9 cases");
+    if (cases[k].storage != cases[0].storage) return fail(VCLB_EINVAL, "every case of a batch has one storage");
+    if (cases[k].nlabels > 1) return fail(VCLB_EINVAL, "batched cases have one observation label");
+  }
+  vclb_batch* b = new (std::nothrow) vclb_batch();
+  if (!b) return fail(VCLB_ENOMEM, "host allocation");
+  b->n = ncases;
+  b->storage = cases[0].storage;
+  // the kernel indexes the table as an array of DevCase: the stride is exactly its size
+  b->dcase_stride = size_t(dispatch_storage(b->storage, [&](auto st) {
+    return int(sizeof(vclb::DevCase<vclb::D2Q9, decltype(st)>));
+  }));
+  size_t total = 0;
+  std::vector<size_t> off(static_cast<size_t>(ncases), 0);
+  size_t cap = 0;
+  for (int k = 0; k < ncases; ++k) {
+    off[size_t(k)] = total;
+    total += align_up(layout_for(cases[k]).total);
+    cap += size_t((cases[k].nx + 63) / 64) * size_t((cases[k].ny + 7) / 8);
+    b->nodes += int64_t(cases[k].nx) * cases[k].ny;
+  }
+  const size_t o_cases = total;
+  total += align_up(b->dcase_stride * size_t(ncases));
+  const size_t o_items = total;
+  total += align_up(cap * sizeof(int4));
+  const size_t o_ci = total;
+  total += align_up(size_t(ncases) * sizeof(int2));
+  size_t o_part[2];
+  for (int i = 0; i < 2; ++i) {
+    o_part[i] = total;
+    total += align_up(cap * 12 * sizeof(double));
+  }
+  void* m = nullptr;
+  hipError_t e = hipMalloc(&m, total);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(e == hipErrorOutOfMemory ? VCLB_ENOMEM : VCLB_EHIP, "hipMalloc of the batch workspace failed");
+  }
+  b->ws = static_cast<char*>(m);
+  b->items_cap = cap;
+  b->d_cases = b->ws + o_cases;
+  b->d_items = reinterpret_cast<int4*>(b->ws + o_items);
+  b->d_case_items = reinterpret_cast<int2*>(b->ws + o_ci);
+  for (int i = 0; i < 2; ++i) b->part[i] = reinterpret_cast<double*>(b->ws + o_part[i]);
+  for (int k = 0; k < ncases; ++k) {
+    vclb_case* c = nullptr;
+    int rc = vclb_case_create(&cases[k], b->ws + off[size_t(k)], layout_for(cases[k]).total, &c);
+    if (rc) {
+      vclb_batch_destroy(b);
+      return rc;
+    }
+    b->cases.push_back(c);
+  }
+  // device table of per-case descriptors (pointers and constants; the step index and the
+  // partial-sum buffers are batch arguments)
+  std::vector<char> table(b->dcase_stride * size_t(ncases));
+  const int layout_rc = dispatch_storage(b->storage, [&](auto st) {
+    using St = decltype(st);
+    for (int k = 0; k < ncases; ++k) {
+      auto d = make_dev<vclb::D2Q9, St>(*b->cases[size_t(k)]);
+      std::memcpy(table.data() + b->dcase_stride * size_t(k), &d, sizeof(d));
+    }
+    // the device reads entry k as cases[k]: check that indexing the table that way finds
+    // each case's own buffers
+    const auto* arr = reinterpret_cast<const vclb::DevCase<vclb::D2Q9, St>*>(table.data());
+    for (int k = 0; k < ncases; ++k)
+      if (static_cast<const void*>(arr[k].pop[0][0]) != b->cases[size_t(k)]->ws + b->cases[size_t(k)]->lay.pop[0][0])
+        return -1;
+    return 0;
+  });
+  if (layout_rc) {
+    vclb_batch_destroy(b);
+    return fail(VCLB_EINVAL, "internal: case table layout");
+  }
+  e = hipMemcpy(b->d_cases, table.data(), table.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    vclb_batch_destroy(b);
+    return hip_fail(e, "batch set-up");
+  }
+  int rc = batch_set_tile(b, 128, 32);
+  if (rc) {
+    vclb_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return VCLB_OK;
+}
+
+void vclb_batch_destroy(vclb_batch* b) {
+  if (!b) return;
+  batch_release_graph(b);
+  for (vclb_case* c : b->cases) vclb_case_destroy(c);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->own) (void)hipStreamDestroy(b->own);
+  if (b->ws) (void)hipFree(b->ws);
+  delete b;
+}
+
+int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out) {
+  if (!b || !out || k < 0 || k >= b->n) return fail(VCLB_EINVAL, "bad case index");
+  *out = b->cases[size_t(k)];
+  return VCLB_OK;
+}
+
+int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes) {
+  if (!b || !nodes) return fail(VCLB_EINVAL, "NULL argument");
+  *nodes = b->nodes;
+  return VCLB_OK;
+}
+
+int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty) {
+  if (!b) return fail(VCLB_EINVAL, "batch is NULL");
+  batch_release_graph(b);
+  return batch_set_tile(b, bx, ty);
+}
+
+int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks) {
+  if (!b || !bx || !ty || !blocks) return fail(VCLB_EINVAL, "NULL argument");
+  *bx = b->bx;
+  *ty = b->ty;
+  *blocks = b->blocks;
+  return VCLB_OK;
+}
+
+int vclb_batch_set_reduce_every(vclb_batch* b, int32_t every) {
+  if (!b || every < 0) return fail(VCLB_EINVAL, "bad reduce_every");
+  b->reduce_every = every;
+  return VCLB_OK;
+}
+
+int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stream) {
+  if (!b || nsteps < 0) return fail(VCLB_EINVAL, "bad batch step arguments");
+  const int64_t t0 = b->cases[0]->t_host;
+  for (vclb_case* c : b->cases) {
+    if (!c->inited) return fail(VCLB_ESTATE, "batch step before every case is initialised");
+    if (c->t_host != t0) return fail(VCLB_ESTATE, "batched cases are at different steps");
+    if (c->pending) return fail(VCLB_ESTATE, "a case has pending single-case reductions");
+  }
+  if (nsteps == 0) return VCLB_OK;
+  hipStream_t s = as_stream(stream);
+  batch_release_graph(b);
+  int rc;
+  if (use_graph) {
+    // capture on the library's own stream, ordered after the caller's stream by events
+    HIP_TRY(hipEventRecord(b->ev_in, s));
+    HIP_TRY(hipStreamWaitEvent(b->own, b->ev_in, 0));
+    HIP_TRY(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+    rc = batch_enqueue(b, nsteps, true, b->own);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->own, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    HIP_TRY(hipGraphLaunch(b->gexec, b->own));
+    HIP_TRY(hipEventRecord(b->ev_out, b->own));
+    HIP_TRY(hipStreamWaitEvent(s, b->ev_out, 0));
+  } else {
+    rc = batch_enqueue(b, nsteps, true, s);
+    if (rc) return rc;
+  }
+  for (vclb_case* c : b->cases) {
+    for (int64_t t = t0; t < t0 + nsteps; ++t)
+      if (b->reduce_every > 0 && t % b->reduce_every == 0) c->recorded[size_t(t % vclb::kHistory)] = t;
+    c->t_host = t0 + nsteps;
+  }
+  return VCLB_OK;
+}
+
+int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, void* stream) {
+  if (!b || steps < 1) return fail(VCLB_EINVAL, "bad autotune arguments");
+  for (vclb_case* c : b->cases)
+    if (!c->inited) return fail(VCLB_ESTATE, "autotune needs initialised cases (their state is restored)");
+  // key: storage and every case's shape and boundary
+  std::string desc = "s" + std::to_string(b->storage);
+  for (vclb_case* c : b->cases)
+    desc += ":" + std::to_string(c->p.nx) + "x" + std::to_string(c->p.ny) + (c->p.bc_y == VCLB_WALL ? "w" : "p");
+  char key[32];
+  std::snprintf(key, sizeof(key), "%016llx", static_cast<unsigned long long>(fnv1a(desc.data(), desc.size())));
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[4096];
+      int bx = 0, ty = 0;
+      while (std::fgets(line, sizeof(line), f)) {
+        if (!std::strstr(line, key)) continue;
+        const char* pb = std::strstr(line, "\"bx\": ");
+        const char* pt = std::strstr(line, "\"ty\": ");
+        if (pb && pt) {
+          bx = std::atoi(pb + 6);
+          ty = std::atoi(pt + 6);
+        }
+      }
+      std::fclose(f);
+      if (bx > 0 && ty > 0) return vclb_batch_set_tile(b, bx, ty);
+    }
+  }
+  hipStream_t s = as_stream(stream);
+  batch_release_graph(b);
+  HIP_TRY(hipStreamSynchronize(s));
+  // save every case's device state; the timing steps run on it and it is restored after
+  size_t bytes = 0;
+  for (vclb_case* c : b->cases) bytes += c->lay.total;
+  void* save = nullptr;
+  HIP_TRY(hipMalloc(&save, bytes));
+  size_t o = 0;
+  for (vclb_case* c : b->cases) {
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(save) + o, c->ws, c->lay.total, hipMemcpyDeviceToDevice, s));
+    o += c->lay.total;
+  }
+  const int64_t t0 = b->cases[0]->t_host;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  struct Cand { int bx, ty; float ms; };
+  std::vector<Cand> cands;
+  for (int bx : {64, 128, 256})
+    for (int ty : {16, 32, 64}) cands.push_back({bx, ty, -1.0f});
+  int rc = VCLB_OK;
+  for (Cand& cd : cands) {
+    if ((rc = batch_set_tile(b, cd.bx, cd.ty))) break;
+    if ((rc = batch_enqueue(b, 1, false, s))) break;
+    HIP_TRY(hipEventRecord(e0, s));
+    for (vclb_case* c : b->cases) c->t_host = t0 + 1;
+    if ((rc = batch_enqueue(b, steps, false, s))) break;
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    cd.ms = ms / float(steps);
+    for (vclb_case* c : b->cases) c->t_host = t0;
+  }
+  o = 0;
+  for (vclb_case* c : b->cases) {
+    (void)hipMemcpyAsync(c->ws, static_cast<char*>(save) + o, c->lay.total, hipMemcpyDeviceToDevice, s);
+    c->t_host = t0;
+    o += c->lay.total;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(save);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  Cand best = cands[0];
+  for (const Cand& cd : cands)
+    if (cd.ms > 0 && cd.ms < best.ms) best = cd;
+  rc = batch_set_tile(b, best.bx, best.ty);
+  if (rc) return rc;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "{\"key\": \"%s\", \"cases\": %d, \"storage\": %d, \"bx\": %d, \"ty\": %d, \"ms_per_step\": %.6f, \"candidates\": [",
+                   key, b->n, b->storage, best.bx, best.ty, double(best.ms));
+      for (size_t i = 0; i < cands.size(); ++i)
+        std::fprintf(f, "%s[%d, %d, %.6f]", i ? ", " : "", cands[i].bx, cands[i].ty, double(cands[i].ms));
+      std::fprintf(f, "]}\n");
+      std::fclose(f);
+    }
+  }
   return VCLB_OK;
 }
 

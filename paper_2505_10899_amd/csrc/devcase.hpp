@@ -183,12 +183,10 @@ __device__ __forceinline__ double block_sum_fields(const double (&v)[NF], int nf
 // slot; k_finalize sums the slots in workgroup order after the kernel has finished
 // (no device-scope fence inside the step: on gfx950 it would write back and invalidate
 // the XCD's whole L2, which the neighbouring tiles are still reading).
-template <class Case>
-__device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool reduce) {
-  if (!reduce) return;
+__device__ __forceinline__ void write_partials(const Acc& a, int nl, double* part, long stride, long index) {
   __shared__ double red[16 * kMaxLabels * 12];
   constexpr int NF = kMaxLabels * 12;
-  const int nf = c.nl * 12;
+  const int nf = nl * 12;
   double v[NF];
 #pragma unroll
   for (int k = 0; k < kMaxLabels; ++k)
@@ -196,7 +194,12 @@ __device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool r
     for (int f = 0; f < 12; ++f) v[k * 12 + f] = a.v[k][f];
   const double s = block_sum_fields<NF>(v, nf, red);
   // field-major [field][workgroup]: the second pass reads each field coalesced
-  if (int(threadIdx.x) < nf) c.part_w[long(threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  if (int(threadIdx.x) < nf) part[long(threadIdx.x) * stride + index] = s;
+}
+
+template <class Case>
+__device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool reduce) {
+  if (reduce) write_partials(a, c.nl, c.part_w, gridDim.x, blockIdx.x);
 }
 
 // store one node's post-collision state (with the moving-wall term on f for the

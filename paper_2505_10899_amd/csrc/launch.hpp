@@ -34,6 +34,26 @@ int launch_finalize(const DevCase<L, St>& c, hipStream_t s);
 template <class St>
 int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hipStream_t s);
 
+struct BatchArgs {
+  const int4* items;        // (case, x0, y0, y1) of every work item, case-major
+  int nitems;
+  const int2* case_items;   // (first item, item count) per case
+  int ncases;
+  double* part_w;           // [12][nitems] partials written by this launch
+  const double* part_r;     // [12][nitems] partials of the previous launch
+  int pend;                 // part_r holds partials of step pend_step still to be summed
+  long pend_step;
+  long t;                   // step index of the state this launch reads
+  int reduce;               // record the reductions of this step
+};
+
+template <class St>
+int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s);
+template <class St>
+int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s);
+template <class St>
+int batch_max_blocks_per_cu(int bx);
+
 // number of workgroups the fused step launches for a case of this shape
 inline long fused_blocks(int dim, int nx, int ny, int nz, const Tile& t) {
   if (dim == 2) return long((nx + t.bx - 1) / t.bx) * ((ny + t.ty - 1) / t.ty);

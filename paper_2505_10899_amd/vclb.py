@@ -85,6 +85,15 @@ _SIGS = [
     ("vclb_reduce", ctypes.c_int, [ctypes.c_void_p, _P(Obs), ctypes.c_void_p]),
     ("vclb_history", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
     ("vclb_state_bytes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_size_t)]),
+    ("vclb_batch_create", ctypes.c_int, [_P(Params), ctypes.c_int32, _P(ctypes.c_void_p)]),
+    ("vclb_batch_destroy", None, [ctypes.c_void_p]),
+    ("vclb_batch_case", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_void_p)]),
+    ("vclb_batch_nodes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64)]),
+    ("vclb_batch_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    ("vclb_batch_get_tile", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    ("vclb_batch_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("vclb_batch_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
+    ("vclb_batch_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32, ctypes.c_void_p]),
     ("vclb_state_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("vclb_state_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
 ]
@@ -162,17 +171,21 @@ class Case:
     Device state is a torch uint8 workspace handed to the library; calls are enqueued
     on torch's current stream (or ``stream``)."""
 
-    def __init__(self, p, device="cuda", tile=None):
+    def __init__(self, p, device="cuda", tile=None, _borrowed=None):
         self.p = p
         self.cp = to_cparams(p)
         self.device = torch.device(device)
-        nbytes = workspace_bytes(p)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) // 256 * 256
-        h = ctypes.c_void_p()
-        check(lib().vclb_case_create(ctypes.byref(self.cp), ctypes.c_void_p(aligned), nbytes, ctypes.byref(h)))
-        self.h = h
+        self._owner = None
+        if _borrowed is not None:                 # a case owned by a Batch
+            self._owner, self.h = _borrowed
+        else:
+            nbytes = workspace_bytes(p)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            h = ctypes.c_void_p()
+            check(lib().vclb_case_create(ctypes.byref(self.cp), ctypes.c_void_p(aligned), nbytes, ctypes.byref(h)))
+            self.h = h
         self.n = p.nx * p.ny * p.nz
         self.D = 2 if p.lattice == "D2Q9" else 3
         self.nlabels = max(1, len(p.label_centres))
@@ -181,7 +194,7 @@ class Case:
 
     def __del__(self):
         try:
-            if getattr(self, "h", None):
+            if getattr(self, "h", None) and self._owner is None:
                 torch.cuda.synchronize(self.device)
                 lib().vclb_case_destroy(self.h)
                 self.h = None
@@ -317,3 +330,59 @@ def _obs_to_dict(arr, n) -> dict:
         "nonfinite": np.array([arr[k].nonfinite for k in range(n)]),
         "step": np.array([arr[k].step for k in range(n)]),
     }
+
+
+class Batch:
+    """Many independent coupled D2Q9 cases advanced together (one work-list kernel per
+    step, a call's steps replayed from one hipGraph).  ``cases[k]`` is a Case view of
+    case k (init, observe, reduce, history, get/set_state)."""
+
+    def __init__(self, params_list, device="cuda"):
+        n = len(params_list)
+        arr = (Params * n)(*[to_cparams(p) for p in params_list])
+        h = ctypes.c_void_p()
+        check(lib().vclb_batch_create(arr, n, ctypes.byref(h)))
+        self.h = h
+        self.device = torch.device(device)
+        self.params = list(params_list)
+        self.cases = []
+        for k, p in enumerate(self.params):
+            ch = ctypes.c_void_p()
+            check(lib().vclb_batch_case(self.h, k, ctypes.byref(ch)))
+            self.cases.append(Case(p, device=device, _borrowed=(self, ch)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                torch.cuda.synchronize(self.device)
+                for c in self.cases:
+                    c.h = None
+                lib().vclb_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def nodes(self) -> int:
+        n = ctypes.c_int64()
+        check(lib().vclb_batch_nodes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def set_tile(self, bx, ty):
+        check(lib().vclb_batch_set_tile(self.h, int(bx), int(ty)))
+
+    def tile(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().vclb_batch_get_tile(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_reduce_every(self, every: int):
+        check(lib().vclb_batch_set_reduce_every(self.h, int(every)))
+
+    def step(self, n: int = 1, graph: bool = True, stream=None):
+        check(lib().vclb_batch_step(self.h, int(n), 1 if graph else 0, _stream_handle(stream)))
+        return self
+
+    def autotune(self, cache_path=None, steps: int = 5, stream=None):
+        path = cache_path.encode() if cache_path else None
+        check(lib().vclb_batch_autotune(self.h, path, int(steps), _stream_handle(stream)))
+        return self.tile()

@@ -1,0 +1,99 @@
+"""GPU tests of the batched path: uneven cases advanced together must reproduce each
+case advanced alone with the same tile (the single-case path is itself checked against
+the oracle), the hipGraph replay must equal eager launches, and the autotuner must leave
+the state untouched."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _v():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_10899_amd import vclb
+    return vclb
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_batch(storage="fp64", n=6, seed=7):
+    cases, _ = W.batch_cases(n_cases=n, seed=seed, storage=storage, side_lo=40, side_hi=150)
+    return cases
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp16s"])
+def test_batch_matches_cases_run_alone(storage):
+    v = _v()
+    cases = small_batch(storage)
+    say("case: batch of", [(p.nx, p.ny, p.wall_y) for p, _, _ in cases], storage)
+    b = v.Batch([p for p, _, _ in cases])
+    b.set_tile(64, 16)
+    for c, (p, phi0, u0) in zip(b.cases, cases):
+        c.init(phi0, u0)
+    b.step(25)
+    for k, (p, phi0, u0) in enumerate(cases):
+        alone = v.Case(p, tile=(64, 16)).init(phi0, u0)
+        alone.step(25)
+        ga, fa, Ja = alone.get_state()
+        gb, fb, Jb = b.cases[k].get_state()
+        err = max(np.max(np.abs(ga - gb)), np.max(np.abs(fa - fb)), np.max(np.abs(Ja - Jb)))
+        say(f"  case {k} {p.nx}x{p.ny}: max |batch - alone| = {err:.3e}")
+        assert err <= (1e-13 if storage == "fp64" else 1e-5), k
+        ha, hb = alone.history(0, 25), b.cases[k].history(0, 25)
+        assert np.allclose(ha["sum_phi"], hb["sum_phi"], rtol=1e-12 if storage == "fp64" else 1e-6)
+
+
+def test_batch_graph_equals_eager_and_history():
+    v = _v()
+    cases = small_batch("fp32", n=5, seed=3)
+    runs = []
+    for graph in (True, False):
+        b = v.Batch([p for p, _, _ in cases])
+        for c, (p, phi0, u0) in zip(b.cases, cases):
+            c.init(phi0, u0)
+        b.step(7, graph=graph)
+        b.step(6, graph=graph)
+        runs.append((b, [c.get_state() for c in b.cases]))
+    for k in range(len(cases)):
+        for a, c in zip(runs[0][1][k], runs[1][1][k]):
+            assert np.array_equal(a, c), k
+    b = runs[0][0]
+    for k, c in enumerate(b.cases):
+        assert c.time() == 13
+        h = c.history(0, 13)
+        assert np.all(h["step"][:, 0] == np.arange(13))
+        r = c.reduce()
+        assert abs(r["sum_phi"][0] - h["sum_phi"][-1, 0]) <= 1e-5 * abs(r["sum_phi"][0])
+
+
+def test_batch_autotune_restores_state_and_uses_cache(tmp_path):
+    v = _v()
+    cases = small_batch("fp32", n=4, seed=11)
+    b = v.Batch([p for p, _, _ in cases])
+    for c, (p, phi0, u0) in zip(b.cases, cases):
+        c.init(phi0, u0)
+    b.step(3)
+    before = [c.get_state() for c in b.cases]
+    cache = str(tmp_path / "tiles.jsonl")
+    tile = b.autotune(cache, steps=2)
+    say("  autotuned tile", tile)
+    after = [c.get_state() for c in b.cases]
+    for x, y in zip(before, after):
+        for a, c in zip(x, y):
+            assert np.array_equal(a, c)
+    assert all(c.time() == 3 for c in b.cases)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"bx"' in lines[0]
+    b.set_tile(64, 64)
+    assert b.autotune(cache, steps=2)[:2] == tile[:2]        # read back from the cache
+    assert len(open(cache).read().strip().splitlines()) == 1
