@@ -173,7 +173,8 @@ int vclb_case_get_state(vclb_case* c, double* g, double* f, double* J, int ptr_k
 int vclb_step(vclb_case* c, int64_t nsteps, void* stream);
 
 /* Same update with the plain two-kernel path (phi/psi pass, then stencil + collision
-   from global memory); bitwise equal to vclb_step.  Asynchronous. */
+   from global memory); the same arithmetic as vclb_step up to the order in which the
+   compiler contracts multiply-adds.  Asynchronous. */
 int vclb_step_plain(vclb_case* c, int64_t nsteps, void* stream);
 
 /* Record the per-step reductions every `every` steps (0 turns them off; default 1). */
@@ -199,6 +200,52 @@ int vclb_history(vclb_case* c, int64_t t_first, int32_t count, vclb_obs* out, vo
 int vclb_state_bytes(const vclb_case* c, size_t* bytes);
 int vclb_state_save(vclb_case* c, void* host_buf, size_t bytes, void* stream);
 int vclb_state_load(vclb_case* c, const void* host_buf, size_t bytes, void* stream);
+
+/* ---------------------------------------------------------------- observables */
+/* Derived observables of each label from its moments (host arithmetic, no HIP call):
+   out[5 * l + k] = volume sum phi, centroid offset sum phi d / sum phi (x, y, z), and the
+   deformation D = (sqrt(l+) - sqrt(l-)) / (sqrt(l+) + sqrt(l-)) of the eigenvalues l+-
+   of the phi-weighted (x, y) second-moment tensor about the centroid. */
+int vclb_obs_derived(const vclb_obs* obs, int32_t nlabels, double* out);
+
+/* Moment weights seed[10 * l + j] (j: sum, d[3], dd[6] as in vclb_obs) of the
+   linearisation of J = sum_l sum_k weights[5 * l + k] O_k(l) about obs, with O the
+   derived observables of vclb_obs_derived.  Host arithmetic, no HIP call.  At D = 0 the
+   direction-dependent terms of dD are dropped. */
+int vclb_obs_seed(const vclb_obs* obs, int32_t nlabels, const double* weights, double* seed);
+
+/* ---------------------------------------------------------------- adjoint */
+/* Gradients of a function J of the phase field after nsteps steps with respect to the
+   surface tension sigma, the mobility M and the initial field phi0, by the discrete
+   adjoint of the time step: the reverse of the streaming (with bounce-back and the
+   moving-wall term), of the collisions Eqs. 25 and 33 with their equilibria and sources
+   (Eqs. 21-23, 31-32), of u and p (Eqs. 28-29), mu (Eq. 2), psi (Eq. 37) and the
+   stencils Eqs. 39-40, and of the initial state.  FP64 D2Q9 coupled cases only
+   (VCLB_EINVAL otherwise).  The derivative of the clip of phi to [0, 1] is taken as 1
+   inside the interval and 0 outside.
+
+   Device bytes of the checkpoint store and adjoint fields (no HIP call); every = 0
+   selects ceil(sqrt(nsteps)). */
+int vclb_adjoint_bytes(const vclb_params* p, int64_t nsteps, int32_t every, size_t* bytes);
+
+/* Forward pass: vclb_case_init(phi0, u0), then nsteps fused steps, keeping a copy of the
+   state (pulled g and f, previous phi u) every `every` steps (0: ceil(sqrt(nsteps))).
+   The library allocates the store (vclb_adjoint_bytes; freed by the next record or by
+   vclb_case_destroy).  Afterwards the case holds the state at step nsteps.  Synchronises
+   the stream. */
+int vclb_adjoint_record(vclb_case* c, const double* phi0, const double* u0, int ptr_kind, int64_t nsteps,
+                        int32_t every, void* stream);
+
+/* Backward pass of the recorded run for J = sum_l seed[10 l] sum phi + seed[10 l + 1..3] .
+   sum phi d + seed[10 l + 4..9] . sum phi dd (moments of the final state, labels as in
+   vclb_reduce; seed is host memory, see vclb_obs_seed).  Each segment between
+   checkpoints is recomputed with the forward step and then run backward.  Writes dJ/dphi0
+   to dphi0 (N doubles, ptr_kind; NULL: not returned) and (dJ/dsigma, dJ/dM) to dparams
+   (2 doubles, host; NULL: not returned).  M acts through the rates of g left at their
+   default 1 / tau_g.  The case state is left unchanged.  Synchronises the stream.
+   VCLB_ESTATE without a prior vclb_adjoint_record. */
+int vclb_adjoint_run(vclb_case* c, const double* seed, double* dphi0, int ptr_kind, double* dparams,
+                     void* stream);
 
 /* ---------------------------------------------------------------- batches of cases */
 /* Many independent coupled D2Q9 cases of uneven sizes (one storage precision), advanced

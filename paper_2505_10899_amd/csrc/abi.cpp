@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/vclb.h"
+#include "adjoint.hpp"
 #include "launch.hpp"
 
 namespace {
@@ -175,7 +176,12 @@ struct vclb_case {
   bool pending = false;
   int pend_nb = 0, pend_buf = 0;
   int64_t pend_step = 0;
+  struct AdjStore* adj = nullptr;   // recorded forward pass of the adjoint (FP64 D2Q9 only)
 };
+
+namespace {
+void adj_release(vclb_case* c);
+}
 
 namespace {
 
@@ -394,6 +400,7 @@ int vclb_case_create(const vclb_params* p, void* workspace, size_t workspace_byt
 
 void vclb_case_destroy(vclb_case* c) {
   if (!c) return;
+  adj_release(c);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   delete c;
 }
@@ -1181,6 +1188,313 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
         std::fprintf(f, "%s[%d, %d, %.6f]", i ? ", " : "", cands[i].bx, cands[i].ty, double(cands[i].ms));
       std::fprintf(f, "]}\n");
       std::fclose(f);
+    }
+  }
+  return VCLB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- adjoint
+// Device memory of one recorded forward pass: the initial fields, a state (g, f, Jprev:
+// 20 N doubles) every `every` steps, room for the `every` states of the segment being
+// recomputed, and the fields of the backward sweep.
+struct AdjStore {
+  char* mem = nullptr;
+  int64_t nsteps = 0;
+  int32_t every = 1;
+  int64_t nckpt = 0;
+  bool has_u0 = false;
+  size_t n = 0, state = 0;   // nodes, doubles per state
+  size_t phi0 = 0, u0 = 0, ckpt = 0, seg = 0, lg[2]{}, lf[2]{}, lJ[2]{}, lphi = 0, aux = 0, part = 0,
+         seed = 0, out = 0, dphi = 0, total = 0;
+  long blocks = 0;
+};
+
+namespace {
+
+void adj_release(vclb_case* c) {
+  if (!c->adj) return;
+  if (c->adj->mem) (void)hipFree(c->adj->mem);
+  delete c->adj;
+  c->adj = nullptr;
+}
+
+int32_t adj_default_every(int64_t nsteps) {
+  if (nsteps <= 1) return 1;
+  return int32_t(std::ceil(std::sqrt(double(nsteps))));
+}
+
+AdjStore adj_layout(const vclb_params& p, int64_t nsteps, int32_t every) {
+  AdjStore a;
+  a.nsteps = nsteps;
+  a.every = every;
+  a.nckpt = nsteps > 0 ? (nsteps + every - 1) / every : 0;
+  a.n = size_t(p.nx) * p.ny;
+  a.state = 20 * a.n;
+  a.blocks = vclb::adj_blocks(long(a.n));
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t o = off;
+    off = align_up(off + doubles * sizeof(double));
+    return o;
+  };
+  a.phi0 = take(a.n);
+  a.u0 = take(2 * a.n);
+  a.ckpt = take(size_t(a.nckpt) * a.state);
+  a.seg = take(size_t(std::min<int64_t>(every, std::max<int64_t>(nsteps, 1))) * a.state);
+  for (int b = 0; b < 2; ++b) {
+    a.lg[b] = take(9 * a.n);
+    a.lf[b] = take(9 * a.n);
+    a.lJ[b] = take(2 * a.n);
+  }
+  a.lphi = take(a.n);
+  a.aux = take(6 * a.n);
+  a.part = take(2 * size_t(a.blocks));
+  a.seed = take(size_t(vclb::kMaxLabels) * vclb::kSeedFields);
+  a.out = take(2);
+  a.dphi = take(a.n);
+  a.total = off;
+  return a;
+}
+
+int adj_check_case(const vclb_case* c) {
+  if (c->p.lattice != VCLB_D2Q9 || c->p.storage != VCLB_FP64 || c->p.mode != VCLB_COUPLED)
+    return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
+  return VCLB_OK;
+}
+
+// copy the case's current state (pulled populations of the current parity, Jprev)
+int adj_save_state(vclb_case* c, double* dst, hipStream_t s) {
+  const size_t n = c->adj->n;
+  const int par = int(c->t_host & 1);
+  HIP_TRY(hipMemcpyAsync(dst, c->ws + c->lay.pop[0][par], 9 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dst + 9 * n, c->ws + c->lay.pop[1][par], 9 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dst + 18 * n, c->ws + c->lay.J, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return VCLB_OK;
+}
+
+// derived observables of one label and their gradients with respect to the moments
+// m = (sum, d[3], dd[6]): volume, centroid offset (3), deformation D of the in-plane
+// second-moment tensor about the centroid
+void derived_with_grad(const vclb_obs& o, double out[5], double grad[5][vclb::kSeedFields]) {
+  for (int k = 0; k < 5; ++k)
+    for (int j = 0; j < vclb::kSeedFields; ++j) grad[k][j] = 0.0;
+  const double V = o.sum_phi;
+  const double cx = o.sum_phi_d[0] / V, cy = o.sum_phi_d[1] / V, cz = o.sum_phi_d[2] / V;
+  out[0] = V;
+  out[1] = cx;
+  out[2] = cy;
+  out[3] = cz;
+  grad[0][0] = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    grad[1 + a][0] = -o.sum_phi_d[a] / (V * V);
+    grad[1 + a][1 + a] = 1.0 / V;
+  }
+  const double dxx = o.sum_phi_dd[0] / V, dyy = o.sum_phi_dd[1] / V, dxy = o.sum_phi_dd[3] / V;
+  const double ixx = dxx - cx * cx, iyy = dyy - cy * cy, ixy = dxy - cx * cy;
+  // d(ixx, iyy, ixy)/dm over the entries m0, m1 (x), m2 (y), m4 (xx), m5 (yy), m7 (xy)
+  double gi[3][vclb::kSeedFields] = {};
+  gi[0][0] = (-dxx + 2.0 * cx * cx) / V;
+  gi[0][1] = -2.0 * cx / V;
+  gi[0][4] = 1.0 / V;
+  gi[1][0] = (-dyy + 2.0 * cy * cy) / V;
+  gi[1][2] = -2.0 * cy / V;
+  gi[1][5] = 1.0 / V;
+  gi[2][0] = (-dxy + 2.0 * cx * cy) / V;
+  gi[2][1] = -cy / V;
+  gi[2][2] = -cx / V;
+  gi[2][7] = 1.0 / V;
+  const double half = 0.5 * (ixx - iyy);
+  const double disc = std::sqrt(half * half + ixy * ixy);
+  const double lp = 0.5 * (ixx + iyy) + disc, lm = 0.5 * (ixx + iyy) - disc;
+  const double a = std::sqrt(lp), b = std::sqrt(lm);
+  out[4] = (a - b) / (a + b);
+  // dD/dl+ = b / (a (a + b)^2), dD/dl- = -a / (b (a + b)^2); at a circle (disc = 0) the
+  // one-sided derivatives differ and the terms in half/disc, ixy/disc are dropped
+  const double s2 = (a + b) * (a + b);
+  const double dlp = b / (a * s2), dlm = -a / (b * s2);
+  const double hx = disc > 0.0 ? half / (2.0 * disc) : 0.0, hy = disc > 0.0 ? ixy / disc : 0.0;
+  const double dIxx = dlp * (0.5 + hx) + dlm * (0.5 - hx);
+  const double dIyy = dlp * (0.5 - hx) + dlm * (0.5 + hx);
+  const double dIxy = dlp * hy - dlm * hy;
+  for (int j = 0; j < vclb::kSeedFields; ++j) grad[4][j] = dIxx * gi[0][j] + dIyy * gi[1][j] + dIxy * gi[2][j];
+}
+
+}  // namespace
+
+extern "C" {
+
+int vclb_adjoint_bytes(const vclb_params* p, int64_t nsteps, int32_t every, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bytes || nsteps < 0 || every < 0) return fail(VCLB_EINVAL, "bad argument");
+  if (p->lattice != VCLB_D2Q9 || p->storage != VCLB_FP64 || p->mode != VCLB_COUPLED)
+    return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
+  if (every == 0) every = adj_default_every(nsteps);
+  *bytes = adj_layout(*p, nsteps, every).total;
+  return VCLB_OK;
+}
+
+int vclb_adjoint_record(vclb_case* c, const double* phi0, const double* u0, int ptr_kind, int64_t nsteps,
+                        int32_t every, void* stream) {
+  if (!c || !phi0) return fail(VCLB_EINVAL, "case or phi0 is NULL");
+  if (int rc = adj_check_case(c)) return rc;
+  if (ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
+  if (nsteps < 0 || every < 0) return fail(VCLB_EINVAL, "nsteps and every must be >= 0");
+  if (every == 0) every = adj_default_every(nsteps);
+  const size_t n = size_t(c->p.nx) * c->p.ny;
+  if (ptr_kind == VCLB_HOST)
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(phi0[i])) return fail(VCLB_ENONFINITE, "phi0 has a NaN/Inf");
+  hipStream_t s = as_stream(stream);
+  adj_release(c);
+  AdjStore lay = adj_layout(c->p, nsteps, every);
+  void* m = nullptr;
+  hipError_t e = hipMalloc(&m, lay.total);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? VCLB_ENOMEM : VCLB_EHIP, "hipMalloc of the adjoint store failed");
+  c->adj = new (std::nothrow) AdjStore(lay);
+  if (!c->adj) {
+    (void)hipFree(m);
+    return fail(VCLB_ENOMEM, "host allocation");
+  }
+  AdjStore& a = *c->adj;
+  a.mem = static_cast<char*>(m);
+  a.has_u0 = u0 != nullptr;
+  const hipMemcpyKind kind = ptr_kind == VCLB_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  double* dphi0 = reinterpret_cast<double*>(a.mem + a.phi0);
+  double* du0 = reinterpret_cast<double*>(a.mem + a.u0);
+  HIP_TRY(hipMemcpyAsync(dphi0, phi0, n * sizeof(double), kind, s));
+  if (u0) HIP_TRY(hipMemcpyAsync(du0, u0, 2 * n * sizeof(double), kind, s));
+  int rc = vclb_case_init(c, dphi0, u0 ? du0 : nullptr, VCLB_DEVICE, stream);
+  if (rc) {
+    adj_release(c);
+    return rc;
+  }
+  for (int64_t k = 0; k < a.nckpt; ++k) {
+    rc = adj_save_state(c, reinterpret_cast<double*>(a.mem + a.ckpt) + size_t(k) * a.state, s);
+    if (!rc) rc = vclb_step(c, std::min<int64_t>(a.every, a.nsteps - k * a.every), stream);
+    if (rc) {
+      adj_release(c);
+      return rc;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return VCLB_OK;
+}
+
+int vclb_adjoint_run(vclb_case* c, const double* seed, double* dphi0, int ptr_kind, double* dparams,
+                     void* stream) {
+  if (!c || !seed) return fail(VCLB_EINVAL, "case or seed is NULL");
+  if (int rc = adj_check_case(c)) return rc;
+  if (!c->adj) return fail(VCLB_ESTATE, "adjoint run before vclb_adjoint_record");
+  if (dphi0 && ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
+  const int nl = std::max(1, c->p.nlabels);
+  for (int k = 0; k < nl * vclb::kSeedFields; ++k)
+    if (!std::isfinite(seed[k])) return fail(VCLB_EINVAL, "seed has a NaN/Inf");
+  hipStream_t s = as_stream(stream);
+  AdjStore& st = *c->adj;
+  char* M = st.mem;
+  const size_t n = st.n;
+  auto dptr = [&](size_t off) { return reinterpret_cast<double*>(M + off); };
+  HIP_TRY(hipMemcpyAsync(dptr(st.seed), seed, size_t(nl) * vclb::kSeedFields * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  if (vclb::launch_adj_zero(dptr(st.part), 2 * st.blocks, s)) return fail(VCLB_EHIP, "adjoint launch failed");
+
+  vclb::DevCase<vclb::D2Q9, vclb::StoreF64> base = make_dev<vclb::D2Q9, vclb::StoreF64>(*c);
+  base.t = 0;
+  base.pend_nb = 0;
+  base.part_r = nullptr;
+  vclb::AdjArgs a{};
+  a.lphi = dptr(st.lphi);
+  a.aux = dptr(st.aux);
+  a.param_part = dptr(st.part);
+  a.seed = dptr(st.seed);
+  a.beta4_per_sigma = 48.0 / c->p.W;
+  a.kappa_per_sigma = 1.5 * c->p.W;
+  a.mobility_rows = 0;
+  for (int k = 0; k < 9; ++k)
+    if (c->p.s_g[k] == 0.0 && vclb::D2Q9::g_flux_row[k]) a.mobility_rows |= 1u << k;
+  int cur = 0;
+  auto bind = [&](int in) {
+    a.lg_in = dptr(st.lg[in]);
+    a.lf_in = dptr(st.lf[in]);
+    a.lJ_in = dptr(st.lJ[in]);
+    a.lg_out = dptr(st.lg[in ^ 1]);
+    a.lf_out = dptr(st.lf[in ^ 1]);
+    a.lJ_out = dptr(st.lJ[in ^ 1]);
+  };
+  bind(1);   // the seed writes buffer 0
+  int rc = vclb::launch_adj_seed(base, a, s);
+  auto slot = [&](int64_t k) { return dptr(st.seg) + size_t(k) * st.state; };
+  for (int64_t seg = st.nckpt - 1; seg >= 0 && !rc; --seg) {
+    const int64_t t0 = seg * st.every, len = std::min<int64_t>(st.every, st.nsteps - t0);
+    HIP_TRY(hipMemcpyAsync(slot(0), dptr(st.ckpt) + size_t(seg) * st.state, st.state * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    // recompute the segment's states with the forward step (no reductions)
+    for (int64_t k = 0; k + 1 < len && !rc; ++k) {
+      HIP_TRY(hipMemcpyAsync(slot(k + 1) + 18 * n, slot(k) + 18 * n, 2 * n * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      auto f = base;
+      f.pop[0][0] = slot(k);
+      f.pop[1][0] = slot(k) + 9 * n;
+      f.pop[0][1] = slot(k + 1);
+      f.pop[1][1] = slot(k + 1) + 9 * n;
+      f.J = slot(k + 1) + 18 * n;
+      rc = vclb::launch_step_fused<vclb::D2Q9, vclb::StoreF64, true>(f, c->tile, 0, s);
+    }
+    // backward through the segment
+    for (int64_t k = len - 1; k >= 0 && !rc; --k) {
+      auto b = base;
+      b.pop[0][0] = slot(k);
+      b.pop[1][0] = slot(k) + 9 * n;
+      b.pop[0][1] = nullptr;
+      b.pop[1][1] = nullptr;
+      b.J = slot(k) + 18 * n;
+      bind(cur);
+      rc = vclb::launch_phi_psi<vclb::D2Q9, vclb::StoreF64>(b, s);
+      if (!rc) rc = vclb::launch_adj_step(b, a, s);
+      cur ^= 1;
+    }
+  }
+  if (rc) return fail(VCLB_EHIP, "adjoint launch failed");
+  bind(cur);
+  double* dst = (dphi0 && ptr_kind == VCLB_DEVICE) ? dphi0 : dptr(st.dphi);
+  rc = vclb::launch_adj_init(base, a, dptr(st.phi0), st.has_u0 ? dptr(st.u0) : nullptr, dst, s);
+  if (!rc) rc = vclb::launch_adj_params(a, int(st.blocks), dptr(st.out), s);
+  if (rc) return fail(VCLB_EHIP, "adjoint launch failed");
+  double host_out[2] = {0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(host_out, dptr(st.out), sizeof(host_out), hipMemcpyDeviceToHost, s));
+  if (dphi0 && ptr_kind == VCLB_HOST) HIP_TRY(hipMemcpyAsync(dphi0, dst, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (dparams) {
+    dparams[0] = host_out[0];
+    dparams[1] = host_out[1];
+  }
+  return VCLB_OK;
+}
+
+int vclb_obs_derived(const vclb_obs* obs, int32_t nlabels, double* out) {
+  if (!obs || !out || nlabels < 1 || nlabels > VCLB_MAX_LABELS) return fail(VCLB_EINVAL, "bad argument");
+  for (int l = 0; l < nlabels; ++l) {
+    double g[5][vclb::kSeedFields];
+    derived_with_grad(obs[l], out + 5 * l, g);
+  }
+  return VCLB_OK;
+}
+
+int vclb_obs_seed(const vclb_obs* obs, int32_t nlabels, const double* weights, double* seed) {
+  if (!obs || !weights || !seed || nlabels < 1 || nlabels > VCLB_MAX_LABELS)
+    return fail(VCLB_EINVAL, "bad argument");
+  for (int l = 0; l < nlabels; ++l) {
+    double v[5], g[5][vclb::kSeedFields];
+    derived_with_grad(obs[l], v, g);
+    for (int j = 0; j < vclb::kSeedFields; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 5; ++k)
+        if (weights[5 * l + k] != 0.0) acc += weights[5 * l + k] * g[k][j];
+      seed[vclb::kSeedFields * l + j] = acc;
     }
   }
   return VCLB_OK;

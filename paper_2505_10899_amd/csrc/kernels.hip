@@ -331,6 +331,13 @@ int launch_observe(const DevCase<L, St>& c, unsigned mask, double* out, hipStrea
 }
 
 template <class L, class St>
+int launch_phi_psi(const DevCase<L, St>& c, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class L, class St>
 int launch_reduce_state(const DevCase<L, St>& c, hipStream_t s) {
   const unsigned nb = unsigned((c.n + 255) / 256);
   hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
@@ -375,6 +382,7 @@ VCLB_INSTANTIATE(D3Q19, StoreF64, true)
 VCLB_INSTANTIATE(D3Q19, StoreF32, true)
 VCLB_INSTANTIATE(D3Q19, StoreF16S, true)
 template int launch_reduce_state<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
+template int launch_phi_psi<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
 template int launch_finalize<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
 template int launch_finalize<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
 template int launch_finalize<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);

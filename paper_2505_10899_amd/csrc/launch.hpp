@@ -23,6 +23,8 @@ int launch_step_fused(const DevCase<L, St>& c, const Tile& tile, int reduce, hip
 template <class L, class St, bool COUPLED>
 int launch_observe(const DevCase<L, St>& c, unsigned mask, double* out, hipStream_t s);
 template <class L, class St>
+int launch_phi_psi(const DevCase<L, St>& c, hipStream_t s);
+template <class L, class St>
 int launch_reduce_state(const DevCase<L, St>& c, hipStream_t s);
 template <class L, class St, bool COUPLED>
 int launch_set_state(const DevCase<L, St>& c, const double* g, const double* f, const double* J, long t,

@@ -96,7 +96,17 @@ _SIGS = [
     ("vclb_batch_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32, ctypes.c_void_p]),
     ("vclb_state_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("vclb_state_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    ("vclb_obs_derived", ctypes.c_int, [_P(Obs), ctypes.c_int32, _P(ctypes.c_double)]),
+    ("vclb_obs_seed", ctypes.c_int, [_P(Obs), ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_double)]),
+    ("vclb_adjoint_bytes", ctypes.c_int, [_P(Params), ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_size_t)]),
+    ("vclb_adjoint_record", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
+    ("vclb_adjoint_run", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_void_p, ctypes.c_int,
+                                        _P(ctypes.c_double), ctypes.c_void_p]),
 ]
+
+DERIVED = ("volume", "centroid_x", "centroid_y", "centroid_z", "D")
+SEED_FIELDS = 10
 
 
 def lib():
@@ -286,6 +296,44 @@ class Case:
                 off += k * self.n
         return res
 
+    def reduce_raw(self, stream=None):
+        """Moments of the current state as the C array of vclb_obs (one per label)."""
+        arr = (Obs * self.nlabels)()
+        rc = lib().vclb_reduce(self.h, arr, _stream_handle(stream))
+        if rc not in (VCLB_OK, VCLB_ENONFINITE):
+            check(rc)
+        return arr
+
+    def derived(self, stream=None) -> np.ndarray:
+        """(labels, 5) array of volume, centroid offset (x, y, z) and deformation D."""
+        return obs_derived(self.reduce_raw(stream), self.nlabels)
+
+    # ---------------------------------------------------------------- adjoint (FP64 D2Q9 coupled)
+    def adjoint_record(self, phi0, u0=None, nsteps: int = 0, every: int = 0, stream=None):
+        """Forward pass from phi0 (and u0) over nsteps steps, keeping a state every
+        `every` steps (0: ceil(sqrt(nsteps))) for vclb_adjoint_run."""
+        phi = _as_device_f64(phi0, self.device)
+        u = _as_device_f64(u0, self.device) if u0 is not None else None
+        if not torch.isfinite(phi).all():
+            raise VclbError(VCLB_ENONFINITE, "phi0 has a NaN/Inf")
+        check(lib().vclb_adjoint_record(self.h, ctypes.c_void_p(phi.data_ptr()),
+                                        ctypes.c_void_p(u.data_ptr() if u is not None else 0), DEVICE,
+                                        int(nsteps), int(every), _stream_handle(stream)))
+        return self
+
+    def adjoint_run(self, seed, stream=None):
+        """Backward pass for the moment weights `seed` ((labels, 10) array, see
+        obs_seed).  Returns (dJ/dphi0 as a float64 device tensor shaped (nz, ny, nx),
+        dJ/dsigma, dJ/dM)."""
+        sd = np.ascontiguousarray(seed, dtype=np.float64).reshape(-1)
+        if sd.size != self.nlabels * SEED_FIELDS:
+            raise VclbError(VCLB_EINVAL, "seed must hold 10 weights per label")
+        dphi = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        out = (ctypes.c_double * 2)()
+        check(lib().vclb_adjoint_run(self.h, sd.ctypes.data_as(_P(ctypes.c_double)),
+                                     ctypes.c_void_p(dphi.data_ptr()), DEVICE, out, _stream_handle(stream)))
+        return dphi.reshape(self.p.nz, self.p.ny, self.p.nx), out[0], out[1]
+
     def reduce(self, stream=None) -> dict:
         arr = (Obs * self.nlabels)()
         rc = lib().vclb_reduce(self.h, arr, _stream_handle(stream))
@@ -319,6 +367,60 @@ class Case:
         buf = ctypes.create_string_buffer(blob, len(blob))
         check(lib().vclb_state_load(self.h, buf, len(blob), _stream_handle(stream)))
         return self
+
+
+def _as_device_f64(a, device):
+    if isinstance(a, torch.Tensor):
+        return a.detach().to(device=device, dtype=torch.float64).contiguous().reshape(-1)
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to(device)
+
+
+def obs_derived(arr, nlabels: int) -> np.ndarray:
+    """Derived observables (volume, centroid offset x/y/z, D) per label from vclb_obs moments."""
+    out = (ctypes.c_double * (5 * nlabels))()
+    check(lib().vclb_obs_derived(arr, int(nlabels), out))
+    return np.array(out[:]).reshape(nlabels, 5)
+
+
+def obs_seed(arr, nlabels: int, weights) -> np.ndarray:
+    """Moment weights (labels, 10) of J = sum weights[l, k] * derived[l, k], linearised at arr."""
+    w = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+    if w.size != 5 * nlabels:
+        raise VclbError(VCLB_EINVAL, "weights must hold 5 values per label")
+    out = (ctypes.c_double * (SEED_FIELDS * nlabels))()
+    check(lib().vclb_obs_seed(arr, int(nlabels), w.ctypes.data_as(_P(ctypes.c_double)), out))
+    return np.array(out[:]).reshape(nlabels, SEED_FIELDS)
+
+
+class _Rollout(torch.autograd.Function):
+    """Derived observables after nsteps steps as a differentiable function of
+    (phi0, sigma, mobility); the backward pass is the library's discrete adjoint."""
+
+    @staticmethod
+    def forward(ctx, phi0, sigma, mobility, p, nsteps, every, u0, device):
+        q = p.replace(sigma=float(sigma), mobility=float(mobility))
+        case = Case(q, device=device)
+        case.adjoint_record(phi0, u0, nsteps=nsteps, every=every)
+        raw = case.reduce_raw()
+        ctx.case, ctx.raw = case, raw
+        ctx.shape = phi0.shape
+        return torch.as_tensor(obs_derived(raw, case.nlabels), dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        case = ctx.case
+        seed = obs_seed(ctx.raw, case.nlabels, grad_out.detach().cpu().numpy())
+        dphi, dsig, dmob = case.adjoint_run(seed)
+        return (dphi.reshape(ctx.shape), torch.tensor(dsig, dtype=torch.float64),
+                torch.tensor(dmob, dtype=torch.float64), None, None, None, None, None)
+
+
+def rollout(p, phi0: torch.Tensor, sigma: torch.Tensor, mobility: torch.Tensor, nsteps: int, every: int = 0,
+            u0=None, device="cuda") -> torch.Tensor:
+    """(labels, 5) tensor of volume, centroid offset (x, y, z) and deformation D after
+    nsteps FP64 D2Q9 coupled steps from phi0, differentiable in phi0, sigma and mobility
+    (checkpoint every `every` steps; 0: ceil(sqrt(nsteps)))."""
+    return _Rollout.apply(phi0, sigma, mobility, p, int(nsteps), int(every), u0, device)
 
 
 def _obs_to_dict(arr, n) -> dict:

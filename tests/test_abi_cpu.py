@@ -132,3 +132,29 @@ def test_corrupt_checkpoints_rejected_before_any_copy():
     assert L.vclb_state_load(h, blob, good_len, None) == v.VCLB_EINVAL
     assert b"checkpoint" in L.vclb_last_error()
     L.vclb_case_destroy(h)
+
+
+def test_adjoint_entry_points_reject_without_gpu():
+    v = _vclb()
+    L = v.lib()
+    p64 = W.shear_droplet(nx=64, ny=32, R=8.0)[0]
+    n = ctypes.c_size_t()
+    assert L.vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p64)), 100, 10, ctypes.byref(n)) == 0
+    # 10 checkpoints + 10 segment states of 20 doubles per node, plus 50 doubles of fields
+    assert n.value >= (20 * 20 + 50) * 8 * p64.nx * p64.ny
+    for q in (p64.replace(storage="fp32"), W.two_droplets()[0].replace(storage="fp16s"),
+              W.single_vortex()[0], W.rayleigh_plateau(storage="fp64")[0]):
+        assert L.vclb_adjoint_bytes(ctypes.byref(v.to_cparams(q)), 10, 0, ctypes.byref(n)) == v.VCLB_EINVAL
+    assert L.vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p64)), -1, 0, ctypes.byref(n)) == v.VCLB_EINVAL
+    seed = (ctypes.c_double * 10)(1.0)
+    out = (ctypes.c_double * 2)()
+    h = _fake_case(v, p64)
+    assert L.vclb_adjoint_run(h, seed, None, v.DEVICE, out, None) == v.VCLB_ESTATE   # nothing recorded
+    assert L.vclb_adjoint_run(h, None, None, v.DEVICE, out, None) == v.VCLB_EINVAL
+    assert L.vclb_adjoint_record(h, None, None, v.DEVICE, 10, 0, None) == v.VCLB_EINVAL
+    L.vclb_case_destroy(h)
+    h = _fake_case(v, p64.replace(storage="fp32"))
+    phi = (ctypes.c_double * (p64.nx * p64.ny))()
+    assert L.vclb_adjoint_record(h, phi, None, v.HOST, 10, 0, None) == v.VCLB_EINVAL
+    assert L.vclb_adjoint_run(h, seed, None, v.DEVICE, out, None) == v.VCLB_EINVAL
+    L.vclb_case_destroy(h)

@@ -1,0 +1,157 @@
+"""GPU parity of the discrete adjoint (FP64 D2Q9 coupled) through the C ABI.
+
+References: the oracle's complex-step derivatives (exact derivatives of the same
+discrete map, oracle/gradient.py), central differences of the GPU forward run, and
+the exact values conservation fixes (d sum(phi) / d phi0 = 1 at every node, zero
+derivative with respect to sigma and M).  phi0 directions are r 4 phi0 (1 - phi0) with
+r standard normal from PCG64(1): changes that stay off the clipped bulk, where the map
+has a kink.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import gradient as OG
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6     # relative, on every derivative
+
+
+def _vclb():
+    from paper_2505_10899_amd import vclb
+    return vclb
+
+
+def _shear():
+    p, phi0, u0 = W.shear_droplet(nx=64, ny=32, R=8.0)
+    return "shear64x32", p, phi0, u0, 120, 16
+
+
+def _drops():
+    p, _, _ = W.two_droplets(scale=1)
+    p = p.replace(nx=64, ny=48, label_centres=[(20.0, 24.0, 0.0), (46.0, 22.0, 0.0)])
+    phi0 = W.drops_phi(p, [(20.0, 24.0, 0.0, 10.0), (46.0, 22.0, 0.0, 5.0)])
+    return "drops64x48", p, phi0, None, 60, 0
+
+
+CASES = [_shear, _drops]
+
+
+def _direction(phi0, k=0):
+    rng = np.random.Generator(np.random.PCG64(1))
+    for _ in range(k + 1):
+        r = rng.standard_normal(phi0.shape)
+    return r * 4.0 * phi0 * (1.0 - phi0)
+
+
+def _record(case_fn, every=None):
+    v = _vclb()
+    name, p, phi0, u0, n, ev = case_fn()
+    print(f"[adjoint] case {name} steps {n} every {ev if every is None else every}", flush=True)
+    c = v.Case(p)
+    c.adjoint_record(phi0, u0, nsteps=n, every=ev if every is None else every)
+    return c, p, phi0, u0, n
+
+
+def _grad(c, weights):
+    v = _vclb()
+    raw = c.reduce_raw()
+    seed = v.obs_seed(raw, c.nlabels, weights)
+    dphi, ds, dm = c.adjoint_run(seed)
+    torch.cuda.synchronize()
+    return dphi.cpu().numpy().reshape(-1), ds, dm
+
+
+def _close(got, ref, scale):
+    return abs(got - ref) <= TOL * max(abs(ref), scale)
+
+
+@pytest.mark.parametrize("case_fn", CASES)
+def test_total_phi_adjoint_is_exact(case_fn):
+    c, p, phi0, u0, n = _record(case_fn)
+    w = np.zeros((c.nlabels, 5))
+    w[:, 0] = 1.0
+    dphi, ds, dm = _grad(c, w)
+    assert np.abs(dphi - 1.0).max() < 1e-12
+    V = c.derived()[:, 0].sum()
+    assert abs(ds) < 1e-12 * V and abs(dm) < 1e-12 * V
+
+
+@pytest.mark.parametrize("case_fn", CASES)
+def test_adjoint_matches_complex_step(case_fn):
+    c, p, phi0, u0, n = _record(case_fn)
+    d = _direction(phi0).reshape(-1)
+    cs = {wrt: OG.complex_step(p, phi0, u0, n, wrt, direction=d.reshape(phi0.shape))
+          for wrt in ("sigma", "mobility", "phi0")}
+    fwd = c.derived()
+    ref_fwd = OG.derived_after(p, phi0, u0, n)
+    assert np.allclose(fwd, ref_fwd, rtol=1e-9, atol=1e-9)
+    for label in range(c.nlabels):
+        for k, name in ((0, "volume"), (1, "centroid_x"), (2, "centroid_y"), (4, "D")):
+            w = np.zeros((c.nlabels, 5))
+            w[label, k] = 1.0
+            dphi, ds, dm = _grad(c, w)
+            got = {"sigma": ds, "mobility": dm, "phi0": float(dphi @ d)}
+            # scale for derivatives that vanish (volume vs sigma, M; symmetric centroids)
+            scale = 1e-6 * abs(fwd[label, 0]) if k == 0 else 1e-3
+            for wrt, val in got.items():
+                ref = cs[wrt][label, k]
+                print(f"[adjoint] label {label} {name} d/d{wrt}: gpu {val:.12e} cs {ref:.12e}", flush=True)
+                assert _close(val, ref, scale), (label, name, wrt, val, ref)
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    w = np.array([[0.0, 0.3, 0.0, 0.0, 1.0]])
+    res = []
+    for every in (1, 7, 120):
+        c, *_ = _record(_shear, every=every)
+        res.append(_grad(c, w))
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0]) and r[1] == res[0][1] and r[2] == res[0][2]
+
+
+def test_adjoint_matches_gpu_central_differences():
+    v = _vclb()
+    name, p, phi0, u0, n, ev = _shear()
+    c, *_ = _record(_shear)
+    w = np.array([[0.0, 0.0, 0.0, 0.0, 1.0]])
+    dphi, ds, dm = _grad(c, w)
+    d = _direction(phi0, k=1)
+
+    def D_at(q, ph):
+        k = v.Case(q)
+        k.init(ph, u0)
+        k.step(n)
+        return k.derived()[0, 4]
+
+    es = 1e-5 * p.sigma
+    fd_s = (D_at(p.replace(sigma=p.sigma + es), phi0) - D_at(p.replace(sigma=p.sigma - es), phi0)) / (2 * es)
+    em = 1e-5 * p.mobility
+    fd_m = (D_at(p.replace(mobility=p.mobility + em), phi0) - D_at(p.replace(mobility=p.mobility - em), phi0)) / (2 * em)
+    e = 1e-4
+    fd_p = (D_at(p, phi0 + e * d) - D_at(p, phi0 - e * d)) / (2 * e)
+    print(f"[adjoint] FD sigma {fd_s:.10e} adj {ds:.10e}; M {fd_m:.10e} adj {dm:.10e}; "
+          f"phi0 {fd_p:.10e} adj {float(dphi @ d.reshape(-1)):.10e}", flush=True)
+    assert _close(ds, fd_s, 0.0) and _close(dm, fd_m, 0.0)
+    assert _close(float(dphi @ d.reshape(-1)), fd_p, 0.0)
+
+
+def test_autograd_function():
+    v = _vclb()
+    name, p, phi0, u0, n, ev = _shear()
+    phi = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+    sig = torch.tensor(p.sigma, dtype=torch.float64, requires_grad=True)
+    mob = torch.tensor(p.mobility, dtype=torch.float64, requires_grad=True)
+    out = v.rollout(p, phi, sig, mob, nsteps=n, every=ev, u0=u0)
+    assert out.shape == (1, 5)
+    loss = out[0, 4] + 0.3 * out[0, 1] - 0.01 * out[0, 0]
+    gphi, gs, gm = torch.autograd.grad(loss, (phi, sig, mob))
+    c, *_ = _record(_shear)
+    dphi, ds, dm = _grad(c, np.array([[-0.01, 0.3, 0.0, 0.0, 1.0]]))
+    assert np.array_equal(gphi.detach().cpu().numpy().reshape(-1), dphi)
+    assert float(gs) == ds and float(gm) == dm
+    assert np.allclose(out.detach().numpy(), OG.derived_after(p, phi0, u0, n), rtol=1e-9, atol=1e-9)

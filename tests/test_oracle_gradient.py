@@ -1,0 +1,63 @@
+"""Pins of the oracle's reference derivatives (oracle/gradient.py): complex step against
+central differences (independent arithmetic), and the exact values conservation fixes:
+the total of phi does not depend on sigma or M, and its derivative along a change d of
+phi0 is sum(d) (g = g_eq(phi0) sums to phi0, and every step keeps sum_x phi)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gradient as G
+
+
+def _shear():
+    p, phi0, u0 = W.shear_droplet(nx=64, ny=32, R=8.0)
+    return p, phi0, u0, 120
+
+
+def _drops():
+    p, phi0, u0 = W.two_droplets(scale=1)
+    p = p.replace(nx=64, ny=48, label_centres=[(20.0, 24.0, 0.0), (46.0, 22.0, 0.0)])
+    phi0 = W.drops_phi(p, [(20.0, 24.0, 0.0, 10.0), (46.0, 22.0, 0.0, 5.0)])
+    return p, phi0, None, 60
+
+
+def _direction(phi0, seed=1):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(phi0.shape) * 4.0 * phi0 * (1.0 - phi0)
+
+
+@pytest.mark.parametrize("wrt", ["sigma", "mobility"])
+def test_complex_step_matches_central_difference_parameters(wrt):
+    p, phi0, u0, n = _shear()
+    cs = G.complex_step(p, phi0, u0, n, wrt)
+    eps = 1e-5 * (p.sigma if wrt == "sigma" else p.mobility)
+    fd = G.central_difference(p, phi0, u0, n, wrt, eps)
+    # deformation D: a non-trivial derivative; relative agreement to the FD error
+    assert abs(cs[0, 4]) > 1e-3
+    assert abs(fd[0, 4] - cs[0, 4]) <= 1e-6 * abs(cs[0, 4])
+
+
+def test_complex_step_matches_central_difference_phi0():
+    p, phi0, u0, n = _shear()
+    d = _direction(phi0)
+    cs = G.complex_step(p, phi0, u0, n, "phi0", direction=d)
+    fd = G.central_difference(p, phi0, u0, n, "phi0", 1e-4, direction=d)
+    for k in (0, 1, 2, 4):                 # volume, centroid x, y, D
+        assert abs(cs[0, k]) > 1e-4
+        assert abs(fd[0, k] - cs[0, k]) <= 1e-6 * abs(cs[0, k]), (k, fd[0, k], cs[0, k])
+
+
+@pytest.mark.parametrize("case", [_shear, _drops])
+def test_total_phi_gradients_fixed_by_conservation(case):
+    p, phi0, u0, n = case()
+    total = lambda v: v[:, 0].sum()
+    V = total(G.derived_after(p, phi0, u0, n))
+    for wrt in ("sigma", "mobility"):
+        assert abs(total(G.complex_step(p, phi0, u0, n, wrt))) <= 1e-11 * V
+    d = _direction(phi0, seed=3)
+    dv = total(G.complex_step(p, phi0, u0, n, "phi0", direction=d))
+    assert abs(dv - d.sum()) <= 1e-12 * np.abs(d).sum()
+    # a direction with mass in the bulk of both phases too
+    d2 = np.cos(np.arange(phi0.size).reshape(phi0.shape) * 0.37)
+    dv2 = total(G.complex_step(p, phi0, u0, n, "phi0", direction=d2))
+    assert abs(dv2 - d2.sum()) <= 1e-11 * np.abs(d2).sum()
