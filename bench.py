@@ -1,17 +1,27 @@
-"""Throughput of the fused phase-field LB step on one MI355X.
+"""Throughput of the phase-field LB hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storages fp32,fp16s,fp64]
+                    [--no-adjoint] [--no-single] [--no-cpu-baseline]
 
-One step is one pass of the whole hot path over the workload: pull streaming, phi and
-psi with their LDS halo, the gradient/Laplacian/normal stencils, chemical potential,
-velocity and pressure, g and f collisions with the level-set source, the FP64 volume
-reductions.  The workload is timed for each storage precision (FP64, FP32 and
-FP16-shifted; arithmetic in FP64 / FP32 / FP32); `value` is the FP32-storage rate, the
-others are reported under `variants`.  Prints one JSON line.
+Headline workload: 512 independent D2Q9 coupled drop cases of uneven sizes (sides
+log-uniform in [64, 512], PCG64 seed 10899), advanced together.  One step is one pass
+of the whole hot path over every case: pull streaming with bounce-back/moving walls,
+phi and psi with their LDS halo, the gradient/Laplacian/normal stencils, chemical
+potential, velocity and pressure, g and f collisions with the level-set source, and
+the per-case FP64 volume reductions, as one work-list kernel per step; a call's steps
+are replayed from one hipGraph.  The tile is chosen by the library's autotuner.  The
+batch is timed for each storage precision; `value` is the FP32-storage rate (FP32
+arithmetic), FP16-shifted and FP64 are under `variants`.
+
+Also reported: the adjoint/forward time ratio on the 512x256 shear-flow case (4000
+steps, a checkpoint every 200), single large cases for the fused single-case kernel,
+and the CPU oracle on a sample of the batch.  Prints one JSON line on stdout.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline, FP32/FP16-store vs FP64 GPU; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch512.txt")
 
 # algorithmic HBM bytes per node update: every population read once and written once,
 # the previous phi u read and written, and (shifted storage) the phi of the writing
@@ -39,78 +50,193 @@ BYTES_PER_NODE = {
                       "fp32": 2 * 19 * 4 * 2 + 3 * 4 * 2 + 4 * 2,
                       "fp16s": 2 * 19 * 2 * 2 + 3 * 4 * 2 + 4 * 2},
 }
+KERNEL = {"fp64": "k_batch_step2d<StoreF64>", "fp32": "k_batch_step2d<StoreF32>",
+          "fp16s": "k_batch_step2d<StoreF16S>"}
+
+BATCH_DESC = ("512 independent D2Q9 coupled drop cases, sides log-uniform in [64, 512] (independent "
+              "nx, ny), radius 0.1-0.3 of the shorter side, density ratio log-uniform in [1, 100], static "
+              "periodic or shear between walls moving +-0.02 (1/2 each), W = 4, M = 0.1, sigma = 0.01, "
+              "nu = 0.1; PCG64 seed 10899; one work-list kernel per step, hipGraph replay")
 
 
-def workload(name: str, storage: str):
-    import workloads as W
-    if name == "two_droplets_x32":
-        p, phi0, u0 = W.two_droplets(storage, scale=32)
-        return p, phi0, u0, {"workload": "two static drops, D2Q9 coupled, 4096x4096 periodic "
-                                         "(the 128x128 two-drop case scaled x32: R = 768, 256), W = 4, "
-                                         "density ratio 10, M = 0.1, sigma = 0.01, nu = 0.1"}
-    if name == "rayleigh_plateau":
-        p, phi0, u0 = W.rayleigh_plateau(storage)
-        return p, phi0, u0, {"workload": "Rayleigh-Plateau column, D3Q19 coupled, 96x96x384 periodic, "
-                                         "R(z) = 16 (1 + 0.1 cos(2 pi z / 384)), W = 4, density ratio 10, "
-                                         "sigma = 0.005, nu = 0.05, M = 0.1"}
-    raise SystemExit(f"unknown workload {name}")
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_case(p, phi0, u0, steps: int, warmup: int, tile=None):
+def source_hash() -> str:
+    """Fingerprint of the HIP sources: counter figures taken on other sources are stale."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2505_10899_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(storage: str):
+    """HBM bytes per launch of the batched step from the committed rocprofv3 counter
+    summary, if it was taken on the current sources; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    v = kv.get(f"traffic_bytes_per_launch_{storage}")
+    return float(v) if v else None
+
+
+def timer():
     import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+# ----------------------------------------------------------------------------- batch
+def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_steps: int):
+    import torch
+    import workloads as W
     from paper_2505_10899_amd import vclb
-    case = vclb.Case(p, tile=tile).init(phi0, u0)
-    case.step(warmup)
+    cases, _ = W.batch_cases(512, storage=storage)
+    b = vclb.Batch([p for p, _, _ in cases])
+    for c, (p, phi0, u0) in zip(b.cases, cases):
+        c.init(phi0, u0)
+    N = b.nodes()
+    v0 = np.array([c.reduce()["sum_phi"].sum() for c in b.cases])
+    tile = b.autotune(None, steps=tune_steps)
+    log(f"batch {storage}: {len(cases)} cases, {N} nodes, autotuned tile {tile}")
+    b.step(warmup, graph=True)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = timer()
     t0 = time.perf_counter()
     e0.record(s)
-    case.step(steps)
+    b.step(steps, graph=True)
     e1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = e0.elapsed_time(e1)
-    # per-launch kernel duration: one fused kernel per step, bracketed by events
-    k = min(steps, 50)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
-    for a, b in evs:
-        a.record(s)
-        case.step(1)
-        b.record(s)
+    ms = e0.elapsed_time(e1) / steps
+    # average duration of one step kernel: an eager run of launch_steps launches on this
+    # stream (one closing fold of the reductions is included)
+    e0, e1 = timer()
+    e0.record(s)
+    b.step(launch_steps, graph=False)
+    e1.record(s)
     torch.cuda.synchronize()
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    obs = case.reduce()
-    return dict(total_ms=total_ms, wall_s=wall, kern_ms=kern_ms, tile=case.tile(),
-                sum_phi=float(np.sum(obs["sum_phi"])))
+    launch_ms = e0.elapsed_time(e1) / launch_steps
+    total = steps + warmup + launch_steps + 2 * tune_steps * 9
+    v1 = np.array([c.reduce()["sum_phi"].sum() for c in b.cases])
+    t_end = b.cases[0].time()
+    drift = float(np.max(np.abs(v1 - v0) / np.abs(v0)))
+    bpn = BYTES_PER_NODE[("D2Q9", True)][storage]
+    gbs = N * bpn / (launch_ms * 1e-3) / 1e9
+    del b
+    return dict(nodes=N, ms_per_step=ms, wall_s=wall, mlups=N / (ms * 1e-3) / 1e6, launch_ms=launch_ms,
+                bytes_per_node=bpn, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=list(tile),
+                max_rel_volume_drift=drift, drift_steps=int(t_end), approx_steps=total)
 
 
+# ----------------------------------------------------------------------------- adjoint
+def run_adjoint(nsteps: int = 4000, every: int = 200):
+    import torch
+    import workloads as W
+    from paper_2505_10899_amd import vclb
+    p, phi0, u0 = W.shear_droplet("fp64")
+    c = vclb.Case(p)
+    c.set_reduce_every(0)
+    s = torch.cuda.current_stream()
+    c.init(phi0, u0).step(50)
+    torch.cuda.synchronize()
+    c.init(phi0, u0)
+    e0, e1 = timer()
+    e0.record(s)
+    c.step(nsteps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    w = np.array([[0.0, 0.0, 0.0, 0.0, 1.0]])          # J = deformation D
+    res = None
+    for _ in range(2):                                  # the first pass allocates the store
+        e0, e1 = timer()
+        t0 = time.perf_counter()
+        c.adjoint_record(phi0, u0, nsteps=nsteps, every=every)
+        rec_s = time.perf_counter() - t0
+        seed = vclb.obs_seed(c.reduce_raw(), 1, w)
+        D = float(c.derived()[0, 4])
+        torch.cuda.synchronize()
+        e0.record(s)
+        dphi, ds, dm = c.adjoint_run(seed)
+        e1.record(s)
+        torch.cuda.synchronize()
+        res = (rec_s, e0.elapsed_time(e1), D, ds, dm, float(dphi.abs().max()))
+    rec_s, bwd_ms, D, ds, dm, gmax = res
+    nck = -(-nsteps // every)
+    return {"workload": "drop in shear, D2Q9 FP64, 512x256, walls moving -+0.02, R = 48, Ca = 0.2, Re = 0.5, "
+                        f"{nsteps} steps, a checkpoint every {every}; J = deformation D",
+            "forward_ms": round(fwd_ms, 3), "record_ms": round(rec_s * 1e3, 3), "backward_ms": round(bwd_ms, 3),
+            "ratio_backward_over_forward": round(bwd_ms / fwd_ms, 4),
+            "recomputed_steps": nsteps - nck,
+            "D": D, "dD_dsigma": ds, "dD_dM": dm, "max_abs_dD_dphi0": gmax}
+
+
+# ----------------------------------------------------------------------------- single cases
+def run_single(name: str, storage: str, steps: int, warmup: int):
+    import torch
+    import workloads as W
+    from paper_2505_10899_amd import vclb
+    if name == "two_droplets_4096":
+        p, phi0, u0 = W.two_droplets(storage, scale=32)
+    else:
+        p, phi0, u0 = W.rayleigh_plateau(storage)
+    c = vclb.Case(p).init(phi0, u0)
+    c.step(warmup)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = timer()
+    e0.record(s)
+    c.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bpn = BYTES_PER_NODE[(p.lattice, p.mode == "coupled")][storage]
+    gbs = p.n_nodes * bpn / (ms * 1e-3) / 1e9
+    return {"nodes": p.n_nodes, "MLUPS": round(p.n_nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "achieved_GBs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_node": bpn, "tile": list(c.tile())}
+
+
+# ----------------------------------------------------------------------------- CPU oracle
 def cpu_baseline(budget_s: float = 15.0):
-    """The CPU oracle on a bounded sample of the same kind of work: the two-drop
-    case on a 256x256 box, as many steps as fit the budget, BLAS limited to 1 thread."""
+    """The CPU oracle on a bounded sample of the batch: its cases in order, 3 steps each
+    after init, until the budget is spent; BLAS limited to 1 thread."""
     import workloads as W
     from oracle import Model
     try:
         from threadpoolctl import threadpool_limits
     except Exception:       # pragma: no cover
         threadpool_limits = None
-    p, phi0, _ = W.two_droplets("fp64", scale=2)
+    cases, _ = W.batch_cases(512, storage="fp64")
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    updates, dt, used = 0, 0.0, 0
     try:
-        m = Model(p).init(phi0)
-        m.step(2)
-        n = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < budget_s:
-            m.step(5)
-            n += 5
-        dt = time.perf_counter() - t0
+        for p, phi0, u0 in cases:
+            m = Model(p).init(phi0, u0)
+            t0 = time.perf_counter()
+            m.step(3)
+            dt += time.perf_counter() - t0
+            updates += 3 * p.n_nodes
+            used += 1
+            if dt > budget_s:
+                break
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
-    return {"value": round(p.n_nodes * n / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"numpy FP64 oracle, two-drop case 256x256 (D2Q9 coupled), {n} steps in {dt:.1f} s, "
-                      f"single thread (BLAS limited to 1 thread); host has {os.cpu_count()} logical CPUs"}
+    return {"value": round(updates / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"numpy FP64 oracle on the first {used} of the 512 batch cases, 3 steps each "
+                      f"({updates} node updates in {dt:.1f} s of step time), single thread (BLAS limited "
+                      f"to 1 thread); host has {os.cpu_count()} logical CPUs"}
 
 
 def main(argv=None):
@@ -118,10 +244,12 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="two_droplets_x32")
-    ap.add_argument("--storages", default="fp32,fp64,fp16s")
+    ap.add_argument("--storages", default="fp32,fp16s,fp64")
+    ap.add_argument("--launch-steps", type=int, default=50)
+    ap.add_argument("--tune-steps", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", default=None, help="bx,ty[,by3]: launch shape of the fused step")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (a known-size reference "
                          "for the HBM byte counters)")
@@ -131,43 +259,51 @@ def main(argv=None):
               "(run with --gpus 1).", file=sys.stderr)
         return 2
     import torch
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
     storages = a.storages.split(",")
     res = {}
-    meta = None
     for st in storages:
-        p, phi0, u0, meta = workload(a.workload, st)
-        print(f"[bench] {a.workload} {st}: {p.n_nodes} nodes, {a.warmup} warmup + {a.steps} timed steps",
-              file=sys.stderr, flush=True)
-        tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
-        r = time_case(p, phi0, u0, a.steps, a.warmup, tile)
-        coupled = p.mode == "coupled"
-        bpn = BYTES_PER_NODE[(p.lattice, coupled)][st]
-        ms = r["total_ms"] / a.steps
-        mlups = p.n_nodes / (ms * 1e-3) / 1e6
-        gbs = p.n_nodes * bpn / (r["kern_ms"] * 1e-3) / 1e9
-        res[st] = dict(mlups=mlups, ms_per_step=ms, kernel_ms=r["kern_ms"], bytes_per_node=bpn,
-                       achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=r["tile"], nodes=p.n_nodes)
-        print(f"[bench] {st}: {mlups:.0f} MLUPS, {ms:.3f} ms/step, kernel {r['kern_ms']:.3f} ms, "
-              f"{gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM peak), tile {r['tile']}",
-              file=sys.stderr, flush=True)
+        log(f"batch {st}: {a.warmup} warmup + {a.steps} timed steps")
+        r = run_batch(st, a.steps, a.warmup, a.launch_steps, a.tune_steps)
+        res[st] = r
+        log(f"batch {st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, launch {r['launch_ms']:.3f} ms, "
+            f"{r['achieved_GBs']:.0f} GB/s ({100 * r['frac']:.1f}% of HBM peak), drift {r['max_rel_volume_drift']:.2e}")
     head = "fp32" if "fp32" in res else storages[0]
     h = res[head]
+    traffic = recorded_traffic(head)
     out = {
         "metric": METRIC, "value": round(h["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(h["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if head == "fp64" else "f32", "data": "synthetic",
-        "config": dict(meta, storage=head, nodes=h["nodes"], tile=list(h["tile"])),
+        "config": {"workload": BATCH_DESC, "storage": head, "cases": 512, "nodes": h["nodes"],
+                   "tile": h["tile"]},
         "roofline": {"bound": "hbm", "achieved": round(h["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(h["frac"], 4), "traffic": None,
-                     "bytes_per_node": h["bytes_per_node"], "kernel_ms": round(h["kernel_ms"], 5)},
+                     "unit": "GB/s", "frac": round(h["frac"], 4), "traffic": traffic,
+                     "kernel": KERNEL[head], "bytes_per_node": h["bytes_per_node"],
+                     "bytes_per_launch": h["bytes_per_node"] * h["nodes"],
+                     "launch_ms": round(h["launch_ms"], 5)},
         "variants": {st: {"MLUPS": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
-                          "kernel_ms": round(v["kernel_ms"], 5), "achieved_GBs": round(v["achieved_GBs"], 1),
+                          "launch_ms": round(v["launch_ms"], 5), "achieved_GBs": round(v["achieved_GBs"], 1),
                           "frac_hbm_peak": round(v["frac"], 4), "bytes_per_node": v["bytes_per_node"],
+                          "tile": v["tile"], "max_rel_volume_drift": v["max_rel_volume_drift"],
+                          "drift_over_steps": v["drift_steps"],
                           "speedup_vs_fp64": (round(v["mlups"] / res["fp64"]["mlups"], 3) if "fp64" in res else None)}
                      for st, v in res.items()},
     }
+    if not a.no_adjoint:
+        log("adjoint: 512x256 shear, 4000 steps, checkpoint every 200")
+        out["adjoint"] = run_adjoint()
+        log(f"adjoint: backward/forward = {out['adjoint']['ratio_backward_over_forward']}")
+    if not a.no_single:
+        single = {}
+        for name, st in (("two_droplets_4096", "fp32"), ("two_droplets_4096", "fp64"),
+                         ("two_droplets_4096", "fp16s"), ("rayleigh_plateau_96x96x384", "fp32")):
+            single[f"{name}_{st}"] = run_single(name, st, min(a.steps, 100), 10)
+            log(f"single {name} {st}: {single[f'{name}_{st}']}")
+        out["single_case"] = single
     if a.copy_probe:
         nbytes = a.copy_probe << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -176,7 +312,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nbytes
     if not a.no_cpu_baseline:
-        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        log("CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
     return 0

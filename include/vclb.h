@@ -239,13 +239,19 @@ int vclb_adjoint_record(vclb_case* c, const double* phi0, const double* u0, int 
 /* Backward pass of the recorded run for J = sum_l seed[10 l] sum phi + seed[10 l + 1..3] .
    sum phi d + seed[10 l + 4..9] . sum phi dd (moments of the final state, labels as in
    vclb_reduce; seed is host memory, see vclb_obs_seed).  Each segment between
-   checkpoints is recomputed with the forward step and then run backward.  Writes dJ/dphi0
+   checkpoints is recomputed with the forward step and then run backward.
+   normal_tau >= 0: the unit normal n = grad psi / |grad psi| of Eq. 32 is differentiated
+   only where |grad psi| >= normal_tau and held fixed elsewhere.  Away from the interface
+   psi saturates, |grad psi| falls to rounding level and the exact derivative of n (gain
+   ~ lambda / |grad psi| per step) grows without bound over long runs; 0.3 keeps every
+   node of the interface region (|grad psi| = 1 there), 0 gives the exact derivative of
+   the discrete map.  Writes dJ/dphi0
    to dphi0 (N doubles, ptr_kind; NULL: not returned) and (dJ/dsigma, dJ/dM) to dparams
    (2 doubles, host; NULL: not returned).  M acts through the rates of g left at their
    default 1 / tau_g.  The case state is left unchanged.  Synchronises the stream.
    VCLB_ESTATE without a prior vclb_adjoint_record. */
-int vclb_adjoint_run(vclb_case* c, const double* seed, double* dphi0, int ptr_kind, double* dparams,
-                     void* stream);
+int vclb_adjoint_run(vclb_case* c, const double* seed, double normal_tau, double* dphi0, int ptr_kind,
+                     double* dparams, void* stream);
 
 /* ---------------------------------------------------------------- batches of cases */
 /* Many independent coupled D2Q9 cases of uneven sizes (one storage precision), advanced

@@ -49,10 +49,12 @@ class Model:
 
     ``sigma`` and ``mobility`` may be overridden (e.g. by complex numbers for
     complex-step derivatives); everything else comes from the ``CaseParams``.
+    ``normal_tau`` only affects complex-step derivatives: see ``unit_normal``.
     """
 
-    def __init__(self, p, dtype=np.float64, sigma=None, mobility=None):
+    def __init__(self, p, dtype=np.float64, sigma=None, mobility=None, normal_tau=0.0):
         self.p = p
+        self.normal_tau = float(normal_tau)
         self.lat = lat = lattice_for(p.lattice)
         self.dtype = dtype
         self.cs2 = lat.cs2
@@ -198,9 +200,19 @@ class Model:
 
     def unit_normal(self, gpsi):
         """grad psi / |grad psi|, with |grad psi| = sqrt(|grad psi|^2 + eps_n^2) (a reading: the
-        paper does not say what to do where psi is flat)."""
+        paper does not say what to do where psi is flat).
+
+        With complex arrays and normal_tau > 0, the normal is held at its real value (no
+        derivative) where |Re grad psi| < normal_tau: away from the interface psi
+        saturates, |grad psi| falls towards eps_n, and the derivative of n there, with
+        gain lambda / |grad psi| per step, is rounding-driven and grows without bound
+        over long runs.  The value of n is unchanged; only derivatives see the cut."""
         n2 = (gpsi * gpsi).sum(axis=0)
-        return gpsi / np.sqrt(n2 + self.p.eps_n ** 2)
+        n = gpsi / np.sqrt(n2 + self.p.eps_n ** 2)
+        if self.normal_tau > 0.0 and np.iscomplexobj(n):
+            mag2 = (np.real(gpsi) ** 2).sum(axis=0)
+            n = np.where(mag2[None] < self.normal_tau ** 2, np.real(n) + 0j, n)
+        return n
 
     def f_equilibrium(self, press, rho, u):
         """Eq. 22: f0 = (w0 - 1) p / cs^2 + rho s0(u); fi = wi p / cs^2 + rho si(u)."""

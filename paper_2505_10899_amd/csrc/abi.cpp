@@ -1384,9 +1384,10 @@ int vclb_adjoint_record(vclb_case* c, const double* phi0, const double* u0, int 
   return VCLB_OK;
 }
 
-int vclb_adjoint_run(vclb_case* c, const double* seed, double* dphi0, int ptr_kind, double* dparams,
-                     void* stream) {
+int vclb_adjoint_run(vclb_case* c, const double* seed, double normal_tau, double* dphi0, int ptr_kind,
+                     double* dparams, void* stream) {
   if (!c || !seed) return fail(VCLB_EINVAL, "case or seed is NULL");
+  if (!(normal_tau >= 0.0) || !std::isfinite(normal_tau)) return fail(VCLB_EINVAL, "normal_tau must be >= 0");
   if (int rc = adj_check_case(c)) return rc;
   if (!c->adj) return fail(VCLB_ESTATE, "adjoint run before vclb_adjoint_record");
   if (dphi0 && ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
@@ -1413,6 +1414,7 @@ int vclb_adjoint_run(vclb_case* c, const double* seed, double* dphi0, int ptr_ki
   a.seed = dptr(st.seed);
   a.beta4_per_sigma = 48.0 / c->p.W;
   a.kappa_per_sigma = 1.5 * c->p.W;
+  a.normal_tau2 = normal_tau * normal_tau;
   a.mobility_rows = 0;
   for (int k = 0; k < 9; ++k)
     if (c->p.s_g[k] == 0.0 && vclb::D2Q9::g_flux_row[k]) a.mobility_rows |= 1u << k;

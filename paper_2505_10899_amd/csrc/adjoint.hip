@@ -15,6 +15,11 @@
 //                  Accumulates dJ/dsigma and dJ/dM per workgroup.
 //   k_adj_stencil  per node y: the transposed stencils (walls mirror the edge row),
 //                  dpsi/dphi from Eq. 37, giving lphi of step t.
+// Away from the interface psi saturates and |grad psi| falls to rounding level; the
+// derivative of the unit normal there has a gain of order lambda / |grad psi| per step
+// and grows without bound, so the normal is differentiated only where
+// |grad psi| >= normal_tau (psi is a signed distance, |grad psi| = 1, across the
+// interface); normal_tau = 0 gives the exact derivative of the discrete map.
 // The initial state (g = g_eq(phi0), f = f_eq(0, rho(phi0), u0), Jprev = phi0 u0) has its
 // own reverse pair giving dJ/dphi0.
 #include <hip/hip_runtime.h>
@@ -244,7 +249,10 @@ __global__ void __launch_bounds__(256) k_adj_local(DC c, AdjArgs a) {
     lJx += R(3) * lVx + a.lJ_in[n];
     lJy += R(3) * lVy + a.lJ_in[c.n + n];
     const R lAn = lVx * nxn + lVy * nyn;
-    const R lgsx = An * (lVx - nxn * lAn) / r, lgsy = An * (lVy - nyn * lAn) / r;
+    // where psi has saturated (|grad psi| below the cut) the normal is held fixed
+    const bool n_live = !(gsx * gsx + gsy * gsy < a.normal_tau2);
+    const R lgsx = n_live ? An * (lVx - nxn * lAn) / r : R(0);
+    const R lgsy = n_live ? An * (lVy - nyn * lAn) / r : R(0);
 
     // ---- J = phi u
     lphi += lJx * ux + lJy * uy;

@@ -23,6 +23,7 @@ struct AdjArgs {
   double beta4_per_sigma;   // 4 beta / sigma = 48 / W
   double kappa_per_sigma;   // kappa / sigma = 3 W / 2
   unsigned mobility_rows;   // bit k: s_k^g is the default 1 / tau_g
+  double normal_tau2;       // n is held fixed (no derivative) where |grad psi|^2 < normal_tau2
 };
 
 long adj_blocks(long n);

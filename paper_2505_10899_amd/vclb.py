@@ -101,12 +101,13 @@ _SIGS = [
     ("vclb_adjoint_bytes", ctypes.c_int, [_P(Params), ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_size_t)]),
     ("vclb_adjoint_record", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                            ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
-    ("vclb_adjoint_run", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_void_p, ctypes.c_int,
-                                        _P(ctypes.c_double), ctypes.c_void_p]),
+    ("vclb_adjoint_run", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_double, ctypes.c_void_p,
+                                        ctypes.c_int, _P(ctypes.c_double), ctypes.c_void_p]),
 ]
 
 DERIVED = ("volume", "centroid_x", "centroid_y", "centroid_z", "D")
 SEED_FIELDS = 10
+NORMAL_TAU = 0.3   # the unit normal is differentiated where |grad psi| >= NORMAL_TAU
 
 
 def lib():
@@ -321,16 +322,16 @@ class Case:
                                         int(nsteps), int(every), _stream_handle(stream)))
         return self
 
-    def adjoint_run(self, seed, stream=None):
+    def adjoint_run(self, seed, normal_tau: float = NORMAL_TAU, stream=None):
         """Backward pass for the moment weights `seed` ((labels, 10) array, see
-        obs_seed).  Returns (dJ/dphi0 as a float64 device tensor shaped (nz, ny, nx),
-        dJ/dsigma, dJ/dM)."""
+        obs_seed), with the unit normal differentiated where |grad psi| >= normal_tau.
+        Returns (dJ/dphi0 as a float64 device tensor shaped (nz, ny, nx), dJ/dsigma, dJ/dM)."""
         sd = np.ascontiguousarray(seed, dtype=np.float64).reshape(-1)
         if sd.size != self.nlabels * SEED_FIELDS:
             raise VclbError(VCLB_EINVAL, "seed must hold 10 weights per label")
         dphi = torch.empty(self.n, dtype=torch.float64, device=self.device)
         out = (ctypes.c_double * 2)()
-        check(lib().vclb_adjoint_run(self.h, sd.ctypes.data_as(_P(ctypes.c_double)),
+        check(lib().vclb_adjoint_run(self.h, sd.ctypes.data_as(_P(ctypes.c_double)), float(normal_tau),
                                      ctypes.c_void_p(dphi.data_ptr()), DEVICE, out, _stream_handle(stream)))
         return dphi.reshape(self.p.nz, self.p.ny, self.p.nx), out[0], out[1]
 
@@ -397,12 +398,12 @@ class _Rollout(torch.autograd.Function):
     (phi0, sigma, mobility); the backward pass is the library's discrete adjoint."""
 
     @staticmethod
-    def forward(ctx, phi0, sigma, mobility, p, nsteps, every, u0, device):
+    def forward(ctx, phi0, sigma, mobility, p, nsteps, every, u0, device, normal_tau):
         q = p.replace(sigma=float(sigma), mobility=float(mobility))
         case = Case(q, device=device)
         case.adjoint_record(phi0, u0, nsteps=nsteps, every=every)
         raw = case.reduce_raw()
-        ctx.case, ctx.raw = case, raw
+        ctx.case, ctx.raw, ctx.tau = case, raw, normal_tau
         ctx.shape = phi0.shape
         return torch.as_tensor(obs_derived(raw, case.nlabels), dtype=torch.float64)
 
@@ -410,17 +411,17 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, grad_out):
         case = ctx.case
         seed = obs_seed(ctx.raw, case.nlabels, grad_out.detach().cpu().numpy())
-        dphi, dsig, dmob = case.adjoint_run(seed)
+        dphi, dsig, dmob = case.adjoint_run(seed, normal_tau=ctx.tau)
         return (dphi.reshape(ctx.shape), torch.tensor(dsig, dtype=torch.float64),
-                torch.tensor(dmob, dtype=torch.float64), None, None, None, None, None)
+                torch.tensor(dmob, dtype=torch.float64), None, None, None, None, None, None)
 
 
 def rollout(p, phi0: torch.Tensor, sigma: torch.Tensor, mobility: torch.Tensor, nsteps: int, every: int = 0,
-            u0=None, device="cuda") -> torch.Tensor:
+            u0=None, device="cuda", normal_tau: float = NORMAL_TAU) -> torch.Tensor:
     """(labels, 5) tensor of volume, centroid offset (x, y, z) and deformation D after
     nsteps FP64 D2Q9 coupled steps from phi0, differentiable in phi0, sigma and mobility
-    (checkpoint every `every` steps; 0: ceil(sqrt(nsteps)))."""
-    return _Rollout.apply(phi0, sigma, mobility, p, int(nsteps), int(every), u0, device)
+    (checkpoint every `every` steps; 0: ceil(sqrt(nsteps)); normal_tau: see adjoint_run)."""
+    return _Rollout.apply(phi0, sigma, mobility, p, int(nsteps), int(every), u0, device, float(normal_tau))
 
 
 def _obs_to_dict(arr, n) -> dict:

@@ -149,12 +149,14 @@ def test_adjoint_entry_points_reject_without_gpu():
     seed = (ctypes.c_double * 10)(1.0)
     out = (ctypes.c_double * 2)()
     h = _fake_case(v, p64)
-    assert L.vclb_adjoint_run(h, seed, None, v.DEVICE, out, None) == v.VCLB_ESTATE   # nothing recorded
-    assert L.vclb_adjoint_run(h, None, None, v.DEVICE, out, None) == v.VCLB_EINVAL
+    assert L.vclb_adjoint_run(h, seed, 0.1, None, v.DEVICE, out, None) == v.VCLB_ESTATE   # nothing recorded
+    assert L.vclb_adjoint_run(h, None, 0.1, None, v.DEVICE, out, None) == v.VCLB_EINVAL
+    assert L.vclb_adjoint_run(h, seed, -1.0, None, v.DEVICE, out, None) == v.VCLB_EINVAL
+    assert L.vclb_adjoint_run(h, seed, float("nan"), None, v.DEVICE, out, None) == v.VCLB_EINVAL
     assert L.vclb_adjoint_record(h, None, None, v.DEVICE, 10, 0, None) == v.VCLB_EINVAL
     L.vclb_case_destroy(h)
     h = _fake_case(v, p64.replace(storage="fp32"))
     phi = (ctypes.c_double * (p64.nx * p64.ny))()
     assert L.vclb_adjoint_record(h, phi, None, v.HOST, 10, 0, None) == v.VCLB_EINVAL
-    assert L.vclb_adjoint_run(h, seed, None, v.DEVICE, out, None) == v.VCLB_EINVAL
+    assert L.vclb_adjoint_run(h, seed, 0.1, None, v.DEVICE, out, None) == v.VCLB_EINVAL
     L.vclb_case_destroy(h)

@@ -5,7 +5,8 @@ discrete map, oracle/gradient.py), central differences of the GPU forward run, a
 the exact values conservation fixes (d sum(phi) / d phi0 = 1 at every node, zero
 derivative with respect to sigma and M).  phi0 directions are r 4 phi0 (1 - phi0) with
 r standard normal from PCG64(1): changes that stay off the clipped bulk, where the map
-has a kink.
+has a kink.  Both sides differentiate the unit normal only where |grad psi| >= 0.3
+(the default cut; tau = 0 is the exact derivative, checked on the small case).
 """
 import sys
 
@@ -155,3 +156,83 @@ def test_autograd_function():
     assert np.array_equal(gphi.detach().cpu().numpy().reshape(-1), dphi)
     assert float(gs) == ds and float(gm) == dm
     assert np.allclose(out.detach().numpy(), OG.derived_after(p, phi0, u0, n), rtol=1e-9, atol=1e-9)
+
+
+def test_exact_derivative_without_the_normal_cut():
+    c, p, phi0, u0, n = _record(_shear)
+    d = _direction(phi0).reshape(-1)
+    w = np.array([[0.0, 0.0, 0.0, 0.0, 1.0]])
+    seed = _vclb().obs_seed(c.reduce_raw(), 1, w)
+    dphi, ds, dm = c.adjoint_run(seed, normal_tau=0.0)
+    dphi = dphi.cpu().numpy().reshape(-1)
+    for wrt, val in (("sigma", ds), ("mobility", dm), ("phi0", float(dphi @ d))):
+        ref = OG.complex_step(p, phi0, u0, n, wrt, direction=d.reshape(phi0.shape), tau=0.0)[0, 4]
+        print(f"[adjoint] exact d D/d{wrt}: gpu {val:.12e} cs {ref:.12e}", flush=True)
+        assert _close(val, ref, 1e-3)
+
+
+def test_medium_case_matches_complex_step():
+    """128x64 shear, 200 steps: the size at which the exact derivative is already dominated
+    by bulk terms (so the normal cut matters)."""
+    v = _vclb()
+    p, phi0, u0 = W.shear_droplet(nx=128, ny=64, R=16.0)
+    n = 200
+    print("[adjoint] case shear128x64 steps 200", flush=True)
+    c = v.Case(p)
+    c.adjoint_record(phi0, u0, nsteps=n, every=0)
+    d = _direction(phi0).reshape(-1)
+    dphi, ds, dm = _grad(c, np.array([[0.0, 0.0, 0.0, 0.0, 1.0]]))
+    for wrt, val in (("sigma", ds), ("mobility", dm), ("phi0", float(dphi @ d))):
+        ref = OG.complex_step(p, phi0, u0, n, wrt, direction=d.reshape(phi0.shape))[0, 4]
+        print(f"[adjoint] shear128x64 d D/d{wrt}: gpu {val:.12e} cs {ref:.12e}", flush=True)
+        assert _close(val, ref, 1e-3)
+
+
+def test_full_shear_case_against_central_differences():
+    """The 512x256 shear case over 4000 steps with a checkpoint every 200: dD/dsigma, dD/dM
+    and dD/dphi0 along 10 directions (PCG64(1)) against central differences of the GPU
+    forward run.  At this length the differences scatter with their step e (rounding
+    and truncation; e.g. 1e-4 relative for dD/dM over e = 3e-4..1e-2), so each adjoint
+    value is compared with the median over several steps, within twice their spread plus
+    1e-6 of the largest derivative of its kind."""
+    v = _vclb()
+    p, phi0, u0 = W.shear_droplet("fp64")
+    n, every = 4000, 200
+    print("[adjoint] case shear512x256 steps 4000 every 200", flush=True)
+    c = v.Case(p)
+    c.set_reduce_every(0)
+    c.adjoint_record(phi0, u0, nsteps=n, every=every)
+    dphi, ds, dm = _grad(c, np.array([[0.0, 0.0, 0.0, 0.0, 1.0]]))
+    assert np.isfinite(dphi).all()
+
+    def D_at(q, ph):
+        k = v.Case(q)
+        k.set_reduce_every(0)
+        k.init(ph, u0)
+        k.step(n)
+        return k.derived()[0, 4]
+
+    def central(at, steps):
+        vals = np.array([(at(e) - at(-e)) / (2 * e) for e in steps])
+        return float(np.median(vals)), float(vals.max() - vals.min())
+
+    rel = (1e-2, 3e-3, 1e-3, 3e-4)
+    fd_s, sp_s = central(lambda e: D_at(p.replace(sigma=p.sigma * (1 + e)), phi0), rel)
+    fd_s, sp_s = fd_s / p.sigma, sp_s / p.sigma
+    fd_m, sp_m = central(lambda e: D_at(p.replace(mobility=p.mobility * (1 + e)), phi0), rel)
+    fd_m, sp_m = fd_m / p.mobility, sp_m / p.mobility
+    print(f"[adjoint] C4 dD/dsigma adj {ds:.10e} fd {fd_s:.10e} (spread {sp_s:.1e}); "
+          f"dD/dM adj {dm:.10e} fd {fd_m:.10e} (spread {sp_m:.1e})", flush=True)
+    assert abs(ds - fd_s) <= 2 * sp_s + 1e-6 * abs(fd_s)
+    assert abs(dm - fd_m) <= 2 * sp_m + 1e-6 * abs(fd_m)
+    rng = np.random.Generator(np.random.PCG64(1))
+    rows = []
+    for k in range(10):
+        d = rng.standard_normal(phi0.shape) * 4.0 * phi0 * (1.0 - phi0)
+        fd, sp = central(lambda e: D_at(p, phi0 + e * d), (1e-2, 1e-3, 1e-4))
+        adj = float(dphi @ d.reshape(-1))
+        rows.append((adj, fd, sp))
+        print(f"[adjoint] C4 direction {k}: adj {adj:.10e} fd {fd:.10e} spread {sp:.1e}", flush=True)
+    scale = max(abs(r[1]) for r in rows)
+    for adj, fd, sp in rows:
+        assert abs(adj - fd) <= 2 * sp + 1e-6 * scale
