@@ -272,8 +272,10 @@ int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out);
 /* Total nodes of all cases. */
 int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
 
-/* Tile of the batched step: bx in {64, 128, 256} columns, ty >= 8 rows per work item.
-   get_tile also returns the number of resident workgroups launched per step. */
+/* Launch shape of the batched step: bx in {64, 128, 256} lanes per workgroup, and work
+   items of about ty * 256 nodes (whole rows of one case; ty in 1..1024).  Each item is
+   marched in the row-major order of its rows, so that cases of any width keep every
+   lane busy.  get_tile also returns the number of resident workgroups launched per step. */
 int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty);
 int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks);
 

@@ -807,7 +807,7 @@ struct vclb_batch {
   size_t items_cap = 0;
   std::vector<int4> items;
   std::vector<int2> case_items;
-  int bx = 128, ty = 32, blocks = 0;
+  int bx = 128, ty = 32, blocks = 0, cap = 0, lag = 1;
   int reduce_every = 1;
   int64_t nodes = 0;
   bool pend = false;
@@ -831,27 +831,41 @@ int dispatch_storage(int storage, Fn&& fn) {
 }
 
 // work items of a tile shape: per case, bands of ty rows, x strips of bx columns fastest
-void build_items(vclb_batch* b, int bx, int ty, std::vector<int4>& items, std::vector<int2>& ci) {
+// Work items of the flattened batched march: bands of whole rows of one case holding
+// about ty * 256 nodes each, case-major.
+void build_items(vclb_batch* b, int ty, std::vector<int4>& items, std::vector<int2>& ci) {
   items.clear();
   ci.assign(size_t(b->n), int2{0, 0});
   for (int k = 0; k < b->n; ++k) {
     const vclb_params& p = b->cases[size_t(k)]->p;
+    const int P = p.nx + 2;
+    const int rows = std::max(1, std::min(p.ny, (ty * 256 + P / 2) / P));
     const int first = int(items.size());
-    for (int y0 = 0; y0 < p.ny; y0 += ty)
-      for (int x0 = 0; x0 < p.nx; x0 += bx) items.push_back(int4{k, x0, y0, std::min(y0 + ty, p.ny)});
+    for (int y0 = 0; y0 < p.ny; y0 += rows) items.push_back(int4{k, 0, y0, std::min(y0 + rows, p.ny)});
     ci[size_t(k)] = int2{first, int(items.size()) - first};
   }
 }
 
 int batch_set_tile(vclb_batch* b, int bx, int ty) {
-  if (bx < 64 || bx > 256 || bx % 64 != 0 || ty < 8) return fail(VCLB_EINVAL, "bad batch tile (bx in 64..256, multiple of 64; ty >= 8)");
+  if (bx < 64 || bx > 256 || bx % 64 != 0 || ty < 1 || ty > 1024)
+    return fail(VCLB_EINVAL, "bad batch tile (bx in 64..256, multiple of 64; ty in 1..1024)");
+  int pmax = 0, lag = 1;
+  for (const vclb_case* c : b->cases) {
+    const int l = vclb::flat_lag(c->p.nx + 2, bx);
+    if (l == 0) return fail(VCLB_EINVAL, "a case is too wide for the batched step with this many lanes");
+    lag = std::max(lag, l);
+    pmax = std::max(pmax, c->p.nx + 2);
+  }
+  const int cap = vclb::flat_ring_cap(pmax, bx, lag);
+  const size_t lds = dispatch_storage(b->storage, [&](auto st) { return int(vclb::batch_lds_bytes<decltype(st)>(cap)); });
+  if (lds > 64 * 1024) return fail(VCLB_EINVAL, "a case is too wide for the batched step with this tile");
   std::vector<int4> items;
   std::vector<int2> ci;
-  build_items(b, bx, ty, items, ci);
+  build_items(b, ty, items, ci);
   if (items.size() > b->items_cap) return fail(VCLB_EINVAL, "too many work items");
   HIP_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_case_items, ci.data(), ci.size() * sizeof(int2), hipMemcpyHostToDevice));
-  int per_cu = dispatch_storage(b->storage, [&](auto st) { return vclb::batch_max_blocks_per_cu<decltype(st)>(bx); });
+  int per_cu = dispatch_storage(b->storage, [&](auto st) { return vclb::batch_max_blocks_per_cu<decltype(st)>(bx, cap, lag); });
   int dev = 0, ncu = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -859,6 +873,8 @@ int batch_set_tile(vclb_batch* b, int bx, int ty) {
   b->blocks = int(std::min<long>(long(items.size()), long(per_cu) * ncu));
   b->bx = bx;
   b->ty = ty;
+  b->cap = cap;
+  b->lag = lag;
   b->items = std::move(items);
   b->case_items = std::move(ci);
   return VCLB_OK;
@@ -876,6 +892,8 @@ vclb::BatchArgs batch_args(const vclb_batch* b, int64_t t, int reduce) {
   a.pend_step = long(b->pend_step);
   a.t = long(t);
   a.reduce = reduce;
+  a.cap = b->cap;
+  a.lag = b->lag;
   return a;
 }
 
@@ -929,6 +947,8 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
       return fail(VCLB_EINVAL, "batches hold coupled D2Q9 cases");
     if (cases[k].storage != cases[0].storage) return fail(VCLB_EINVAL, "every case of a batch has one storage");
     if (cases[k].nlabels > 1) return fail(VCLB_EINVAL, "batched cases have one observation label");
+    if (double(cases[k].nx + 2) * (cases[k].ny + 2) >= double(1 << 24))
+      return fail(VCLB_EINVAL, "batched cases hold fewer than 2^24 padded nodes");
   }
   vclb_batch* b = new (std::nothrow) vclb_batch();
   if (!b) return fail(VCLB_ENOMEM, "host allocation");
@@ -944,7 +964,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
   for (int k = 0; k < ncases; ++k) {
     off[size_t(k)] = total;
     total += align_up(layout_for(cases[k]).total);
-    cap += size_t((cases[k].nx + 63) / 64) * size_t((cases[k].ny + 7) / 8);
+    cap += size_t(cases[k].ny);   // at most one work item per row
     b->nodes += int64_t(cases[k].nx) * cases[k].ny;
   }
   const size_t o_cases = total;
@@ -1008,7 +1028,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
     vclb_batch_destroy(b);
     return hip_fail(e, "batch set-up");
   }
-  int rc = batch_set_tile(b, 128, 32);
+  int rc = batch_set_tile(b, 256, 32);
   if (rc) {
     vclb_batch_destroy(b);
     return rc;
@@ -1149,10 +1169,10 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   struct Cand { int bx, ty; float ms; };
   std::vector<Cand> cands;
   for (int bx : {64, 128, 256})
-    for (int ty : {16, 32, 64}) cands.push_back({bx, ty, -1.0f});
+    for (int ty : {8, 16, 32, 64}) cands.push_back({bx, ty, -1.0f});
   int rc = VCLB_OK;
   for (Cand& cd : cands) {
-    if ((rc = batch_set_tile(b, cd.bx, cd.ty))) break;
+    if (batch_set_tile(b, cd.bx, cd.ty) == VCLB_EINVAL) continue;   // shape not valid for these cases
     if ((rc = batch_enqueue(b, 1, false, s))) break;
     HIP_TRY(hipEventRecord(e0, s));
     for (vclb_case* c : b->cases) c->t_host = t0 + 1;
@@ -1175,9 +1195,10 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  Cand best = cands[0];
+  Cand best{0, 0, -1.0f};
   for (const Cand& cd : cands)
-    if (cd.ms > 0 && cd.ms < best.ms) best = cd;
+    if (cd.ms > 0 && (best.ms < 0 || cd.ms < best.ms)) best = cd;
+  if (best.ms < 0) return fail(VCLB_EINVAL, "no batched launch shape fits these cases");
   rc = batch_set_tile(b, best.bx, best.ty);
   if (rc) return rc;
   if (cache_path) {

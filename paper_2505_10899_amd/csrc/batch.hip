@@ -1,8 +1,8 @@
 // Many independent D2Q9 cases of uneven sizes advanced by one work-list kernel per step.
 //
-// A fixed number of resident workgroups strides over the work items (case, x strip,
-// band of rows) of all cases; each item is the same tile march as the single-case
-// fused step (step2d_tile).  The n launches of a call are captured in one hipGraph and
+// A fixed number of resident workgroups strides over the work items (case, band of
+// rows) of all cases; each item is a flattened march over the band (step2d_flat), so
+// that cases of any width keep every lane busy.  The n launches of a call are captured in one hipGraph and
 // replayed as one launch.  Per-case volume reductions: every item writes its partial
 // sums; the next launch (or a fold-only launch at the end of a call) sums each case's
 // items in a fixed order into that case's observation history.
@@ -10,7 +10,7 @@
 
 #include "devcase.hpp"
 #include "launch.hpp"
-#include "step2d.hpp"
+#include "flat2d.hpp"
 
 namespace vclb {
 
@@ -35,8 +35,9 @@ __device__ __forceinline__ void fold_case(const DevCase<D2Q9, St>& c, const Batc
   __syncthreads();
 }
 
-template <class St>
-__global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4)
+// the lag-3 FIFO of FP32 values needs a little more than 128 VGPRs: 3 waves per SIMD
+template <class St, int DL>
+__global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : (DL == 3 ? 3 : 4))
     k_batch_step2d(const DevCase<D2Q9, St>* __restrict__ cases, BatchArgs a) {
   extern __shared__ unsigned char smem_raw[];
   if (a.pend)
@@ -48,7 +49,7 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4)
     const int it = base + slot;
     if (it >= a.nitems) break;
     const int4 w = a.items[it];
-    step2d_tile<St, true>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems, it, smem_raw);
+    step2d_flat<St, DL>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);
     __syncthreads();
   }
 }
@@ -59,10 +60,17 @@ __global__ void __launch_bounds__(256) k_batch_fold(const DevCase<D2Q9, St>* __r
 }
 
 template <class St>
+size_t batch_lds_bytes(int cap) {
+  return size_t(2) * cap * sizeof(typename St::R);
+}
+
+template <class St>
 int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s) {
-  const size_t lds = size_t(2) * 4 * (bx + 2) * sizeof(typename St::R);
-  hipLaunchKernelGGL((k_batch_step2d<St>), dim3(blocks), dim3(bx), lds, s,
-                     static_cast<const DevCase<D2Q9, St>*>(cases), a);
+  const size_t lds = batch_lds_bytes<St>(a.cap);
+  const auto* cs = static_cast<const DevCase<D2Q9, St>*>(cases);
+  if (a.lag == 1) hipLaunchKernelGGL((k_batch_step2d<St, 1>), dim3(blocks), dim3(bx), lds, s, cs, a);
+  else if (a.lag == 3) hipLaunchKernelGGL((k_batch_step2d<St, 3>), dim3(blocks), dim3(bx), lds, s, cs, a);
+  else return -1;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -74,10 +82,12 @@ int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s) {
 }
 
 template <class St>
-int batch_max_blocks_per_cu(int bx) {
+int batch_max_blocks_per_cu(int bx, int cap, int lag) {
   int nb = 0;
-  const size_t lds = size_t(2) * 4 * (bx + 2) * sizeof(typename St::R);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St>, bx, lds) != hipSuccess) return 0;
+  const size_t lds = batch_lds_bytes<St>(cap);
+  const hipError_t e = lag == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 1>, bx, lds)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 3>, bx, lds);
+  if (e != hipSuccess) return 0;
   return nb;
 }
 
@@ -87,8 +97,11 @@ template int launch_batch_step<StoreF16S>(const void*, const BatchArgs&, int, in
 template int launch_batch_fold<StoreF64>(const void*, const BatchArgs&, hipStream_t);
 template int launch_batch_fold<StoreF32>(const void*, const BatchArgs&, hipStream_t);
 template int launch_batch_fold<StoreF16S>(const void*, const BatchArgs&, hipStream_t);
-template int batch_max_blocks_per_cu<StoreF64>(int);
-template int batch_max_blocks_per_cu<StoreF32>(int);
-template int batch_max_blocks_per_cu<StoreF16S>(int);
+template int batch_max_blocks_per_cu<StoreF64>(int, int, int);
+template int batch_max_blocks_per_cu<StoreF32>(int, int, int);
+template int batch_max_blocks_per_cu<StoreF16S>(int, int, int);
+template size_t batch_lds_bytes<StoreF64>(int);
+template size_t batch_lds_bytes<StoreF32>(int);
+template size_t batch_lds_bytes<StoreF16S>(int);
 
 }  // namespace vclb

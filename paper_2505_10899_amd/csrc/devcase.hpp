@@ -76,7 +76,7 @@ __device__ __forceinline__ void pull(const Case& c, const typename St::S* __rest
     const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
     out[i] = St::load(src, long(pi) * c.n + s);
     if constexpr (St::shifted) {
-      if (ps) ps[i] = R(phis[s]);
+      if (ps) ps[i] = R(ldg(phis, s));
     }
   }
 }
@@ -230,8 +230,8 @@ __device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, lon
     for (int i = 0; i < L::Q; ++i) St::store(c.pop[1][dst], long(i) * c.n + n, f[i]);
   }
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) c.J[d * c.n + n] = J[d];
-  if constexpr (St::shifted) c.phis[dst][n] = float(phi);
+  for (int d = 0; d < L::D; ++d) stg(c.J, d * c.n + n, J[d]);
+  if constexpr (St::shifted) stg(c.phis[dst], n, float(phi));
 }
 
 template <class L, class St, bool COUPLED>

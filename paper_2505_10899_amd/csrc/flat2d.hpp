@@ -1,0 +1,196 @@
+// One work item of the batched D2Q9 step: a band of rows [y0, y1) of one case, marched
+// in the row-major order of the case padded by one ghost column on each side.
+//
+// Lanes walk consecutive nodes of that padded order, so a row of any width keeps every
+// lane busy (a 200-wide case leaves no partial wave at the end of each row) and
+// successive rows run back to back.  Virtual index v = (y + 1) P + (x + 1), P = nx + 2,
+// covers x in [-1, nx] and y in [-1, ny]; ghost columns hold the periodic neighbour
+// column, ghost rows the periodic neighbour row or, behind a wall, the edge row itself
+// (mirrored stencil ghosts).  Every stencil neighbour of v is then v + cx + P cy.
+//
+// The band's window (padded rows y0 - 1 .. y1) is cut into chunks of B consecutive
+// virtual nodes, one per lane.  Iteration i pulls the populations of chunk i, forms
+// phi and psi into an LDS ring of `cap` entries (a power of two), and keeps the pulled
+// populations in a register FIFO of DL + 1 slots; it then updates chunk i - DL from the
+// FIFO, in the same lanes that pulled it, once the ring holds every stencil input of
+// that chunk (DL B >= P + 1).  Each population is read from memory once, as in the row
+// march.  One barrier per iteration suffices when cap > (DL + 2) B + P: the chunk
+// written in iteration i + 1 cannot share a ring slot with anything iteration i's
+// update still reads.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "devcase.hpp"
+#include "launch.hpp"
+#include "step2d.hpp"
+
+namespace vclb {
+
+// v = q P + r with 0 <= r < P (v < 2^24, P >= 3), without an integer division
+__device__ __forceinline__ void divmod_pitch(int v, int P, float rcpP, int& q, int& r) {
+  q = int(float(v) * rcpP);
+  r = v - q * P;
+  if (r < 0) {
+    --q;
+    r += P;
+  } else if (r >= P) {
+    ++q;
+    r -= P;
+  }
+}
+
+template <class St, int DL>
+__device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, int y0, int y1, bool reduce,
+                                            int cap, double* __restrict__ part, long part_stride, long part_index,
+                                            unsigned char* smem_raw) {
+  using L = D2Q9;
+  using R = typename St::R;
+  using S = typename St::S;
+  constexpr int Q = 9;
+  constexpr int DEPTH = DL + 1;
+  static_assert((DEPTH & (DEPTH - 1)) == 0, "FIFO depth must be a power of two");
+  const int B = blockDim.x;
+  const int lane = threadIdx.x;
+  const int nx = c.nx, ny = c.ny, n = int(c.n);
+  const int P = nx + 2;
+  const float rcpP = 1.0f / float(P);
+  const int mask = cap - 1;
+  R* sphi = reinterpret_cast<R*>(smem_raw);
+  R* spsi = sphi + cap;
+  const int par = int(t & 1);
+  const int dst = par ^ 1;
+  const S* gsrc[9];
+  const S* fsrc[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    gsrc[i] = c.pop[0][par] + long(i) * n;
+    fsrc[i] = c.pop[1][par] + long(i) * n;
+  }
+  const float* phis = c.phis[par];
+  const bool wall = c.wall != 0;
+  auto row3 = [&](int yr) -> Row3 {   // yr in [0, ny)
+    Row3 o;
+    o.c = yr * nx;
+    o.m = (yr == 0 ? ny - 1 : yr - 1) * nx;
+    o.p = (yr == ny - 1 ? 0 : yr + 1) * nx;
+    o.lo = wall && yr == 0;
+    o.hi = wall && yr == ny - 1;
+    return o;
+  };
+  auto col3 = [&](int xr) -> Col3 { return Col3{xr, xr == 0 ? nx - 1 : xr - 1, xr == nx - 1 ? 0 : xr + 1}; };
+  const int f_begin = y0 * P, f_end = (y1 + 2) * P;   // padded rows y0 - 1 .. y1
+  const int nchunk = (f_end - f_begin + B - 1) / B;
+  const int niter = nchunk + DL;
+  R e[DEPTH][Q];          // pulled populations of the last DEPTH chunks (static indices only)
+  double a0 = 0.0, ax = 0.0, ay = 0.0, axx = 0.0, ayy = 0.0, axy = 0.0;   // one label per case
+  int acnt = 0, abad = 0;
+
+  auto iteration = [&](int i, auto front_slot) {
+    constexpr int SF = decltype(front_slot)::value;
+    constexpr int SU = (SF + DEPTH - DL) % DEPTH;
+    // the chunk updated in this iteration: its f and previous phi u are requested first,
+    // so that they are in flight while the front's phi is formed
+    const int vu = f_begin + (i - DL) * B + lane;
+    int x = -1, y = -1;
+    if (i >= DL && vu < f_end) {
+      int q, r;
+      divmod_pitch(vu, P, rcpP, q, r);
+      x = r - 1;
+      y = q - 1;
+    }
+    const bool act = x >= 0 && x < nx && y >= y0 && y < y1;
+    R f[Q], J[2];
+    const int nn = x + nx * y;
+    if (act) {
+      pull9<St>(fsrc, phis, col3(x), row3(y), f, nullptr);
+      J[0] = ldg(c.J, nn);
+      J[1] = ldg(c.J, n + nn);
+    }
+    // front: chunk i
+    if (i < nchunk) {
+      const int vf = f_begin + i * B + lane;
+      if (vf < f_end) {
+        int q, r;
+        divmod_pitch(vf, P, rcpP, q, r);
+        int xr = r - 1, yr = q - 1;
+        xr = xr < 0 ? nx - 1 : (xr >= nx ? 0 : xr);
+        if (yr < 0) yr = wall ? 0 : ny - 1;
+        else if (yr >= ny) yr = wall ? ny - 1 : 0;
+        R ps[Q];
+        pull9<St>(gsrc, phis, col3(xr), row3(yr), e[SF], ps);
+        const R ph = phi_of_pulled<L, St>(e[SF], ps, c.np.rest);
+        sphi[vf & mask] = ph;
+        spsi[vf & mask] = psi_of<R>(ph, c.np.W4, c.np.xi);
+      }
+    }
+    __syncthreads();
+    if (act) {
+      NodeIn<L, R> in;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const int s = (vu + L::cx[j] + P * L::cy[j]) & mask;
+        in.nphi[j] = sphi[s];
+        in.npsi[j] = spsi[s];
+      }
+      NodeOut<L, R> out;
+      node_update<L, R, true, St::shifted>(c.np, in, e[SU], f, J, out);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) St::store(c.pop[0][dst] + long(j) * n, nn, e[SU][j]);
+      if (wall && y == 0) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+          if (L::cy[j] < 0) f[j] += c.np.wb[j] * out.rho;
+      }
+      if (wall && y == ny - 1) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+          if (L::cy[j] > 0) f[j] += c.np.wt[j] * out.rho;
+      }
+#pragma unroll
+      for (int j = 0; j < Q; ++j) St::store(c.pop[1][dst] + long(j) * n, nn, f[j]);
+      stg(c.J, nn, J[0]);
+      stg(c.J, n + nn, J[1]);
+      if constexpr (St::shifted) stg(c.phis[dst], nn, float(in.nphi[0]));
+      if (reduce) {
+        const double ph = double(in.nphi[0]);
+        const double dx = min_image(double(x) - c.cen[0][0], nx, true);
+        const double dy = min_image(double(y) - c.cen[0][1], ny, !wall);
+        a0 += ph;
+        ax += ph * dx;
+        ay += ph * dy;
+        axx += ph * dx * dx;
+        ayy += ph * dy * dy;
+        axy += ph * dx * dy;
+        acnt += ph >= 0.5 ? 1 : 0;
+        abad += isfinite(ph) ? 0 : 1;
+      }
+    }
+  };
+  // unrolled by the FIFO depth so that every slot index is a compile-time constant;
+  // i is uniform over the workgroup, so the barriers inside stay uniform
+  for (int i0 = 0; i0 < niter; i0 += DEPTH) {
+    iteration(i0, std::integral_constant<int, 0>{});
+    if (i0 + 1 < niter) iteration(i0 + 1, std::integral_constant<int, 1 % DEPTH>{});
+    if constexpr (DEPTH > 2) {
+      if (i0 + 2 < niter) iteration(i0 + 2, std::integral_constant<int, 2 % DEPTH>{});
+      if (i0 + 3 < niter) iteration(i0 + 3, std::integral_constant<int, 3 % DEPTH>{});
+    }
+  }
+  if (reduce) {
+    Acc full;
+    full.zero();
+    full.v[0][0] = a0;
+    full.v[0][1] = double(acnt);
+    full.v[0][2] = ax;
+    full.v[0][3] = ay;
+    full.v[0][5] = axx;
+    full.v[0][6] = ayy;
+    full.v[0][8] = axy;
+    full.v[0][11] = double(abad);
+    write_partials(full, 1, part, part_stride, part_index);
+  }
+}
+
+}  // namespace vclb

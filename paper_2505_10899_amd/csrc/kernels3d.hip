@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       R f[Q], J[L::D];
       pull<L, St>(c, fsrc, phis, xw, yw, z, f, nullptr);
 #pragma unroll
-      for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
+      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J, d * c.n + n);
       NodeOut<L, R> out;
       node_update<L, R, true, St::shifted>(c.np, in, gcur, f, J, out);
       store_node<L, St, true>(c, par, n, yw, in.nphi[0], out.rho, gcur, f, J);

@@ -47,14 +47,33 @@ struct BatchArgs {
   long pend_step;
   long t;                   // step index of the state this launch reads
   int reduce;               // record the reductions of this step
+  int cap;                  // LDS ring entries of the flattened march (power of two)
+  int lag;                  // its lag in chunks (1 or 3)
 };
 
 template <class St>
 int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s);
 template <class St>
+size_t batch_lds_bytes(int cap);
+template <class St>
 int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s);
 template <class St>
-int batch_max_blocks_per_cu(int bx);
+int batch_max_blocks_per_cu(int bx, int cap, int lag);
+
+// Lag (in chunks of B lanes) of the flattened batched march for rows of padded pitch
+// P = nx + 2: 1 or 3 (the register FIFO holds lag + 1 chunks), 0 if the rows are too
+// wide for B lanes.
+inline int flat_lag(int P, int B) {
+  const int need = (P + 1 + B - 1) / B;
+  return need <= 1 ? 1 : (need <= 3 ? 3 : 0);
+}
+
+// LDS ring entries (a power of two) of the flattened march: more than (lag + 2) B + P
+inline int flat_ring_cap(int P, int B, int lag) {
+  int cap = 1;
+  while (cap <= (lag + 2) * B + P) cap <<= 1;
+  return cap;
+}
 
 // number of workgroups the fused step launches for a case of this shape
 inline long fused_blocks(int dim, int nx, int ny, int nz, const Tile& t) {

@@ -18,13 +18,29 @@
 
 namespace vclb {
 
+// ---------------------------------------------------------------- global memory access
+// Every device buffer of the library lives in global memory.  Pointers that reach a
+// kernel through a struct are generic to the compiler, which then emits flat memory
+// instructions; flat accesses also wait on the LDS/scalar counter and so overlap less
+// with the LDS traffic of the stencils.  These helpers cast to the global address
+// space, so that the accesses compile to global_load / global_store.
+#define VCLB_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T ldg(const T* p, long i) {
+  return ((const T VCLB_GLOBAL*)p)[i];
+}
+template <class T>
+__device__ __forceinline__ void stg(T* p, long i, T v) {
+  ((T VCLB_GLOBAL*)p)[i] = v;
+}
+
 // ---------------------------------------------------------------- storage codecs
 struct StoreF64 {
   using S = double;
   using R = double;
   static constexpr bool shifted = false;
-  __device__ static R load(const S* p, long i) { return p[i]; }
-  __device__ static void store(S* p, long i, R v) { p[i] = v; }
+  __device__ static R load(const S* p, long i) { return ldg(p, i); }
+  __device__ static void store(S* p, long i, R v) { stg(p, i, v); }
 };
 // FP32 storage uses the same deviation representation as FP16S (see below): the g
 // arithmetic then never rounds at the magnitude of the rest populations (~0.7), which
@@ -33,8 +49,8 @@ struct StoreF32 {
   using S = float;
   using R = float;
   static constexpr bool shifted = true;
-  __device__ static R load(const S* p, long i) { return p[i]; }
-  __device__ static void store(S* p, long i, R v) { p[i] = v; }
+  __device__ static R load(const S* p, long i) { return ldg(p, i); }
+  __device__ static void store(S* p, long i, R v) { stg(p, i, v); }
 };
 // FP16 storage of deviations from the rest equilibrium: g_i - phi r_i with
 // r_0 = 1 + (w_0 - 1) lambda, r_i = w_i lambda (g_eq at u = 0, mu = 0); f is stored
@@ -45,8 +61,12 @@ struct StoreF16S {
   using S = __half;
   using R = float;
   static constexpr bool shifted = true;
-  __device__ static R load(const S* p, long i) { return __half2float(p[i]); }
-  __device__ static void store(S* p, long i, R v) { p[i] = __float2half_rn(v); }
+  __device__ static R load(const S* p, long i) {
+    return __half2float(__ushort_as_half(ldg(reinterpret_cast<const unsigned short*>(p), i)));
+  }
+  __device__ static void store(S* p, long i, R v) {
+    stg(reinterpret_cast<unsigned short*>(p), i, __half_as_ushort(__float2half_rn(v)));
+  }
 };
 
 // ---------------------------------------------------------------- per-case constants

@@ -35,7 +35,7 @@ __device__ __forceinline__ void pull9(const typename St::S* const (&src)[9], con
   for (int i = 0; i < 9; ++i) {
     v[i] = St::load(base[i], off[i]);
     if constexpr (St::shifted) {
-      if (ps) ps[i] = R(phis[off[i]]);
+      if (ps) ps[i] = R(ldg(phis, off[i]));
     }
   }
 }
@@ -134,8 +134,8 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
     const int nn = xw + nx * y;
     R f[Q], J[2];
     if constexpr (COUPLED) pull9<St>(fsrc, phis, col, row3(y), f, nullptr);
-    J[0] = c.J[nn];
-    J[1] = c.J[n + nn];
+    J[0] = ldg(c.J, nn);
+    J[1] = ldg(c.J, n + nn);
     phi_row(y + 1, gnext);
     __syncthreads();
     if (active_x) {
@@ -170,9 +170,9 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
 #pragma unroll
         for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + long(i) * n, nn, f[i]);
       }
-      c.J[nn] = J[0];
-      c.J[n + nn] = J[1];
-      if constexpr (St::shifted) c.phis[dst][nn] = float(in.nphi[0]);
+      stg(c.J, nn, J[0]);
+      stg(c.J, n + nn, J[1]);
+      if constexpr (St::shifted) stg(c.phis[dst], nn, float(in.nphi[0]));
       if (reduce) {
         const double ph = double(in.nphi[0]);
         double dy[kMaxLabels];
