@@ -20,7 +20,6 @@ and the CPU oracle on a sample of the batch.  Prints one JSON line on stdout.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -63,13 +62,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+BATCH_SOURCES = ("batch.hip", "flat2d.hpp", "step2d.hpp", "node.hpp", "devcase.hpp", "lattice.hpp", "launch.hpp")
+
+
 def source_hash() -> str:
-    """Fingerprint of the HIP sources: counter figures taken on other sources are stale."""
+    """Fingerprint of the sources the batched step kernel is built from: counter figures
+    taken on other sources are stale."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2505_10899_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+    for name in BATCH_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(ROOT, "paper_2505_10899_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -106,7 +108,8 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     N = b.nodes()
     v0 = np.array([c.reduce()["sum_phi"].sum() for c in b.cases])
     tile = b.autotune(None, steps=tune_steps)
-    log(f"batch {storage}: {len(cases)} cases, {N} nodes, autotuned tile {tile}")
+    sched = b.schedule()
+    log(f"batch {storage}: {len(cases)} cases, {N} nodes, autotuned tile {tile}, flat_pct {sched}")
     b.step(warmup, graph=True)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
@@ -134,7 +137,7 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     gbs = N * bpn / (launch_ms * 1e-3) / 1e9
     del b
     return dict(nodes=N, ms_per_step=ms, wall_s=wall, mlups=N / (ms * 1e-3) / 1e6, launch_ms=launch_ms,
-                bytes_per_node=bpn, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=list(tile),
+                bytes_per_node=bpn, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=list(tile), flat_pct=sched,
                 max_rel_volume_drift=drift, drift_steps=int(t_end), approx_steps=total)
 
 
@@ -279,7 +282,7 @@ def main(argv=None):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if head == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": BATCH_DESC, "storage": head, "cases": 512, "nodes": h["nodes"],
-                   "tile": h["tile"]},
+                   "tile": h["tile"], "flat_pct": h["flat_pct"]},
         "roofline": {"bound": "hbm", "achieved": round(h["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(h["frac"], 4), "traffic": traffic,
                      "kernel": KERNEL[head], "bytes_per_node": h["bytes_per_node"],
@@ -288,7 +291,8 @@ def main(argv=None):
         "variants": {st: {"MLUPS": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                           "launch_ms": round(v["launch_ms"], 5), "achieved_GBs": round(v["achieved_GBs"], 1),
                           "frac_hbm_peak": round(v["frac"], 4), "bytes_per_node": v["bytes_per_node"],
-                          "tile": v["tile"], "max_rel_volume_drift": v["max_rel_volume_drift"],
+                          "tile": v["tile"], "flat_pct": v["flat_pct"],
+                          "max_rel_volume_drift": v["max_rel_volume_drift"],
                           "drift_over_steps": v["drift_steps"],
                           "speedup_vs_fp64": (round(v["mlups"] / res["fp64"]["mlups"], 3) if "fp64" in res else None)}
                      for st, v in res.items()},

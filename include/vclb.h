@@ -273,11 +273,18 @@ int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out);
 int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
 
 /* Launch shape of the batched step: bx in {64, 128, 256} lanes per workgroup, and work
-   items of about ty * 256 nodes (whole rows of one case; ty in 1..1024).  Each item is
-   marched in the row-major order of its rows, so that cases of any width keep every
-   lane busy.  get_tile also returns the number of resident workgroups launched per step. */
+   items of about ty * 256 nodes (ty in 1..1024).  get_tile also returns the number of
+   resident workgroups launched per step. */
 int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty);
 int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks);
+
+/* How each case is cut into work items.  A case whose width leaves more than
+   (100 - flat_pct)% of the lanes of one-lane-per-column waves idle runs as bands of whole
+   rows marched in padded row-major order (every lane busy, some extra index arithmetic);
+   the others run as strips of bx columns, one lane per column.  flat_pct in 0..101:
+   0 puts every case in strips, 101 every case that fits in bands (default 90). */
+int vclb_batch_set_schedule(vclb_batch* b, int32_t flat_pct);
+int vclb_batch_get_schedule(const vclb_batch* b, int32_t* flat_pct);
 
 /* Record each case's volume reductions every `every` steps (0: off; default 1). */
 int vclb_batch_set_reduce_every(vclb_batch* b, int32_t every);
@@ -287,9 +294,10 @@ int vclb_batch_set_reduce_every(vclb_batch* b, int32_t every);
    ordered after `stream`.  Asynchronous with respect to the host. */
 int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stream);
 
-/* Pick the batched tile by timing `steps` steps of every candidate on the current state
-   (saved and restored), or take it from the JSON-lines file cache_path when that holds
-   an entry for this batch; a measured choice is appended to cache_path (NULL: no file). */
+/* Pick the batched tile and schedule (bx, ty, flat_pct) by timing `steps` steps of every
+   candidate on the current state (saved and restored), or take them from the JSON-lines
+   file cache_path when that holds an entry for this batch; a measured choice is appended
+   to cache_path (NULL: no file). */
 int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, void* stream);
 
 #ifdef __cplusplus

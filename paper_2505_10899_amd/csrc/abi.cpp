@@ -807,7 +807,7 @@ struct vclb_batch {
   size_t items_cap = 0;
   std::vector<int4> items;
   std::vector<int2> case_items;
-  int bx = 128, ty = 32, blocks = 0, cap = 0, lag = 1;
+  int bx = 128, ty = 32, blocks = 0, cap = 0, lag = 1, flat_pct = 90;
   int reduce_every = 1;
   int64_t nodes = 0;
   bool pend = false;
@@ -831,37 +831,51 @@ int dispatch_storage(int storage, Fn&& fn) {
 }
 
 // work items of a tile shape: per case, bands of ty rows, x strips of bx columns fastest
-// Work items of the flattened batched march: bands of whole rows of one case holding
-// about ty * 256 nodes each, case-major.
-void build_items(vclb_batch* b, int ty, std::vector<int4>& items, std::vector<int2>& ci) {
+// Whether case p runs as flattened bands: when one lane per column would leave more
+// than (100 - flat_pct)% of the lanes of its row waves idle, and its rows fit the
+// flattened march with bx lanes.
+bool batch_case_flat(const vclb_params& p, int bx, int flat_pct) {
+  const int lanes = (p.nx + 63) / 64 * 64;
+  return 100L * p.nx < long(flat_pct) * lanes && vclb::flat_lag(p.nx + 2, bx) != 0;
+}
+
+// Work items, case-major: flattened bands of whole rows holding about ty * 256 nodes, or
+// strips of bx columns by bands of rows holding about as many nodes.
+void build_items(vclb_batch* b, int bx, int ty, int flat_pct, std::vector<int4>& items, std::vector<int2>& ci) {
   items.clear();
   ci.assign(size_t(b->n), int2{0, 0});
   for (int k = 0; k < b->n; ++k) {
     const vclb_params& p = b->cases[size_t(k)]->p;
-    const int P = p.nx + 2;
-    const int rows = std::max(1, std::min(p.ny, (ty * 256 + P / 2) / P));
     const int first = int(items.size());
-    for (int y0 = 0; y0 < p.ny; y0 += rows) items.push_back(int4{k, 0, y0, std::min(y0 + rows, p.ny)});
+    if (batch_case_flat(p, bx, flat_pct)) {
+      const int P = p.nx + 2;
+      const int rows = std::max(1, std::min(p.ny, (ty * 256 + P / 2) / P));
+      for (int y0 = 0; y0 < p.ny; y0 += rows) items.push_back(int4{k, -1, y0, std::min(y0 + rows, p.ny)});
+    } else {
+      const int w = std::min(bx, (p.nx + 63) / 64 * 64);
+      const int rows = std::max(4, std::min(p.ny, ty * 256 / w));
+      for (int y0 = 0; y0 < p.ny; y0 += rows)
+        for (int x0 = 0; x0 < p.nx; x0 += bx) items.push_back(int4{k, x0, y0, std::min(y0 + rows, p.ny)});
+    }
     ci[size_t(k)] = int2{first, int(items.size()) - first};
   }
 }
 
-int batch_set_tile(vclb_batch* b, int bx, int ty) {
-  if (bx < 64 || bx > 256 || bx % 64 != 0 || ty < 1 || ty > 1024)
-    return fail(VCLB_EINVAL, "bad batch tile (bx in 64..256, multiple of 64; ty in 1..1024)");
-  int pmax = 0, lag = 1;
+int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
+  if (bx < 64 || bx > 256 || bx % 64 != 0 || ty < 1 || ty > 1024 || flat_pct < 0 || flat_pct > 101)
+    return fail(VCLB_EINVAL, "bad batch launch shape (bx in 64..256, multiple of 64; ty in 1..1024; flat_pct in 0..101)");
+  int pmax = 1, lag = 1;
   for (const vclb_case* c : b->cases) {
-    const int l = vclb::flat_lag(c->p.nx + 2, bx);
-    if (l == 0) return fail(VCLB_EINVAL, "a case is too wide for the batched step with this many lanes");
-    lag = std::max(lag, l);
+    if (!batch_case_flat(c->p, bx, flat_pct)) continue;
+    lag = std::max(lag, vclb::flat_lag(c->p.nx + 2, bx));
     pmax = std::max(pmax, c->p.nx + 2);
   }
   const int cap = vclb::flat_ring_cap(pmax, bx, lag);
-  const size_t lds = dispatch_storage(b->storage, [&](auto st) { return int(vclb::batch_lds_bytes<decltype(st)>(cap)); });
+  const size_t lds = dispatch_storage(b->storage, [&](auto st) { return int(vclb::batch_lds_bytes<decltype(st)>(cap, bx)); });
   if (lds > 64 * 1024) return fail(VCLB_EINVAL, "a case is too wide for the batched step with this tile");
   std::vector<int4> items;
   std::vector<int2> ci;
-  build_items(b, ty, items, ci);
+  build_items(b, bx, ty, flat_pct, items, ci);
   if (items.size() > b->items_cap) return fail(VCLB_EINVAL, "too many work items");
   HIP_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_case_items, ci.data(), ci.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -873,6 +887,7 @@ int batch_set_tile(vclb_batch* b, int bx, int ty) {
   b->blocks = int(std::min<long>(long(items.size()), long(per_cu) * ncu));
   b->bx = bx;
   b->ty = ty;
+  b->flat_pct = flat_pct;
   b->cap = cap;
   b->lag = lag;
   b->items = std::move(items);
@@ -964,7 +979,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
   for (int k = 0; k < ncases; ++k) {
     off[size_t(k)] = total;
     total += align_up(layout_for(cases[k]).total);
-    cap += size_t(cases[k].ny);   // at most one work item per row
+    cap += size_t(cases[k].ny) * size_t((cases[k].nx + 63) / 64);   // at most one item per row and strip
     b->nodes += int64_t(cases[k].nx) * cases[k].ny;
   }
   const size_t o_cases = total;
@@ -1028,7 +1043,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
     vclb_batch_destroy(b);
     return hip_fail(e, "batch set-up");
   }
-  int rc = batch_set_tile(b, 256, 32);
+  int rc = batch_set_tile(b, 256, 32, 90);
   if (rc) {
     vclb_batch_destroy(b);
     return rc;
@@ -1063,7 +1078,7 @@ int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes) {
 int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty) {
   if (!b) return fail(VCLB_EINVAL, "batch is NULL");
   batch_release_graph(b);
-  return batch_set_tile(b, bx, ty);
+  return batch_set_tile(b, bx, ty, b->flat_pct);
 }
 
 int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks) {
@@ -1071,6 +1086,18 @@ int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* 
   *bx = b->bx;
   *ty = b->ty;
   *blocks = b->blocks;
+  return VCLB_OK;
+}
+
+int vclb_batch_set_schedule(vclb_batch* b, int32_t flat_pct) {
+  if (!b) return fail(VCLB_EINVAL, "batch is NULL");
+  batch_release_graph(b);
+  return batch_set_tile(b, b->bx, b->ty, flat_pct);
+}
+
+int vclb_batch_get_schedule(const vclb_batch* b, int32_t* flat_pct) {
+  if (!b || !flat_pct) return fail(VCLB_EINVAL, "NULL argument");
+  *flat_pct = b->flat_pct;
   return VCLB_OK;
 }
 
@@ -1135,18 +1162,23 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[4096];
-      int bx = 0, ty = 0;
+      int bx = 0, ty = 0, fp = -1;
       while (std::fgets(line, sizeof(line), f)) {
         if (!std::strstr(line, key)) continue;
         const char* pb = std::strstr(line, "\"bx\": ");
         const char* pt = std::strstr(line, "\"ty\": ");
-        if (pb && pt) {
+        const char* pf = std::strstr(line, "\"flat_pct\": ");
+        if (pb && pt && pf) {
           bx = std::atoi(pb + 6);
           ty = std::atoi(pt + 6);
+          fp = std::atoi(pf + 12);
         }
       }
       std::fclose(f);
-      if (bx > 0 && ty > 0) return vclb_batch_set_tile(b, bx, ty);
+      if (bx > 0 && ty > 0 && fp >= 0) {
+        batch_release_graph(b);
+        return batch_set_tile(b, bx, ty, fp);
+      }
     }
   }
   hipStream_t s = as_stream(stream);
@@ -1166,13 +1198,14 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  struct Cand { int bx, ty; float ms; };
+  struct Cand { int bx, ty, fp; float ms; };
   std::vector<Cand> cands;
-  for (int bx : {64, 128, 256})
-    for (int ty : {8, 16, 32, 64}) cands.push_back({bx, ty, -1.0f});
+  for (int fp : {0, 90, 101})
+    for (int bx : {64, 128, 256})
+      for (int ty : {8, 16, 32, 64}) cands.push_back({bx, ty, fp, -1.0f});
   int rc = VCLB_OK;
   for (Cand& cd : cands) {
-    if (batch_set_tile(b, cd.bx, cd.ty) == VCLB_EINVAL) continue;   // shape not valid for these cases
+    if (batch_set_tile(b, cd.bx, cd.ty, cd.fp) == VCLB_EINVAL) continue;   // shape not valid for these cases
     if ((rc = batch_enqueue(b, 1, false, s))) break;
     HIP_TRY(hipEventRecord(e0, s));
     for (vclb_case* c : b->cases) c->t_host = t0 + 1;
@@ -1195,18 +1228,18 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  Cand best{0, 0, -1.0f};
+  Cand best{0, 0, 0, -1.0f};
   for (const Cand& cd : cands)
     if (cd.ms > 0 && (best.ms < 0 || cd.ms < best.ms)) best = cd;
   if (best.ms < 0) return fail(VCLB_EINVAL, "no batched launch shape fits these cases");
-  rc = batch_set_tile(b, best.bx, best.ty);
+  rc = batch_set_tile(b, best.bx, best.ty, best.fp);
   if (rc) return rc;
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "{\"key\": \"%s\", \"cases\": %d, \"storage\": %d, \"bx\": %d, \"ty\": %d, \"ms_per_step\": %.6f, \"candidates\": [",
-                   key, b->n, b->storage, best.bx, best.ty, double(best.ms));
+      std::fprintf(f, "{\"key\": \"%s\", \"cases\": %d, \"storage\": %d, \"bx\": %d, \"ty\": %d, \"flat_pct\": %d, \"ms_per_step\": %.6f, \"candidates\": [",
+                   key, b->n, b->storage, best.bx, best.ty, best.fp, double(best.ms));
       for (size_t i = 0; i < cands.size(); ++i)
-        std::fprintf(f, "%s[%d, %d, %.6f]", i ? ", " : "", cands[i].bx, cands[i].ty, double(cands[i].ms));
+        std::fprintf(f, "%s[%d, %d, %d, %.6f]", i ? ", " : "", cands[i].bx, cands[i].ty, cands[i].fp, double(cands[i].ms));
       std::fprintf(f, "]}\n");
       std::fclose(f);
     }

@@ -1,8 +1,10 @@
 // Many independent D2Q9 cases of uneven sizes advanced by one work-list kernel per step.
 //
-// A fixed number of resident workgroups strides over the work items (case, band of
-// rows) of all cases; each item is a flattened march over the band (step2d_flat), so
-// that cases of any width keep every lane busy.  The n launches of a call are captured in one hipGraph and
+// A fixed number of resident workgroups strides over the work items of all cases.  An
+// item is either a strip of columns marched row by row (step2d_tile, one lane per
+// column: best when the width is close to a multiple of the wave size) or a band of
+// whole rows marched in padded row-major order (step2d_flat: every lane busy for any
+// width, at some extra index arithmetic); the host picks per case.  The n launches of a call are captured in one hipGraph and
 // replayed as one launch.  Per-case volume reductions: every item writes its partial
 // sums; the next launch (or a fold-only launch at the end of a call) sums each case's
 // items in a fixed order into that case's observation history.
@@ -49,7 +51,10 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : (DL == 
     const int it = base + slot;
     if (it >= a.nitems) break;
     const int4 w = a.items[it];
-    step2d_flat<St, DL>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);
+    if (w.y < 0)   // a band of whole rows, marched in padded row-major order
+      step2d_flat<St, DL>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);
+    else           // a strip of columns [w.y, w.y + blockDim.x), one lane per column
+      step2d_tile<St, true>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems, it, smem_raw);
     __syncthreads();
   }
 }
@@ -60,13 +65,15 @@ __global__ void __launch_bounds__(256) k_batch_fold(const DevCase<D2Q9, St>* __r
 }
 
 template <class St>
-size_t batch_lds_bytes(int cap) {
-  return size_t(2) * cap * sizeof(typename St::R);
+size_t batch_lds_bytes(int cap, int bx) {
+  const size_t flat = size_t(2) * cap * sizeof(typename St::R);
+  const size_t rows = size_t(2) * 4 * (bx + 2) * sizeof(typename St::R);
+  return flat > rows ? flat : rows;
 }
 
 template <class St>
 int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s) {
-  const size_t lds = batch_lds_bytes<St>(a.cap);
+  const size_t lds = batch_lds_bytes<St>(a.cap, bx);
   const auto* cs = static_cast<const DevCase<D2Q9, St>*>(cases);
   if (a.lag == 1) hipLaunchKernelGGL((k_batch_step2d<St, 1>), dim3(blocks), dim3(bx), lds, s, cs, a);
   else if (a.lag == 3) hipLaunchKernelGGL((k_batch_step2d<St, 3>), dim3(blocks), dim3(bx), lds, s, cs, a);
@@ -84,7 +91,7 @@ int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s) {
 template <class St>
 int batch_max_blocks_per_cu(int bx, int cap, int lag) {
   int nb = 0;
-  const size_t lds = batch_lds_bytes<St>(cap);
+  const size_t lds = batch_lds_bytes<St>(cap, bx);
   const hipError_t e = lag == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 1>, bx, lds)
                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 3>, bx, lds);
   if (e != hipSuccess) return 0;
@@ -100,8 +107,8 @@ template int launch_batch_fold<StoreF16S>(const void*, const BatchArgs&, hipStre
 template int batch_max_blocks_per_cu<StoreF64>(int, int, int);
 template int batch_max_blocks_per_cu<StoreF32>(int, int, int);
 template int batch_max_blocks_per_cu<StoreF16S>(int, int, int);
-template size_t batch_lds_bytes<StoreF64>(int);
-template size_t batch_lds_bytes<StoreF32>(int);
-template size_t batch_lds_bytes<StoreF16S>(int);
+template size_t batch_lds_bytes<StoreF64>(int, int);
+template size_t batch_lds_bytes<StoreF32>(int, int);
+template size_t batch_lds_bytes<StoreF16S>(int, int);
 
 }  // namespace vclb

@@ -37,7 +37,8 @@ template <class St>
 int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hipStream_t s);
 
 struct BatchArgs {
-  const int4* items;        // (case, x0, y0, y1) of every work item, case-major
+  const int4* items;        // (case, x0, y0, y1) of every work item, case-major; x0 < 0: a
+                            // flattened band of rows [y0, y1), else a strip of columns from x0
   int nitems;
   const int2* case_items;   // (first item, item count) per case
   int ncases;
@@ -54,7 +55,7 @@ struct BatchArgs {
 template <class St>
 int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s);
 template <class St>
-size_t batch_lds_bytes(int cap);
+size_t batch_lds_bytes(int cap, int bx);
 template <class St>
 int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s);
 template <class St>

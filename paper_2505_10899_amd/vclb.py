@@ -92,6 +92,8 @@ _SIGS = [
     ("vclb_batch_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     ("vclb_batch_get_tile", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     ("vclb_batch_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("vclb_batch_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("vclb_batch_get_schedule", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32)]),
     ("vclb_batch_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
     ("vclb_batch_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32, ctypes.c_void_p]),
     ("vclb_state_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -480,6 +482,14 @@ class Batch:
 
     def set_reduce_every(self, every: int):
         check(lib().vclb_batch_set_reduce_every(self.h, int(every)))
+
+    def set_schedule(self, flat_pct: int):
+        check(lib().vclb_batch_set_schedule(self.h, int(flat_pct)))
+
+    def schedule(self) -> int:
+        v = ctypes.c_int32()
+        check(lib().vclb_batch_get_schedule(self.h, ctypes.byref(v)))
+        return v.value
 
     def step(self, n: int = 1, graph: bool = True, stream=None):
         check(lib().vclb_batch_step(self.h, int(n), 1 if graph else 0, _stream_handle(stream)))
