@@ -97,7 +97,7 @@ def timer():
 
 
 # ----------------------------------------------------------------------------- batch
-def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_steps: int):
+def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_steps: int, fixed=None):
     import torch
     import workloads as W
     from paper_2505_10899_amd import vclb
@@ -107,7 +107,12 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
         c.init(phi0, u0)
     N = b.nodes()
     v0 = np.array([c.reduce()["sum_phi"].sum() for c in b.cases])
-    tile = b.autotune(None, steps=tune_steps)
+    if fixed:                      # (bx, ty, flat_pct) given: no autotuning (profiling runs)
+        b.set_tile(fixed[0], fixed[1])
+        b.set_schedule(fixed[2])
+        tile = b.tile()
+    else:
+        tile = b.autotune(None, steps=tune_steps)
     sched = b.schedule()
     log(f"batch {storage}: {len(cases)} cases, {N} nodes, autotuned tile {tile}, flat_pct {sched}")
     b.step(warmup, graph=True)
@@ -129,7 +134,6 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     e1.record(s)
     torch.cuda.synchronize()
     launch_ms = e0.elapsed_time(e1) / launch_steps
-    total = steps + warmup + launch_steps + 2 * tune_steps * 9
     v1 = np.array([c.reduce()["sum_phi"].sum() for c in b.cases])
     t_end = b.cases[0].time()
     drift = float(np.max(np.abs(v1 - v0) / np.abs(v0)))
@@ -138,7 +142,7 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     del b
     return dict(nodes=N, ms_per_step=ms, wall_s=wall, mlups=N / (ms * 1e-3) / 1e6, launch_ms=launch_ms,
                 bytes_per_node=bpn, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=list(tile), flat_pct=sched,
-                max_rel_volume_drift=drift, drift_steps=int(t_end), approx_steps=total)
+                max_rel_volume_drift=drift, drift_steps=int(t_end))
 
 
 # ----------------------------------------------------------------------------- adjoint
@@ -250,6 +254,8 @@ def main(argv=None):
     ap.add_argument("--storages", default="fp32,fp16s,fp64")
     ap.add_argument("--launch-steps", type=int, default=50)
     ap.add_argument("--tune-steps", type=int, default=5)
+    ap.add_argument("--batch-tile", default="",
+                    help="storage=bx,ty,flat_pct[;...]: fixed batched launch shapes instead of autotuning")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -269,7 +275,11 @@ def main(argv=None):
     res = {}
     for st in storages:
         log(f"batch {st}: {a.warmup} warmup + {a.steps} timed steps")
-        r = run_batch(st, a.steps, a.warmup, a.launch_steps, a.tune_steps)
+        fixed = {}
+        for item in filter(None, a.batch_tile.split(";")):
+            k, v = item.split("=")
+            fixed[k.strip()] = tuple(int(x) for x in v.split(","))
+        r = run_batch(st, a.steps, a.warmup, a.launch_steps, a.tune_steps, fixed.get(st))
         res[st] = r
         log(f"batch {st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, launch {r['launch_ms']:.3f} ms, "
             f"{r['achieved_GBs']:.0f} GB/s ({100 * r['frac']:.1f}% of HBM peak), drift {r['max_rel_volume_drift']:.2e}")
