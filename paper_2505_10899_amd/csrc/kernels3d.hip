@@ -3,8 +3,9 @@
 // A workgroup of bx * by threads owns a bx x by column tile of the (x, y) plane and
 // marches over tz planes of z.  For each plane it pulls the next plane's g, forms
 // phi and psi into a 4-plane LDS ring padded by one halo node on every side (the
-// ring of halo nodes is shared out over the threads), then applies the 18-neighbour
-// stencils from LDS and updates the current plane.
+// ring of halo nodes is shared out evenly over the waves), then applies the
+// 18-neighbour stencils from LDS and updates the current plane with the moment-space
+// node update.
 #include <hip/hip_runtime.h>
 
 #include "devcase.hpp"
@@ -49,7 +50,10 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     sphi[s + (ty + 1) * PW + tx + 1] = ph;
     spsi[s + (ty + 1) * PW + tx + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
-    for (int k = tid; k < ring; k += nthr) {
+    // halo cells spread evenly over the waves (thread hstep * k takes cell k), so that no
+    // wave carries a second full pull while the others wait at the barrier
+    const int hstep = nthr >= ring ? nthr / ring : 1;
+    for (int k = (tid % hstep == 0) ? tid / hstep : ring; k < ring; k += nthr / hstep) {
       int px, py;
       if (k < PW) { px = k; py = 0; }
       else if (k < 2 * PW) { px = k - PW; py = PH - 1; }
@@ -65,8 +69,21 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
     }
   };
   if (blockIdx.x == 0 && c.pend_nb > 0) fold_pending(c);
-  Acc acc;
-  acc.zero();
+  // reductions: the lane's (x, y) is fixed, so per label only sum phi, sum phi dz,
+  // sum phi dz^2 and the counts are accumulated; the x and y moments follow at the end
+  double dxl[kMaxLabels], dyl[kMaxLabels];
+#pragma unroll
+  for (int k = 0; k < kMaxLabels; ++k) {
+    dxl[k] = min_image(double(xw) - c.cen[k][0], c.nx, true);
+    dyl[k] = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
+  }
+  double s0[kMaxLabels], s1[kMaxLabels], s2[kMaxLabels];
+  int cnt[kMaxLabels], bad[kMaxLabels];
+#pragma unroll
+  for (int k = 0; k < kMaxLabels; ++k) {
+    s0[k] = s1[k] = s2[k] = 0.0;
+    cnt[k] = bad[k] = 0;
+  }
   R gcur[Q], gnext[Q];
   plane(z0 - 1, gnext);
   plane(z0, gcur);
@@ -74,12 +91,21 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
     plane(z + 1, gnext);
     __syncthreads();
     if (active) {
-      NodeIn<L, R> in;
+      // stencils of Eqs. 39-40 accumulated straight from the LDS ring
+      StencilOut<L, R> st;
+      const int s0i = slot(z) * PS + (ty + 1) * PW + tx + 1;
+      st.phi = sphi[s0i];
+      st.lap = R(0);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
+      for (int d = 0; d < 3; ++d) st.gphi[d] = st.gpsi[d] = R(0);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
         const int s = slot(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
-        in.nphi[i] = sphi[s];
-        in.npsi[i] = spsi[s];
+        const R ph = sphi[s], ps = spsi[s];
+        st.lap += R(6.0 * L::w[i]) * (ph - st.phi);
+        if (L::cx[i] != 0) { st.gphi[0] += R(3.0 * L::w[i] * L::cx[i]) * ph; st.gpsi[0] += R(3.0 * L::w[i] * L::cx[i]) * ps; }
+        if (L::cy[i] != 0) { st.gphi[1] += R(3.0 * L::w[i] * L::cy[i]) * ph; st.gpsi[1] += R(3.0 * L::w[i] * L::cy[i]) * ps; }
+        if (L::cz[i] != 0) { st.gphi[2] += R(3.0 * L::w[i] * L::cz[i]) * ph; st.gpsi[2] += R(3.0 * L::w[i] * L::cz[i]) * ps; }
       }
       const long n = xw + long(c.nx) * (yw + long(c.ny) * z);
       R f[Q], J[L::D];
@@ -87,12 +113,50 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
 #pragma unroll
       for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J, d * c.n + n);
       NodeOut<L, R> out;
-      node_update<L, R, true, St::shifted>(c.np, in, gcur, f, J, out);
-      store_node<L, St, true>(c, par, n, yw, in.nphi[0], out.rho, gcur, f, J);
-      if (reduce) accumulate(c, acc, double(in.nphi[0]), xw, yw, z);
+      node_update_mom_s<L, R, true, St::shifted>(c.np, st, gcur, f, J, out);
+      store_node<L, St, true>(c, par, n, yw, st.phi, out.rho, gcur, f, J);
+      if (reduce) {
+        const double ph = double(st.phi);
+        double dz[kMaxLabels];
+#pragma unroll
+        for (int k = 0; k < kMaxLabels; ++k) dz[k] = min_image(double(z) - c.cen[k][2], c.nz, true);
+        int lab = 0;
+        if (c.nl > 1) {
+          const double r0 = dxl[0] * dxl[0] + dyl[0] * dyl[0] + dz[0] * dz[0];
+          const double r1 = dxl[1] * dxl[1] + dyl[1] * dyl[1] + dz[1] * dz[1];
+          lab = (r1 < r0) ? 1 : 0;
+        }
+        const bool fin = isfinite(ph);
+#pragma unroll
+        for (int k = 0; k < kMaxLabels; ++k) {
+          const double w = (k == lab) ? ph : 0.0;
+          s0[k] += w;
+          s1[k] += w * dz[k];
+          s2[k] += w * dz[k] * dz[k];
+          cnt[k] += (k == lab && ph >= 0.5) ? 1 : 0;
+          bad[k] += (k == lab && !fin) ? 1 : 0;
+        }
+      }
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
+  }
+  Acc acc;
+#pragma unroll
+  for (int k = 0; k < kMaxLabels; ++k) {
+    const double dx = dxl[k], dy = dyl[k];
+    acc.v[k][0] = s0[k];
+    acc.v[k][1] = double(cnt[k]);
+    acc.v[k][2] = dx * s0[k];
+    acc.v[k][3] = dy * s0[k];
+    acc.v[k][4] = s1[k];
+    acc.v[k][5] = dx * dx * s0[k];
+    acc.v[k][6] = dy * dy * s0[k];
+    acc.v[k][7] = s2[k];
+    acc.v[k][8] = dx * dy * s0[k];
+    acc.v[k][9] = dx * s1[k];
+    acc.v[k][10] = dy * s1[k];
+    acc.v[k][11] = double(bad[k]);
   }
   finish_block(c, acc, reduce != 0);
 }

@@ -102,4 +102,30 @@ constexpr int row_norm(int k) {
   return s;
 }
 
+// Moments of the weighted velocity monomials, sum_i M_ki w_i c_i^a: the building blocks
+// of the moments of every equilibrium and source of the model, which are all of the
+// form w_i (a + b . c_i + C : c_i c_i) plus a correction at the rest velocity.
+template <class L>
+constexpr int vel(int i, int d) {
+  return d == 0 ? L::cx[i] : (d == 1 ? L::cy[i] : L::cz[i]);
+}
+template <class L>
+constexpr double mom_w(int k) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::M[k][i] * L::w[i];
+  return s;
+}
+template <class L>
+constexpr double mom_wc(int k, int d) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::M[k][i] * L::w[i] * vel<L>(i, d);
+  return s;
+}
+template <class L>
+constexpr double mom_wcc(int k, int d, int e) {
+  double s = 0.0;
+  for (int i = 0; i < L::Q; ++i) s += L::M[k][i] * L::w[i] * vel<L>(i, d) * vel<L>(i, e);
+  return s;
+}
+
 }  // namespace vclb

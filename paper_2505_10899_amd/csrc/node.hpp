@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace vclb {
@@ -428,11 +430,214 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   out.u[1] = uy;
 }
 
+// ---------------------------------------------------------------- any lattice, moment space
+// Compile-time loop: f(integral_constant<int, K>) for K = B .. E - 1.
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B < E) {
+    fn(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(fn);
+  }
+}
+
+// m = M v with the integer matrix of the lattice (zero entries skipped at compile time)
+template <class L, class R>
+__device__ __forceinline__ void to_moments(const R (&v)[L::Q], R (&m)[L::Q]) {
+  static_for<0, L::Q>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    R acc = R(0);
+    static_for<0, L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int c = L::M[k][i];
+      if constexpr (c == 1) acc += v[i];
+      else if constexpr (c == -1) acc -= v[i];
+      else if constexpr (c != 0) acc += R(c) * v[i];
+    });
+    m[k] = acc;
+  });
+}
+
+// v = M^{-1} m = M^T diag(1 / |M_k|^2) m (m is scaled in place)
+template <class L, class R>
+__device__ __forceinline__ void from_moments(R (&m)[L::Q], R (&v)[L::Q]) {
+  R (&a)[L::Q] = m;
+  static_for<0, L::Q>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    a[k] = m[k] * R(1.0 / double(row_norm<L>(k)));
+  });
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    R acc = R(0);
+    static_for<0, L::Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr int c = L::M[k][i];
+      if constexpr (c == 1) acc += a[k];
+      else if constexpr (c == -1) acc -= a[k];
+      else if constexpr (c != 0) acc += R(c) * a[k];
+    });
+    v[i] = acc;
+  });
+}
+
+// sum_d x_d T(k, d) and sum_{d,e} x_d y_e T(k, d, e) with compile-time tables
+template <class L, class R, int k>
+__device__ __forceinline__ R mom_lin(const R (&x)[L::D]) {
+  R s = R(0);
+  static_for<0, L::D>([&](auto D) {
+    constexpr int d = decltype(D)::value;
+    constexpr double t = mom_wc<L>(k, d);
+    if constexpr (t != 0.0) s += R(t) * x[d];
+  });
+  return s;
+}
+template <class L, class R, int k>
+__device__ __forceinline__ R mom_quad(const R (&x)[L::D], const R (&y)[L::D]) {
+  R s = R(0);
+  static_for<0, L::D>([&](auto D) {
+    constexpr int d = decltype(D)::value;
+    static_for<0, L::D>([&](auto E) {
+      constexpr int e = decltype(E)::value;
+      constexpr double t = mom_wcc<L>(k, d, e);
+      if constexpr (t != 0.0) s += R(t) * (x[d] * y[e]);
+    });
+  });
+  return s;
+}
+
+// One node on any lattice, the same time step as node_update_generic, with the collisions
+// done in moment space and the moments of the equilibria and sources formed row by row
+// from the tables above: with g_eq,i = w_i (H + 3 c_i . J) + delta_i0 (phi - H) (Eq. 31),
+// G_i = w_i c_i . V (Eq. 32), f_eq,i = 3 w_i p + delta_i0 (-3 p) + rho w_i (3 c_i . u +
+// 4.5 (c_i . u)^2 - 1.5 u . u) (Eqs. 22-23) and F_i = 3 w_i (c_i . F + (c_i . u)(c_i .
+// grad rho)) (Eq. 21), no per-population equilibrium is ever stored.
+// What the stencils of Eqs. 39-40 give at one node.
+template <class L, class R>
+struct StencilOut {
+  R phi, lap;
+  R gphi[L::D], gpsi[L::D];
+  R u[L::D];   // prescribed velocity (vortex mode only)
+};
+
+template <class L, class R, bool COUPLED, bool SH>
+__device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, const StencilOut<L, R>& st,
+                                                  R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
+  constexpr int Q = L::Q, D = L::D;
+  const R phi = st.phi;
+  const R rho = p.rho_l + phi * p.drho;
+  const R pc = clamp01(phi);
+  const R a = pc + p.xi, b = (R(1) - pc) + p.xi;
+  const R An = p.lamW * (R(4) * a * b) / ((a + b) * (a + b));
+  const R* gphi = st.gphi;
+  const R* gpsi = st.gpsi;
+  const R lphi = st.lap;
+  const R mu = p.beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - p.kappa * lphi;   // Eq. 2
+  R Fs[D], grho[D], u[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    Fs[d] = mu * gphi[d];
+    grho[d] = p.drho * gphi[d];
+  }
+  R press = R(0);
+  if constexpr (COUPLED) {
+    // momentum and the sum of the moving populations; the full moments of f are formed
+    // only at its collision, so that they are not live across the g collision
+    R jj[3] = {R(0), R(0), R(0)}, P = R(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      P += f[i];
+      if (L::cx[i] != 0) jj[0] += R(L::cx[i]) * f[i];
+      if (L::cy[i] != 0) jj[1] += R(L::cy[i]) * f[i];
+      if (D == 3 && L::cz[i] != 0) jj[2] += R(L::cz[i]) * f[i];
+    }
+    R uu = R(0), ug = R(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      u[d] = (jj[d] + R(0.5) * Fs[d]) / rho;                                        // Eq. 28
+      uu += u[d] * u[d];
+      ug += u[d] * grho[d];
+    }
+    press = R((1.0 / 3.0) / (1.0 - L::w[0])) * (P + R(0.5) * ug + rho * R(-1.5 * L::w[0]) * uu);   // Eq. 29
+  } else {
+#pragma unroll
+    for (int d = 0; d < D; ++d) u[d] = st.u[d];
+  }
+  R Jn[D], V[D];
+  R n2 = p.eps2;
+#pragma unroll
+  for (int d = 0; d < D; ++d) n2 += gpsi[d] * gpsi[d];
+  const R inv = R(1) / sqrt(n2);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    Jn[d] = phi * u[d];
+    V[d] = R(3) * (Jn[d] - J[d]) + An * (gpsi[d] * inv);
+    J[d] = Jn[d];
+  }
+  // g (Eq. 33) in moment space; with SH the equilibrium enters as g_eq - r phi and the
+  // conserved row is not relaxed
+  {
+    R m[Q];
+    to_moments<L, R>(g, m);
+    const R H = mu + p.lam * phi;
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      if constexpr (!(SH && k == 0)) {
+        constexpr double w0 = mom_w<L>(k);
+        constexpr double rest = double(L::M[k][0]);
+        R eq;
+        if constexpr (SH) eq = R(w0 - rest) * mu;
+        else eq = R(w0) * H + R(rest) * (phi - H);
+        eq += R(3) * mom_lin<L, R, k>(Jn);
+        const R src = mom_lin<L, R, k>(V);
+        const R s = p.sgr[k];
+        m[k] = m[k] - s * (m[k] - eq) + (R(1) - R(0.5) * s) * src;
+      }
+    });
+    from_moments<L, R>(m, g);
+  }
+  // f (Eq. 25) in moment space
+  if constexpr (COUPLED) {
+    R fm[Q];
+    to_moments<L, R>(f, fm);
+    R uu = R(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) uu += u[d] * u[d];
+    static_for<0, Q>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr double w0 = mom_w<L>(k);
+      constexpr double rest = double(L::M[k][0]);
+      const R eq = R(3.0 * (w0 - rest)) * press +
+                   rho * (R(3) * mom_lin<L, R, k>(u) + R(4.5) * mom_quad<L, R, k>(u, u) - R(1.5 * w0) * uu);
+      const R src = R(3) * mom_lin<L, R, k>(Fs) + R(3) * mom_quad<L, R, k>(u, grho);
+      const R s = p.sfr[k];
+      fm[k] = fm[k] - s * (fm[k] - eq) + (R(1) - R(0.5) * s) * src;
+    });
+    from_moments<L, R>(fm, f);
+  }
+  out.rho = rho;
+  out.mu = mu;
+  out.press = press;
+#pragma unroll
+  for (int d = 0; d < D; ++d) out.u[d] = u[d];
+}
+
+template <class L, class R, bool COUPLED, bool SH>
+__device__ __forceinline__ void node_update_mom(const NodeParams<L, R>& p, const NodeIn<L, R>& in,
+                                                R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
+  StencilOut<L, R> st;
+  st.phi = in.nphi[0];
+  st.lap = stencil_lap<L, R>(in.nphi);
+  stencil_grad<L, R>(in.nphi, st.gphi);
+  stencil_grad<L, R>(in.npsi, st.gpsi);
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) st.u[d] = in.u[d];
+  node_update_mom_s<L, R, COUPLED, SH>(p, st, g, f, J, out);
+}
+
 template <class L, class R, bool COUPLED, bool SH = false>
 __device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const NodeIn<L, R>& in, R (&g)[L::Q],
                                             R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
   if constexpr (L::Q == 9) node_update_d2q9<R, COUPLED, SH>(p, in, g, f, J, out);
-  else node_update_generic<L, R, COUPLED, SH>(p, in, g, f, J, out);
+  else node_update_mom<L, R, COUPLED, SH>(p, in, g, f, J, out);
 }
 
 // Velocity of the prescribed single vortex, Eqs. 43-44, at node (x, y) and step t.
