@@ -306,6 +306,84 @@ def test_reduced_precision_volume_drift(storage, tol):
     assert np.all(drift <= tol)
 
 
+def _crossings(row):
+    """x positions where a row of phi crosses 1/2 (linear interpolation, periodic)."""
+    out = []
+    n = len(row)
+    for x in range(n):
+        a, b = row[x], row[(x + 1) % n]
+        if (a - 0.5) * (b - 0.5) < 0:
+            out.append(x + (0.5 - a) / (b - a))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16s"])
+def test_reduced_precision_interface_position(storage):
+    """Interface position against the FP64 oracle after 1000 steps of the two-drop case:
+    the four phi = 1/2 crossings along the drops' centre row, and each drop's phi >= 1/2
+    count.  FP64 is bounded by the oracle's own round-off envelope."""
+    say(f"case: two droplets {storage}, 1000 steps, interface position vs the FP64 oracle")
+    g = np.load(os.path.join(HERE, "golden", "two_droplets_fp64_t1000.npz"))
+    p, phi0, u0 = W.two_droplets(storage)
+    c = run_gpu(p, phi0, u0, 1000)
+    phi = c.observe(_v().FIELD_PHI)["phi"]
+    xo, xg = _crossings(g["phi"][0, 64]), _crossings(phi[0, 64])
+    assert len(xo) == 4 and len(xg) == 4
+    err = float(np.max(np.abs(xg - xo)))
+    r = c.reduce()
+    dcount = np.abs(r["count_half"] - g["count_half"])
+    say(f"  max |crossing - oracle| = {err:.3e} lattice units; |count - oracle| per drop {dcount}")
+    bound = {"fp64": 1e-6, "fp32": 1e-4, "fp16s": 2e-3}[storage]
+    assert err <= bound
+    assert np.all(dcount <= {"fp64": 0, "fp32": 1, "fp16s": 4}[storage])
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16s"])
+def test_reduced_precision_deformation(storage):
+    """Deformation D of a drop in shear (128 x 64, R = 16, walls moving -+0.02, 1000 steps)
+    against the FP64 oracle."""
+    from oracle.gradient import derived_after
+    p, phi0, u0 = W.shear_droplet(storage, nx=128, ny=64, R=16.0)
+    say(f"case: shear 128x64 {storage}, 1000 steps, D vs the FP64 oracle")
+    ref = derived_after(p.replace(storage="fp64"), phi0, u0, 1000)[0]
+    c = run_gpu(p, phi0, u0, 1000)
+    got = c.derived()[0]
+    dD = abs(got[4] - ref[4])
+    dV = abs(got[0] - ref[0]) / ref[0]
+    say(f"  D gpu {got[4]:.10f} oracle {ref[4]:.10f}: |dD| = {dD:.3e}; relative volume error {dV:.3e}")
+    assert dD <= {"fp64": 1e-9, "fp32": 1e-5, "fp16s": 1e-3}[storage]
+    assert dV <= {"fp64": 1e-12, "fp32": 1e-6, "fp16s": 1e-4}[storage]
+
+
+def test_single_vortex_return_per_storage():
+    """Single vortex, 256 x 256, T = 8000 (the paper's test shape): the interface error after
+    the return, sum |phi(T) - phi0| / perimeter, in each storage precision.  FP32 and FP16
+    storage must stay within 1% and 5% of the FP64 figure; FP64 on 64 x 64 (T = 1600)
+    matches the oracle's figure to 1e-6."""
+    v = _v()
+    from oracle import Model
+    p, phi0, _ = W.single_vortex(L=64, T=1600.0)
+    m = Model(p).init(phi0)
+    m.step(1600)
+    per = 2.0 * np.pi * 0.15 * 64
+    e_or = np.abs(m.phi() - phi0).sum() / per
+    c = run_gpu(p, phi0, None, 1600)
+    e_gpu = np.abs(c.observe(v.FIELD_PHI)["phi"] - phi0).sum() / per
+    say(f"  64x64 FP64: interface error gpu {e_gpu:.8f} oracle {e_or:.8f}")
+    assert abs(e_gpu - e_or) <= 1e-6
+    errs = {}
+    for storage in ("fp64", "fp32", "fp16s"):
+        p, phi0, _ = W.single_vortex(storage)
+        c = run_gpu(p, phi0, None, 8000)
+        per = 2.0 * np.pi * 0.15 * 256
+        errs[storage] = np.abs(c.observe(v.FIELD_PHI)["phi"] - phi0).sum() / per
+        vol = c.reduce()["sum_phi"].sum()
+        say(f"  256x256 {storage}: interface error after the return {errs[storage]:.6f}, "
+            f"relative volume change {abs(vol - phi0.sum()) / phi0.sum():.3e}")
+    assert abs(errs["fp32"] - errs["fp64"]) <= 0.01 * errs["fp64"]
+    assert abs(errs["fp16s"] - errs["fp64"]) <= 0.05 * errs["fp64"]
+
+
 def test_nonfinite_phi_is_reported():
     say("case: NaN in phi0 reaches the reductions")
     import torch

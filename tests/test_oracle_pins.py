@@ -491,3 +491,25 @@ def test_observables_on_known_field():
     ell = (((x - 99.5) / 40.0) ** 2 + ((y - 99.5) / 20.0) ** 2 <= 1).astype(float)[None]
     dd = derived_observables(observables_from_phi(q, ell))
     assert abs(dd["D"][0] - (40 - 20) / 60) < 5e-3
+
+
+def test_single_vortex_reverses():
+    """Single vortex (Eqs. 43-44) on 64 x 64 with T = 1600 steps: the velocity field
+    reverses at T/2, so the disc is stretched far from its start at T/2 and returns close to
+    it at T (a sign or time-scale error in Eqs. 43-44 breaks the return); the total of phi is
+    conserved; and the penalty term (lambda = 0.5) returns closer than the classical model
+    (lambda = 0), as the paper reports."""
+    errs = {}
+    for lam in (0.5, 0.0):
+        p, phi0, _ = W.single_vortex(L=64, T=1600.0)
+        p = p.replace(lam=lam)
+        m = Model(p).init(phi0)
+        per = 2.0 * np.pi * 0.15 * 64
+        m.step(800)
+        e_half = np.abs(m.phi() - phi0).sum() / per
+        m.step(800)
+        e_end = np.abs(m.phi() - phi0).sum() / per
+        assert abs(m.phi().sum() - phi0.sum()) < 1e-12 * phi0.sum()
+        assert e_half > 5.0 and e_end < 0.4, (lam, e_half, e_end)
+        errs[lam] = e_end
+    assert errs[0.5] < errs[0.0]
