@@ -237,6 +237,7 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   np.W4 = R(W / 4.0);
   np.xi = R(p.xi);
   np.lamW = R(p.lambda / W);
+  np.An4 = R(4.0 * (p.lambda / W) / ((1.0 + 2.0 * p.xi) * (1.0 + 2.0 * p.xi)));
   np.lam = R(p.lambda);
   np.beta4 = R(4.0 * (12.0 * sigma / W));
   np.kappa = R(1.5 * sigma * W);

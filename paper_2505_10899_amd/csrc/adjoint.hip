@@ -143,9 +143,8 @@ __global__ void __launch_bounds__(256) k_adj_local(DC c, AdjArgs a) {
     const bool inside = phi >= R(0) && phi <= R(1);
     const R pc = clamp01(phi);
     const R aa = pc + p.xi, bb = (R(1) - pc) + p.xi;
-    const R den = (aa + bb) * (aa + bb);
-    const R An = p.lamW * (R(4) * aa * bb) / den;
-    const R dAn = inside ? p.lamW * R(4) * (bb - aa) / den : R(0);
+    const R An = p.An4 * aa * bb;                       // a + b = 1 + 2 xi
+    const R dAn = inside ? p.An4 * (bb - aa) : R(0);
     const R gpx = R(1.0 / 3.0) * (q[1] - q[3]) + R(1.0 / 12.0) * ((q[5] - q[7]) + (q[8] - q[6]));
     const R gpy = R(1.0 / 3.0) * (q[2] - q[4]) + R(1.0 / 12.0) * ((q[5] - q[7]) + (q[6] - q[8]));
     const R lap = R(2.0 / 3.0) * (((q[1] + q[3]) + (q[2] + q[4])) - R(4) * q[0]) +

@@ -41,6 +41,42 @@ __device__ __forceinline__ void divmod_pitch(int v, int P, float rcpP, int& q, i
   }
 }
 
+// Pull of the 9 populations arriving at node (x, y) of an nx x ny case from the stored
+// direction planes src[i] (uniform over the wave): periodic wrap and, behind a wall, the
+// node's own opposite population, expressed as an offset from the direction's own plane
+// (plane opp(i) lies (opp(i) - i) n entries further), so that the base stays uniform and
+// each load is a 32-bit offset from a scalar base.  ps: phi of the writer (shifted
+// storage).
+template <class St>
+__device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9], const float* __restrict__ phis,
+                                           int x, int y, int nx, int ny, int n, bool wall,
+                                           typename St::R (&v)[9], typename St::R* ps) {
+  using R = typename St::R;
+  const int s0 = x + nx * y;
+  const int xm = x == 0 ? nx - 1 : -1;                 // to column x - 1 (wrapped)
+  const int xp = x == nx - 1 ? 1 - nx : 1;             // to column x + 1
+  const int ym = y == 0 ? (ny - 1) * nx : -nx;         // to row y - 1 (periodic)
+  const int yp = y == ny - 1 ? (1 - ny) * nx : nx;     // to row y + 1
+  // writer of direction i sits at (x - cx_i, y - cy_i)
+  int nd[9] = {s0, s0 + xm, s0 + ym, s0 + xp, s0 + yp, s0 + xm + ym, s0 + xp + ym, s0 + xp + yp, s0 + xm + yp};
+  int off[9] = {nd[0], nd[1], nd[2], nd[3], nd[4], nd[5], nd[6], nd[7], nd[8]};
+  if (wall && y == 0) {        // c_y = +1 directions 2, 5, 6 come back from 4, 7, 8 of this node
+    nd[2] = nd[5] = nd[6] = s0;
+    off[2] = off[5] = off[6] = s0 + 2 * n;
+  }
+  if (wall && y == ny - 1) {   // c_y = -1 directions 4, 7, 8 come back from 2, 5, 6
+    nd[4] = nd[7] = nd[8] = s0;
+    off[4] = off[7] = off[8] = s0 - 2 * n;
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    v[i] = St::load(src[i], off[i]);
+    if constexpr (St::shifted) {
+      if (ps) ps[i] = R(ldg(phis, nd[i]));
+    }
+  }
+}
+
 template <class St, int DL>
 __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, int y0, int y1, bool reduce,
                                             int cap, double* __restrict__ part, long part_stride, long part_index,
@@ -70,63 +106,61 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
   }
   const float* phis = c.phis[par];
   const bool wall = c.wall != 0;
-  auto row3 = [&](int yr) -> Row3 {   // yr in [0, ny)
-    Row3 o;
-    o.c = yr * nx;
-    o.m = (yr == 0 ? ny - 1 : yr - 1) * nx;
-    o.p = (yr == ny - 1 ? 0 : yr + 1) * nx;
-    o.lo = wall && yr == 0;
-    o.hi = wall && yr == ny - 1;
-    return o;
-  };
-  auto col3 = [&](int xr) -> Col3 { return Col3{xr, xr == 0 ? nx - 1 : xr - 1, xr == nx - 1 ? 0 : xr + 1}; };
   const int f_begin = y0 * P, f_end = (y1 + 2) * P;   // padded rows y0 - 1 .. y1
   const int nchunk = (f_end - f_begin + B - 1) / B;
   const int niter = nchunk + DL;
   R e[DEPTH][Q];          // pulled populations of the last DEPTH chunks (static indices only)
+  int ex[DEPTH], ey[DEPTH];   // their padded coordinates (x, y in [-1, nx] x [-1, ny])
+#pragma unroll
+  for (int k = 0; k < DEPTH; ++k) ex[k] = ey[k] = -1;
   double a0 = 0.0, ax = 0.0, ay = 0.0, axx = 0.0, ayy = 0.0, axy = 0.0;   // one label per case
   int acnt = 0, abad = 0;
+  // padded coordinates of this lane's front node, advanced by B nodes per iteration
+  int qf, rf;
+  divmod_pitch(f_begin + lane, P, rcpP, qf, rf);
+  const int dq = B / P, dr = B - dq * P;
 
   auto iteration = [&](int i, auto front_slot) {
     constexpr int SF = decltype(front_slot)::value;
     constexpr int SU = (SF + DEPTH - DL) % DEPTH;
-    // the chunk updated in this iteration: its f and previous phi u are requested first,
-    // so that they are in flight while the front's phi is formed
-    const int vu = f_begin + (i - DL) * B + lane;
-    int x = -1, y = -1;
-    if (i >= DL && vu < f_end) {
-      int q, r;
-      divmod_pitch(vu, P, rcpP, q, r);
-      x = r - 1;
-      y = q - 1;
-    }
-    const bool act = x >= 0 && x < nx && y >= y0 && y < y1;
+    // the chunk updated in this iteration (pulled DL iterations ago by this same lane):
+    // its f and previous phi u are requested first, so that they are in flight while the
+    // front's phi is formed
+    const int x = ex[SU], y = ey[SU];
+    const bool act = i >= DL && x >= 0 && x < nx && y >= y0 && y < y1;
     R f[Q], J[2];
     const int nn = x + nx * y;
     if (act) {
-      pull9<St>(fsrc, phis, col3(x), row3(y), f, nullptr);
+      pull9_flat<St>(fsrc, phis, x, y, nx, ny, n, wall, f, nullptr);
       J[0] = ldg(c.J, nn);
       J[1] = ldg(c.J, n + nn);
     }
     // front: chunk i
-    if (i < nchunk) {
+    {
       const int vf = f_begin + i * B + lane;
-      if (vf < f_end) {
-        int q, r;
-        divmod_pitch(vf, P, rcpP, q, r);
-        int xr = r - 1, yr = q - 1;
+      ex[SF] = rf - 1;
+      ey[SF] = qf - 1;
+      if (i < nchunk && vf < f_end) {
+        int xr = rf - 1, yr = qf - 1;
         xr = xr < 0 ? nx - 1 : (xr >= nx ? 0 : xr);
         if (yr < 0) yr = wall ? 0 : ny - 1;
         else if (yr >= ny) yr = wall ? ny - 1 : 0;
         R ps[Q];
-        pull9<St>(gsrc, phis, col3(xr), row3(yr), e[SF], ps);
+        pull9_flat<St>(gsrc, phis, xr, yr, nx, ny, n, wall, e[SF], ps);
         const R ph = phi_of_pulled<L, St>(e[SF], ps, c.np.rest);
         sphi[vf & mask] = ph;
         spsi[vf & mask] = psi_of<R>(ph, c.np.W4, c.np.xi);
       }
+      rf += dr;
+      qf += dq;
+      if (rf >= P) {
+        rf -= P;
+        ++qf;
+      }
     }
     __syncthreads();
     if (act) {
+      const int vu = (y + 1) * P + x + 1;
       NodeIn<L, R> in;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {

@@ -77,6 +77,7 @@ struct NodeParams {
   R W4;          // W / 4
   R xi;          // regulariser of Eq. 37
   R lamW;        // lambda / W
+  R An4;         // 4 (lambda / W) / (1 + 2 xi)^2: the correction amplitude is An4 a b
   R lam;         // lambda
   R beta4;       // 4 beta, beta = 12 sigma / W
   R kappa;       // 3 sigma W / 2
@@ -129,41 +130,6 @@ __device__ __forceinline__ R stencil_lap(const R (&nb)[L::Q]) {
   return s;
 }
 
-// pop <- pop + src - M^T diag(srate) M (pop - eq + src/2); with CONSERVE the zeroth
-// moment (sum of the populations, equal to that of the equilibrium) is not relaxed.
-template <class L, class R, bool CONSERVE>
-__device__ __forceinline__ void mrt_collide(R (&pop)[L::Q], const R (&eq)[L::Q], const R (&src)[L::Q],
-                                            const R (&srate)[L::Q]) {
-  R h[L::Q];
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i) h[i] = pop[i] - eq[i] + R(0.5) * src[i];
-  R y[L::Q];
-#pragma unroll
-  for (int k = 0; k < L::Q; ++k) {
-    R acc = R(0);
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      const int m = L::M[k][i];
-      if (m == 1) acc += h[i];
-      else if (m == -1) acc -= h[i];
-      else if (m != 0) acc += R(m) * h[i];
-    }
-    y[k] = (CONSERVE && k == 0) ? R(0) : acc * srate[k];
-  }
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    R acc = R(0);
-#pragma unroll
-    for (int k = 0; k < L::Q; ++k) {
-      const int m = L::M[k][i];
-      if (m == 1) acc += y[k];
-      else if (m == -1) acc -= y[k];
-      else if (m != 0) acc += R(m) * y[k];
-    }
-    pop[i] = pop[i] + src[i] - acc;
-  }
-}
-
 // Everything one node needs besides its own populations.
 template <class L, class R>
 struct NodeIn {
@@ -177,128 +143,6 @@ struct NodeOut {
   R rho, mu, press;
   R u[L::D];
 };
-
-// One node of one time step.  g, f: pulled (time-t) populations in, post-collision out;
-// J: previous phi u in, this step's phi u out.  With SH, g holds the deviations
-// e_i = g_i - r_i phi from the node's rest state (in and out): the equilibrium enters as
-// g_eq - r phi, and the relaxation of the conserved moment sum_i g_i (zero in exact
-// arithmetic) is dropped, so no operation rounds at the magnitude of phi.
-template <class L, class R, bool COUPLED, bool SH = false>
-__device__ __forceinline__ void node_update_generic(const NodeParams<L, R>& p, const NodeIn<L, R>& in,
-                                            R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D],
-                                            NodeOut<L, R>& out) {
-  constexpr int Q = L::Q, D = L::D;
-  const R phi = in.nphi[0];
-  const R rho = p.rho_l + phi * p.drho;
-  // factor (lambda/W)[1 - tanh^2(2 psi / W)] of Eq. 32 via tanh(0.5 ln(a/b)) = (a-b)/(a+b)
-  const R pc = clamp01(phi);
-  const R a = pc + p.xi, b = (R(1) - pc) + p.xi;
-  const R An = p.lamW * (R(4) * a * b) / ((a + b) * (a + b));
-  R gphi[D], gpsi[D];
-  stencil_grad<L, R>(in.nphi, gphi);
-  stencil_grad<L, R>(in.npsi, gpsi);
-  const R lphi = stencil_lap<L, R>(in.nphi);
-  const R mu = p.beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - p.kappa * lphi;   // Eq. 2
-  R Fs[D], grho[D], u[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    Fs[d] = mu * gphi[d];
-    grho[d] = p.drho * gphi[d];
-  }
-  R press = R(0);
-  if constexpr (COUPLED) {
-    R j[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) j[d] = R(0);
-    R P = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int cc[3] = {L::cx[i], L::cy[i], L::cz[i]};
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (cc[d] == 1) j[d] += f[i];
-        else if (cc[d] == -1) j[d] -= f[i];
-      }
-      if (i > 0) P += f[i];
-    }
-    R uu = R(0), ug = R(0);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      u[d] = (j[d] + R(0.5) * Fs[d]) / rho;                                         // Eq. 28
-      uu += u[d] * u[d];
-      ug += u[d] * grho[d];
-    }
-    const R s0 = R(-1.5 * L::w[0]) * uu;                                            // Eq. 23, i = 0
-    press = R((1.0 / 3.0) / (1.0 - L::w[0])) * (P + R(0.5) * ug + rho * s0);       // Eq. 29
-  } else {
-#pragma unroll
-    for (int d = 0; d < D; ++d) u[d] = in.u[d];
-  }
-  // backward difference of phi u
-  R dJ[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const R Jn = phi * u[d];
-    dJ[d] = Jn - J[d];
-    J[d] = Jn;
-  }
-  // V = d_t(phi u)/cs^2 + (lambda/W)(1 - tanh^2) grad psi / |grad psi|, G_i = w_i c_i . V (Eq. 32)
-  R n2 = p.eps2;
-#pragma unroll
-  for (int d = 0; d < D; ++d) n2 += gpsi[d] * gpsi[d];
-  const R inv = R(1) / sqrt(n2);
-  R V[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) V[d] = R(3) * dJ[d] + An * (gpsi[d] * inv);
-  // g: equilibrium Eq. 31 and collision Eq. 33
-  {
-    const R H = mu + p.lam * phi;
-    R geq[Q], G[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int cc[3] = {L::cx[i], L::cy[i], L::cz[i]};
-      R cJ = R(0), cV = R(0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (cc[d] == 1) { cJ += J[d]; cV += V[d]; }
-        else if (cc[d] == -1) { cJ -= J[d]; cV -= V[d]; }
-      }
-      const R wi = R(L::w[i]);
-      if constexpr (SH) geq[i] = (i == 0) ? R(L::w[0] - 1.0) * mu : wi * mu + wi * (R(3) * cJ);
-      else geq[i] = (i == 0) ? phi + R(L::w[0] - 1.0) * H : wi * H + wi * (R(3) * cJ);
-      G[i] = wi * cV;
-    }
-    mrt_collide<L, R, SH>(g, geq, G, p.sg);
-  }
-  // f: equilibrium Eqs. 22-23, forcing Eq. 21 (in the exactly equivalent form
-  // w_i [c_i.F + (c_i.u)(c_i.grad rho)] / cs^2) and collision Eq. 25
-  if constexpr (COUPLED) {
-    R uu = R(0);
-#pragma unroll
-    for (int d = 0; d < D; ++d) uu += u[d] * u[d];
-    R feq[Q], Fi[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int cc[3] = {L::cx[i], L::cy[i], L::cz[i]};
-      R cu = R(0), cF = R(0), cg = R(0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        if (cc[d] == 1) { cu += u[d]; cF += Fs[d]; cg += grho[d]; }
-        else if (cc[d] == -1) { cu -= u[d]; cF -= Fs[d]; cg -= grho[d]; }
-      }
-      const R wi = R(L::w[i]);
-      const R si = wi * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
-      feq[i] = (i == 0) ? R(3.0 * (L::w[0] - 1.0)) * press + rho * si : R(3.0 * L::w[i]) * press + rho * si;
-      Fi[i] = R(3.0 * L::w[i]) * (cF + cu * cg);
-    }
-    mrt_collide<L, R, false>(f, feq, Fi, p.sf);
-  }
-  out.rho = rho;
-  out.mu = mu;
-  out.press = press;
-#pragma unroll
-  for (int d = 0; d < D; ++d) out.u[d] = u[d];
-}
 
 // ---------------------------------------------------------------- D2Q9 in closed form
 // m = M g with the shared partial sums of the rows of Eq. 24
@@ -339,8 +183,12 @@ __device__ __forceinline__ void d2q9_from_moments(const R (&m)[9], R (&v)[9]) {
   v[8] = B + X2 - Y2 - a8;
 }
 
-// One D2Q9 node: the same time step as node_update_generic with the moments of the
-// equilibria and sources in closed form (M g_eq, M f_eq, M G and M F evaluated from
+// One D2Q9 node of one time step.  g, f: pulled (time-t) populations in, post-collision
+// out; J: previous phi u in, this step's phi u out.  With SH, g holds the deviations
+// e_i = g_i - r_i phi from the node's rest state (in and out): the equilibrium enters as
+// g_eq - r phi, and the relaxation of the conserved moment sum_i g_i (zero in exact
+// arithmetic) is dropped, so no operation rounds at the magnitude of phi.  The moments
+// of the equilibria and sources are in closed form (M g_eq, M f_eq, M G and M F evaluated from
 // Eqs. 21-24, 31-32), so that each population set costs one forward and one inverse
 // moment transform.
 template <class R, bool COUPLED, bool SH>
@@ -352,7 +200,8 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   const R rho = p.rho_l + phi * p.drho;
   const R pc = clamp01(phi);
   const R a = pc + p.xi, b = (R(1) - pc) + p.xi;
-  const R An = p.lamW * (R(4) * a * b) / ((a + b) * (a + b));
+  // (lambda/W)[1 - tanh^2(2 psi / W)] = (lambda/W) 4 a b / (a + b)^2, a + b = 1 + 2 xi
+  const R An = p.An4 * a * b;
   // Eqs. 39-40 on D2Q9: 3 w_i c_i = 1/3 (axes), 1/12 (diagonals); 6 w_i = 2/3, 1/6
   const R gpx = R(1.0 / 3.0) * (q[1] - q[3]) + R(1.0 / 12.0) * ((q[5] - q[7]) + (q[8] - q[6]));
   const R gpy = R(1.0 / 3.0) * (q[2] - q[4]) + R(1.0 / 12.0) * ((q[5] - q[7]) + (q[6] - q[8]));
@@ -367,8 +216,9 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   R fm[9];
   if constexpr (COUPLED) {
     d2q9_moments<R>(f, fm);
-    ux = (fm[3] + R(0.5) * Fx) / rho;                                            // Eq. 28
-    uy = (fm[5] + R(0.5) * Fy) / rho;
+    const R irho = R(1) / rho;
+    ux = (fm[3] + R(0.5) * Fx) * irho;                                           // Eq. 28
+    uy = (fm[5] + R(0.5) * Fy) * irho;
     const R P = fm[0] - f[0];
     const R uu = ux * ux + uy * uy, ug = ux * grx + uy * gry;
     press = R(0.6) * (P + R(0.5) * ug - R(2.0 / 3.0) * rho * uu);               // Eq. 29
@@ -380,7 +230,7 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   const R dJx = Jx - J[0], dJy = Jy - J[1];
   J[0] = Jx;
   J[1] = Jy;
-  const R inv = R(1) / sqrt(gsx * gsx + gsy * gsy + p.eps2);
+  const R inv = rsqrt(gsx * gsx + gsy * gsy + p.eps2);
   const R Vx = R(3) * dJx + An * (gsx * inv), Vy = R(3) * dJy + An * (gsy * inv);  // Eq. 32: G_i = w_i c_i . V
   // g (Eq. 33): equilibrium moments (phi, -4 phi + 2H, 4 phi - 3H, Jx, -Jx, Jy, -Jy, 0, 0), H = mu + lambda phi;
   // in deviation variables (subtract M r phi) they are (0, 2 mu, -3 mu, Jx, -Jx, Jy, -Jy, 0, 0).
@@ -504,8 +354,7 @@ __device__ __forceinline__ R mom_quad(const R (&x)[L::D], const R (&y)[L::D]) {
   return s;
 }
 
-// One node on any lattice, the same time step as node_update_generic, with the collisions
-// done in moment space and the moments of the equilibria and sources formed row by row
+// One node on any lattice (used for D3Q19), with the collisions done in moment space and the moments of the equilibria and sources formed row by row
 // from the tables above: with g_eq,i = w_i (H + 3 c_i . J) + delta_i0 (phi - H) (Eq. 31),
 // G_i = w_i c_i . V (Eq. 32), f_eq,i = 3 w_i p + delta_i0 (-3 p) + rho w_i (3 c_i . u +
 // 4.5 (c_i . u)^2 - 1.5 u . u) (Eqs. 22-23) and F_i = 3 w_i (c_i . F + (c_i . u)(c_i .
@@ -526,7 +375,8 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
   const R rho = p.rho_l + phi * p.drho;
   const R pc = clamp01(phi);
   const R a = pc + p.xi, b = (R(1) - pc) + p.xi;
-  const R An = p.lamW * (R(4) * a * b) / ((a + b) * (a + b));
+  // (lambda/W)[1 - tanh^2(2 psi / W)] = (lambda/W) 4 a b / (a + b)^2, a + b = 1 + 2 xi
+  const R An = p.An4 * a * b;
   const R* gphi = st.gphi;
   const R* gpsi = st.gpsi;
   const R lphi = st.lap;
@@ -550,9 +400,10 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
       if (D == 3 && L::cz[i] != 0) jj[2] += R(L::cz[i]) * f[i];
     }
     R uu = R(0), ug = R(0);
+    const R irho = R(1) / rho;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      u[d] = (jj[d] + R(0.5) * Fs[d]) / rho;                                        // Eq. 28
+      u[d] = (jj[d] + R(0.5) * Fs[d]) * irho;                                       // Eq. 28
       uu += u[d] * u[d];
       ug += u[d] * grho[d];
     }
@@ -565,7 +416,7 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
   R n2 = p.eps2;
 #pragma unroll
   for (int d = 0; d < D; ++d) n2 += gpsi[d] * gpsi[d];
-  const R inv = R(1) / sqrt(n2);
+  const R inv = rsqrt(n2);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     Jn[d] = phi * u[d];
