@@ -835,11 +835,15 @@ int dispatch_storage(int storage, Fn&& fn) {
 
 // work items of a tile shape: per case, bands of ty rows, x strips of bx columns fastest
 // Whether case p runs as flattened bands: when one lane per column would leave more
-// than (100 - flat_pct)% of the lanes of its row waves idle, and its rows fit the
-// flattened march with bx lanes.
+// than (100 - flat_pct)% of the lanes of its row waves idle and its rows fit the
+// flattened march with bx lanes.  Below 101 only cases that need the short lag (a row
+// fits in one chunk) qualify: the long lag holds more populations in flight and costs
+// the whole kernel a wave of occupancy.
 bool batch_case_flat(const vclb_params& p, int bx, int flat_pct) {
   const int lanes = (p.nx + 63) / 64 * 64;
-  return 100L * p.nx < long(flat_pct) * lanes && vclb::flat_lag(p.nx + 2, bx) != 0;
+  const int lag = vclb::flat_lag(p.nx + 2, bx);
+  if (lag == 0 || 100L * p.nx >= long(flat_pct) * lanes) return false;
+  return flat_pct > 100 || lag == 1;
 }
 
 // Work items, case-major: flattened bands of whole rows holding about ty * 256 nodes, or
@@ -1203,7 +1207,7 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   HIP_TRY(hipEventCreate(&e1));
   struct Cand { int bx, ty, fp; float ms; };
   std::vector<Cand> cands;
-  for (int fp : {0, 90, 101})
+  for (int fp : {0, 90, 100, 101})
     for (int bx : {64, 128, 256})
       for (int ty : {8, 16, 32, 64}) cands.push_back({bx, ty, fp, -1.0f});
   int rc = VCLB_OK;
