@@ -272,7 +272,7 @@ int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out);
 /* Total nodes of all cases. */
 int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
 
-/* Launch shape of the batched step: bx in {64, 128, 256} lanes per workgroup, and work
+/* Launch shape of the batched step: bx in {64, 128, 256, 512} lanes per workgroup, and work
    items of about ty * 256 nodes (ty in 1..1024).  get_tile also returns the number of
    resident workgroups launched per step. */
 int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty);

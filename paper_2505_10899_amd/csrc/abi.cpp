@@ -869,8 +869,8 @@ void build_items(vclb_batch* b, int bx, int ty, int flat_pct, std::vector<int4>&
 }
 
 int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
-  if (bx < 64 || bx > 256 || bx % 64 != 0 || ty < 1 || ty > 1024 || flat_pct < 0 || flat_pct > 101)
-    return fail(VCLB_EINVAL, "bad batch launch shape (bx in 64..256, multiple of 64; ty in 1..1024; flat_pct in 0..101)");
+  if (!(bx == 64 || bx == 128 || bx == 256 || bx == 512) || ty < 1 || ty > 1024 || flat_pct < 0 || flat_pct > 101)
+    return fail(VCLB_EINVAL, "bad batch launch shape (bx in {64, 128, 256, 512}; ty in 1..1024; flat_pct in 0..101)");
   int pmax = 1, lag = 1;
   for (const vclb_case* c : b->cases) {
     if (!batch_case_flat(c->p, bx, flat_pct)) continue;
@@ -1208,7 +1208,7 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   struct Cand { int bx, ty, fp; float ms; };
   std::vector<Cand> cands;
   for (int fp : {0, 90, 100, 101})
-    for (int bx : {64, 128, 256})
+    for (int bx : {64, 128, 256, 512})
       for (int ty : {8, 16, 32, 64}) cands.push_back({bx, ty, fp, -1.0f});
   int rc = VCLB_OK;
   for (Cand& cd : cands) {

@@ -37,9 +37,17 @@ __device__ __forceinline__ void fold_case(const DevCase<D2Q9, St>& c, const Batc
   __syncthreads();
 }
 
-// the lag-3 FIFO of FP32 values needs a little more than 128 VGPRs: 3 waves per SIMD
-template <class St, int DL>
-__global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : (DL == 3 ? 3 : 4))
+// Workgroups per CU the register budget is sized for: FP32 arithmetic fits 4 waves per
+// SIMD, except the lag-3 FIFO (a little more than 128 VGPRs: 3); FP64 fits 2.
+template <class St, int DL, int BS>
+constexpr int batch_min_blocks() {
+  constexpr int waves = sizeof(typename St::R) == 8 ? 2 : (DL == 3 ? 3 : 4);   // per SIMD
+  constexpr int per_block = BS / 256;                                          // waves per SIMD
+  return waves / per_block > 0 ? waves / per_block : 1;
+}
+
+template <class St, int DL, int BS>
+__global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS>()))
     k_batch_step2d(const DevCase<D2Q9, St>* __restrict__ cases, BatchArgs a) {
   extern __shared__ unsigned char smem_raw[];
   if (a.pend)
@@ -75,9 +83,15 @@ template <class St>
 int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s) {
   const size_t lds = batch_lds_bytes<St>(a.cap, bx);
   const auto* cs = static_cast<const DevCase<D2Q9, St>*>(cases);
-  if (a.lag == 1) hipLaunchKernelGGL((k_batch_step2d<St, 1>), dim3(blocks), dim3(bx), lds, s, cs, a);
-  else if (a.lag == 3) hipLaunchKernelGGL((k_batch_step2d<St, 3>), dim3(blocks), dim3(bx), lds, s, cs, a);
-  else return -1;
+  if (bx <= 256) {
+    if (a.lag == 1) hipLaunchKernelGGL((k_batch_step2d<St, 1, 256>), dim3(blocks), dim3(bx), lds, s, cs, a);
+    else if (a.lag == 3) hipLaunchKernelGGL((k_batch_step2d<St, 3, 256>), dim3(blocks), dim3(bx), lds, s, cs, a);
+    else return -1;
+  } else {
+    if (a.lag == 1) hipLaunchKernelGGL((k_batch_step2d<St, 1, 512>), dim3(blocks), dim3(bx), lds, s, cs, a);
+    else if (a.lag == 3) hipLaunchKernelGGL((k_batch_step2d<St, 3, 512>), dim3(blocks), dim3(bx), lds, s, cs, a);
+    else return -1;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -92,8 +106,13 @@ template <class St>
 int batch_max_blocks_per_cu(int bx, int cap, int lag) {
   int nb = 0;
   const size_t lds = batch_lds_bytes<St>(cap, bx);
-  const hipError_t e = lag == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 1>, bx, lds)
-                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 3>, bx, lds);
+  hipError_t e;
+  if (bx <= 256)
+    e = lag == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 1, 256>, bx, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 3, 256>, bx, lds);
+  else
+    e = lag == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 1, 512>, bx, lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 3, 512>, bx, lds);
   if (e != hipSuccess) return 0;
   return nb;
 }

@@ -31,15 +31,16 @@ def small_batch(storage="fp64", n=6, seed=7):
     return cases
 
 
-@pytest.mark.parametrize("storage,flat_pct", [("fp64", 0), ("fp64", 90), ("fp64", 101), ("fp16s", 90),
-                                              ("fp32", 101)])
-def test_batch_matches_cases_run_alone(storage, flat_pct):
-    """Column strips (flat_pct 0), flattened bands (101) and the mix (90)."""
+@pytest.mark.parametrize("storage,flat_pct,bx", [("fp64", 0, 64), ("fp64", 90, 64), ("fp64", 101, 64),
+                                                 ("fp16s", 90, 64), ("fp32", 101, 64), ("fp64", 100, 512),
+                                                 ("fp32", 0, 512)])
+def test_batch_matches_cases_run_alone(storage, flat_pct, bx):
+    """Column strips (flat_pct 0), flattened bands (101), the mixes (90, 100), 64 and 512 lanes."""
     v = _v()
     cases = small_batch(storage)
-    say("case: batch of", [(p.nx, p.ny, p.wall_y) for p, _, _ in cases], storage, "flat_pct", flat_pct)
+    say("case: batch of", [(p.nx, p.ny, p.wall_y) for p, _, _ in cases], storage, "flat_pct", flat_pct, "bx", bx)
     b = v.Batch([p for p, _, _ in cases])
-    b.set_tile(64, 16)
+    b.set_tile(bx, 16)
     b.set_schedule(flat_pct)
     assert b.schedule() == flat_pct
     for c, (p, phi0, u0) in zip(b.cases, cases):
