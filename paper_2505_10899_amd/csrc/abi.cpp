@@ -303,7 +303,7 @@ int flush_pending(vclb_case* c, hipStream_t s) {
   return rc ? fail(VCLB_EHIP, "finalize launch failed") : VCLB_OK;
 }
 
-vclb::Tile default_tile(const vclb_params& p) {
+vclb::Tile default_tile(const vclb_params& p, int ncu) {
   vclb::Tile t;
   if (p.lattice == VCLB_D2Q9) {
     // one lane per x column, rounded up to whole waves, at most 256
@@ -317,10 +317,15 @@ vclb::Tile default_tile(const vclb_params& p) {
     t.by3 = 1;
   } else {
     // 32 x 8 columns per workgroup (a halo ring of a third of the tile, one wave per two
-    // rows of 32), marching 32 planes: the fastest shape measured on a 96 x 96 x 384 case
+    // rows of 32): the fastest section measured on a 96 x 96 x 384 case.  Each workgroup
+    // is bound by its own memory round trips (two per CU fit the registers), so the
+    // columns are cut along z into as many segments as fill those slots once, with 8 to
+    // 64 planes each.
     t.bx = 32;
     t.by3 = 8;
-    t.ty = 32;
+    const long cols = long((p.nx + 31) / 32) * ((p.ny + 7) / 8);
+    const long segs = std::max(1L, 2L * ncu / cols);
+    t.ty = int(std::max(8L, std::min(64L, (p.nz + segs - 1) / segs)));
   }
   return t;
 }
@@ -383,7 +388,11 @@ int vclb_case_create(const vclb_params* p, void* workspace, size_t workspace_byt
   c->p = *p;
   fill_rates(c->p, c->sg, c->sf);
   c->lay = lay;
-  c->tile = default_tile(c->p);
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 256;
+  c->tile = default_tile(c->p, ncu);
   c->recorded.assign(vclb::kHistory, -1);
   if (workspace) {
     c->ws = static_cast<char*>(workspace);

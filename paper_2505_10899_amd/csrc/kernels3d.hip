@@ -13,9 +13,51 @@
 
 namespace vclb {
 
+// Node offsets of one 3D pull (periodic on every axis): the writer of direction i sits
+// at x - c_i, reached from the node's own index s0 by one of xm / xp, ym / yp, zm / zp
+// per axis (the wrapped steps to x - 1 / x + 1 and so on).
+struct Nbr3 {
+  int s0, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Nbr3 nbr3(int x, int y, int z, int nx, int ny, int nz, int nxy) {
+  Nbr3 o;
+  o.s0 = x + nx * y + nxy * z;
+  o.xm = x == 0 ? nx - 1 : -1;
+  o.xp = x == nx - 1 ? 1 - nx : 1;
+  o.ym = y == 0 ? (ny - 1) * nx : -nx;
+  o.yp = y == ny - 1 ? (1 - ny) * nx : nx;
+  o.zm = z == 0 ? (nz - 1) * nxy : -nxy;
+  o.zp = z == nz - 1 ? (1 - nz) * nxy : nxy;
+  return o;
+}
+
+// The 19 pulls at one node: 32-bit node offsets from the uniform base of each
+// direction's plane (the case has fewer than 2^31 nodes).  ps: phi of the writer.
 template <class St>
-__global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, int BY, int TZ, int nby,
-                                                 int nbz, int reduce) {
+__device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, const float* __restrict__ phis,
+                                       long n, const Nbr3& o, typename St::R (&out)[19], typename St::R* ps) {
+  using L = D3Q19;
+  using R = typename St::R;
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    int s = o.s0;
+    if constexpr (L::cx[i] > 0) s += o.xm;
+    if constexpr (L::cx[i] < 0) s += o.xp;
+    if constexpr (L::cy[i] > 0) s += o.ym;
+    if constexpr (L::cy[i] < 0) s += o.yp;
+    if constexpr (L::cz[i] > 0) s += o.zm;
+    if constexpr (L::cz[i] < 0) s += o.zp;
+    out[i] = St::load(src + i * n, s);
+    if constexpr (St::shifted) {
+      if (ps) ps[i] = R(ldg(phis, s));
+    }
+  });
+}
+
+template <class St>
+__global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, int BY, int nby, int nbz,
+                                                 int reduce) {
   using L = D3Q19;
   using R = typename St::R;
   constexpr int Q = L::Q;
@@ -30,8 +72,9 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
   const int bz = tile % nbz;
   const int rest = tile / nbz;
   const int byi = rest % nby, bxi = rest / nby;
-  const int x0 = bxi * BX, y0 = byi * BY, z0 = bz * TZ;
-  const int z1 = min(z0 + TZ, c.nz);
+  // the nbz workgroups of a column share its planes evenly (they differ by at most one)
+  const int x0 = bxi * BX, y0 = byi * BY;
+  const int z0 = int(long(bz) * c.nz / nbz), z1 = int(long(bz + 1) * c.nz / nbz);
   const int xg = x0 + tx, yg = y0 + ty;
   const bool active = xg < c.nx && yg < c.ny;
   const int xw = xg % c.nx, yw = yg % c.ny;
@@ -40,13 +83,14 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
   const typename St::S* gsrc = c.pop[0][par];
   const typename St::S* fsrc = c.pop[1][par];
   const float* phis = c.phis[par];
+  const int nx = c.nx, ny = c.ny, nz = c.nz, nxy = nx * ny;
   const int ring = 2 * PW + 2 * BY;
   auto slot = [](int r) -> int { return (r + 4) & 3; };
   auto plane = [&](int z, R (&g)[Q]) {
     const int zr = wrapi(z, c.nz);
     const int s = slot(z) * PS;
     R ps[Q];
-    pull<L, St>(c, gsrc, phis, xw, yw, zr, g, ps);
+    pull19<St>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy), g, ps);
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     sphi[s + (ty + 1) * PW + tx + 1] = ph;
     spsi[s + (ty + 1) * PW + tx + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
@@ -59,10 +103,10 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       else if (k < 2 * PW) { px = k - PW; py = PH - 1; }
       else if (k < 2 * PW + BY) { px = 0; py = 1 + k - 2 * PW; }
       else { px = PW - 1; py = 1 + k - 2 * PW - BY; }
-      const int hx = ((x0 - 1 + px) % c.nx + c.nx) % c.nx;
-      const int hy = ((y0 - 1 + py) % c.ny + c.ny) % c.ny;
+      const int hx = ((x0 - 1 + px) % nx + nx) % nx;
+      const int hy = ((y0 - 1 + py) % ny + ny) % ny;
       R gh[Q], hps[Q];
-      pull<L, St>(c, gsrc, phis, hx, hy, zr, gh, hps);
+      pull19<St>(gsrc, phis, c.n, nbr3(hx, hy, zr, nx, ny, nz, nxy), gh, hps);
       const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       sphi[s + py * PW + px] = hp;
       spsi[s + py * PW + px] = psi_of<R>(hp, c.np.W4, c.np.xi);
@@ -88,6 +132,16 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
   plane(z0 - 1, gnext);
   plane(z0, gcur);
   for (int z = z0; z < z1; ++z) {
+    // this plane's f and previous phi u are requested together with the next plane's
+    // g, so that one memory round trip per plane covers both
+    const Nbr3 o = nbr3(xw, yw, z, nx, ny, nz, nxy);
+    const int nn = o.s0;
+    R f[Q], J[L::D];
+    if (active) {
+      pull19<St>(fsrc, phis, c.n, o, f, nullptr);
+#pragma unroll
+      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.n, nn);
+    }
     plane(z + 1, gnext);
     __syncthreads();
     if (active) {
@@ -107,14 +161,16 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
         if (L::cy[i] != 0) { st.gphi[1] += R(3.0 * L::w[i] * L::cy[i]) * ph; st.gpsi[1] += R(3.0 * L::w[i] * L::cy[i]) * ps; }
         if (L::cz[i] != 0) { st.gphi[2] += R(3.0 * L::w[i] * L::cz[i]) * ph; st.gpsi[2] += R(3.0 * L::w[i] * L::cz[i]) * ps; }
       }
-      const long n = xw + long(c.nx) * (yw + long(c.ny) * z);
-      R f[Q], J[L::D];
-      pull<L, St>(c, fsrc, phis, xw, yw, z, f, nullptr);
-#pragma unroll
-      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J, d * c.n + n);
       NodeOut<L, R> out;
       node_update_mom_s<L, R, true, St::shifted>(c.np, st, gcur, f, J, out);
-      store_node<L, St, true>(c, par, n, yw, st.phi, out.rho, gcur, f, J);
+      const int dst = par ^ 1;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + i * c.n, nn, gcur[i]);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, nn, f[i]);
+#pragma unroll
+      for (int d = 0; d < L::D; ++d) stg(c.J + d * c.n, nn, J[d]);
+      if constexpr (St::shifted) stg(c.phis[dst], nn, float(st.phi));
       if (reduce) {
         const double ph = double(st.phi);
         double dz[kMaxLabels];
@@ -168,7 +224,7 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   const int nbz = (c.nz + tile.ty - 1) / tile.ty;
   const size_t lds = size_t(2) * 4 * (tile.bx + 2) * (tile.by3 + 2) * sizeof(typename St::R);
   hipLaunchKernelGGL((k_step3d<St>), dim3(nbx * nby * nbz), dim3(tile.bx * tile.by3), lds, s, c, tile.bx,
-                     tile.by3, tile.ty, nby, nbz, reduce);
+                     tile.by3, nby, nbz, reduce);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

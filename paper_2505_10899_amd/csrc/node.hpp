@@ -290,24 +290,59 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
   }
 }
 
-// m = M v with the integer matrix of the lattice (zero entries skipped at compile time)
+// Every moment row of both bases has a definite parity under c -> -c: even rows see a
+// pair of opposite populations only through their sum, odd rows only through their
+// difference.  The transforms below work on those sums and differences, which halves
+// the multiply-adds of a full matrix product (zero entries are skipped at compile time).
+template <class L>
+constexpr int row_parity(int k) {   // +1 even, -1 odd, 0 neither
+  bool even = true, odd = true;
+  for (int i = 0; i < L::Q; ++i) {
+    even = even && L::M[k][i] == L::M[k][L::opp[i]];
+    odd = odd && L::M[k][i] == -L::M[k][L::opp[i]];
+  }
+  return even ? 1 : (odd ? -1 : 0);
+}
+template <class L>
+constexpr bool pair_lead(int i) {   // first member of an opposite pair
+  return L::opp[i] > i;
+}
+
+// acc += c x for a compile-time integer c
+template <int C, class R>
+__device__ __forceinline__ void add_int_times(R& acc, R x) {
+  if constexpr (C == 1) acc += x;
+  else if constexpr (C == -1) acc -= x;
+  else if constexpr (C != 0) acc += R(C) * x;
+}
+
+// m = M v
 template <class L, class R>
 __device__ __forceinline__ void to_moments(const R (&v)[L::Q], R (&m)[L::Q]) {
+  R sp[L::Q], dp[L::Q];   // pair sums and differences, at the lead index
+  static_for<0, L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    if constexpr (pair_lead<L>(i)) {
+      sp[i] = v[i] + v[L::opp[i]];
+      dp[i] = v[i] - v[L::opp[i]];
+    }
+  });
   static_for<0, L::Q>([&](auto K) {
     constexpr int k = decltype(K)::value;
+    constexpr int par = row_parity<L>(k);
+    static_assert(par != 0, "moment rows must have a definite parity");
     R acc = R(0);
-    static_for<0, L::Q>([&](auto I) {
+    add_int_times<L::M[k][0]>(acc, v[0]);
+    static_for<1, L::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      constexpr int c = L::M[k][i];
-      if constexpr (c == 1) acc += v[i];
-      else if constexpr (c == -1) acc -= v[i];
-      else if constexpr (c != 0) acc += R(c) * v[i];
+      if constexpr (pair_lead<L>(i)) add_int_times<L::M[k][i]>(acc, par > 0 ? sp[i] : dp[i]);
     });
     m[k] = acc;
   });
 }
 
-// v = M^{-1} m = M^T diag(1 / |M_k|^2) m (m is scaled in place)
+// v = M^{-1} m = M^T diag(1 / |M_k|^2) m (m is scaled in place): for each pair the even
+// rows give the common part and the odd rows the antisymmetric part
 template <class L, class R>
 __device__ __forceinline__ void from_moments(R (&m)[L::Q], R (&v)[L::Q]) {
   R (&a)[L::Q] = m;
@@ -317,15 +352,20 @@ __device__ __forceinline__ void from_moments(R (&m)[L::Q], R (&v)[L::Q]) {
   });
   static_for<0, L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    R acc = R(0);
-    static_for<0, L::Q>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      constexpr int c = L::M[k][i];
-      if constexpr (c == 1) acc += a[k];
-      else if constexpr (c == -1) acc -= a[k];
-      else if constexpr (c != 0) acc += R(c) * a[k];
-    });
-    v[i] = acc;
+    if constexpr (i == 0 || pair_lead<L>(i)) {
+      R ev = R(0), od = R(0);
+      static_for<0, L::Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (row_parity<L>(k) > 0) add_int_times<L::M[k][i]>(ev, a[k]);
+        else add_int_times<L::M[k][i]>(od, a[k]);
+      });
+      if constexpr (i == 0) {
+        v[0] = ev + od;
+      } else {
+        v[i] = ev + od;
+        v[L::opp[i]] = ev - od;
+      }
+    }
   });
 }
 
