@@ -815,10 +815,13 @@ struct vclb_batch {
   void* d_cases = nullptr;
   int4* d_items = nullptr;
   int2* d_case_items = nullptr;
+  int2* d_runs = nullptr;             // (first item, count) per resident workgroup slot
+  size_t runs_cap = 0;
   double* part[2] = {nullptr, nullptr};
   size_t items_cap = 0;
   std::vector<int4> items;
   std::vector<int2> case_items;
+  std::vector<int2> runs;
   int bx = 128, ty = 32, blocks = 0, cap = 0, lag = 1, flat_pct = 90;
   int reduce_every = 1;
   int64_t nodes = 0;
@@ -856,7 +859,8 @@ bool batch_case_flat(const vclb_params& p, int bx, int flat_pct) {
 }
 
 // Work items, case-major: flattened bands of whole rows holding about ty * 256 nodes, or
-// strips of bx columns by bands of rows holding about as many nodes.
+// strips of bx columns by bands of rows holding about as many nodes (strip-major, so that
+// a run of items marches on down one strip).
 void build_items(vclb_batch* b, int bx, int ty, int flat_pct, std::vector<int4>& items, std::vector<int2>& ci) {
   items.clear();
   ci.assign(size_t(b->n), int2{0, 0});
@@ -870,10 +874,85 @@ void build_items(vclb_batch* b, int bx, int ty, int flat_pct, std::vector<int4>&
     } else {
       const int w = std::min(bx, (p.nx + 63) / 64 * 64);
       const int rows = std::max(4, std::min(p.ny, ty * 256 / w));
-      for (int y0 = 0; y0 < p.ny; y0 += rows)
-        for (int x0 = 0; x0 < p.nx; x0 += bx) items.push_back(int4{k, x0, y0, std::min(y0 + rows, p.ny)});
+      for (int x0 = 0; x0 < p.nx; x0 += bx)
+        for (int y0 = 0; y0 < p.ny; y0 += rows) items.push_back(int4{k, x0, y0, std::min(y0 + rows, p.ny)});
     }
     ci[size_t(k)] = int2{first, int(items.size()) - first};
+  }
+}
+
+// Cut the case-major item list into nb runs of consecutive items, one per resident
+// workgroup, with about equal iteration counts: a flattened band of r rows costs
+// ceil((r + 2) P / bx) + lag chunk iterations, a strip band r + 2 row iterations (both
+// pull two halo rows).  An item that straddles the end of a run is split between rows.
+// The smallest per-run budget that fits in nb runs is found by bisection.
+void partition_runs(const vclb_batch* b, int bx, int lag, int nb, std::vector<int4>& items, std::vector<int2>& ci,
+                    std::vector<int2>& runs) {
+  struct Cost { double over, row; };
+  auto cost_of = [&](const int4& w) -> Cost {
+    if (w.y < 0) {
+      const double P = b->cases[size_t(w.x)]->p.nx + 2.0;
+      return {2.0 * P / bx + lag + 0.5, P / bx};
+    }
+    return {2.0, 1.0};
+  };
+  // fn(piece, new_run) for each piece of the cut with budget T; returns the runs used
+  auto cut = [&](double T, auto&& fn) -> int {
+    int used = 0;
+    double fill = 0.0;
+    for (const int4& w : items) {
+      const Cost c = cost_of(w);
+      int y = w.z;
+      while (y < w.w) {
+        const int left = w.w - y;
+        if (fill + c.over + left * c.row <= T) {
+          fn(int4{w.x, w.y, y, w.w}, fill == 0.0);
+          if (fill == 0.0) ++used;
+          fill += c.over + left * c.row;
+          break;
+        }
+        int rr = int((T - fill - c.over) / c.row);
+        if (rr < 1 && fill > 0.0) {   // no room left here: the next run starts with this item
+          fill = 0.0;
+          continue;
+        }
+        rr = std::max(1, std::min(rr, left));
+        fn(int4{w.x, w.y, y, y + rr}, fill == 0.0);
+        if (fill == 0.0) ++used;
+        y += rr;
+        fill = 0.0;   // the run is full
+      }
+    }
+    return used;
+  };
+  double total = 0.0, biggest = 0.0;
+  for (const int4& w : items) {
+    const Cost c = cost_of(w);
+    total += c.over + (w.w - w.z) * c.row;
+    biggest = std::max(biggest, c.over + c.row);
+  }
+  double lo = std::max(total / nb, biggest), hi = total + 1.0;
+  auto none = [](const int4&, bool) {};
+  for (int k = 0; k < 60 && hi - lo > 1e-3 * lo; ++k) {
+    const double mid = 0.5 * (lo + hi);
+    if (cut(mid, none) <= nb) hi = mid;
+    else lo = mid;
+  }
+  std::vector<int4> out;
+  out.reserve(items.size() + size_t(nb));
+  runs.clear();
+  cut(hi, [&](const int4& w, bool fresh) {
+    if (fresh) runs.push_back(int2{int(out.size()), 0});
+    out.push_back(w);
+    runs.back().y += 1;
+  });
+  runs.resize(size_t(nb), int2{int(out.size()), 0});   // spare slots take no items
+  items.swap(out);
+  ci.assign(size_t(b->n), int2{0, 0});
+  for (size_t i = 0; i < items.size(); ++i) {
+    int2& r = ci[size_t(items[i].x)];
+    if (r.y == 0) r.x = int(i);
+    r.y += 1;
   }
 }
 
@@ -890,17 +969,20 @@ int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
   const size_t lds = dispatch_storage(b->storage, [&](auto st) { return int(vclb::batch_lds_bytes<decltype(st)>(cap, bx)); });
   if (lds > 64 * 1024) return fail(VCLB_EINVAL, "a case is too wide for the batched step with this tile");
   std::vector<int4> items;
-  std::vector<int2> ci;
+  std::vector<int2> ci, runs;
   build_items(b, bx, ty, flat_pct, items, ci);
-  if (items.size() > b->items_cap) return fail(VCLB_EINVAL, "too many work items");
-  HIP_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(b->d_case_items, ci.data(), ci.size() * sizeof(int2), hipMemcpyHostToDevice));
   int per_cu = dispatch_storage(b->storage, [&](auto st) { return vclb::batch_max_blocks_per_cu<decltype(st)>(bx, cap, lag); });
   int dev = 0, ncu = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   if (per_cu < 1) per_cu = 1;
-  b->blocks = int(std::min<long>(long(items.size()), long(per_cu) * ncu));
+  const int nb = int(std::min<long>(long(per_cu) * ncu, long(b->runs_cap)));
+  partition_runs(b, bx, lag, nb, items, ci, runs);
+  if (items.size() > b->items_cap) return fail(VCLB_EINVAL, "too many work items");
+  HIP_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_case_items, ci.data(), ci.size() * sizeof(int2), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_runs, runs.data(), runs.size() * sizeof(int2), hipMemcpyHostToDevice));
+  b->blocks = nb;
   b->bx = bx;
   b->ty = ty;
   b->flat_pct = flat_pct;
@@ -908,6 +990,7 @@ int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
   b->lag = lag;
   b->items = std::move(items);
   b->case_items = std::move(ci);
+  b->runs = std::move(runs);
   return VCLB_OK;
 }
 
@@ -915,6 +998,7 @@ vclb::BatchArgs batch_args(const vclb_batch* b, int64_t t, int reduce) {
   vclb::BatchArgs a{};
   a.items = b->d_items;
   a.nitems = int(b->items.size());
+  a.runs = b->d_runs;
   a.case_items = b->d_case_items;
   a.ncases = b->n;
   a.part_w = b->part[t & 1];
@@ -1000,10 +1084,14 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
   }
   const size_t o_cases = total;
   total += align_up(b->dcase_stride * size_t(ncases));
+  const size_t runs_cap = 16384;   // resident workgroups: CUs x workgroups per CU
+  cap += runs_cap;                  // each run end may split one item
   const size_t o_items = total;
   total += align_up(cap * sizeof(int4));
   const size_t o_ci = total;
   total += align_up(size_t(ncases) * sizeof(int2));
+  const size_t o_runs = total;
+  total += align_up(runs_cap * sizeof(int2));
   size_t o_part[2];
   for (int i = 0; i < 2; ++i) {
     o_part[i] = total;
@@ -1020,6 +1108,8 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
   b->d_cases = b->ws + o_cases;
   b->d_items = reinterpret_cast<int4*>(b->ws + o_items);
   b->d_case_items = reinterpret_cast<int2*>(b->ws + o_ci);
+  b->d_runs = reinterpret_cast<int2*>(b->ws + o_runs);
+  b->runs_cap = runs_cap;
   for (int i = 0; i < 2; ++i) b->part[i] = reinterpret_cast<double*>(b->ws + o_part[i]);
   for (int k = 0; k < ncases; ++k) {
     vclb_case* c = nullptr;
@@ -1218,7 +1308,7 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   std::vector<Cand> cands;
   for (int fp : {0, 90, 100, 101})
     for (int bx : {64, 128, 256, 512})
-      for (int ty : {8, 16, 32, 64}) cands.push_back({bx, ty, fp, -1.0f});
+      for (int ty : {8, 16, 32, 64, 1024}) cands.push_back({bx, ty, fp, -1.0f});
   int rc = VCLB_OK;
   for (Cand& cd : cands) {
     if (batch_set_tile(b, cd.bx, cd.ty, cd.fp) == VCLB_EINVAL) continue;   // shape not valid for these cases

@@ -1,7 +1,8 @@
 // Many independent D2Q9 cases of uneven sizes advanced by one work-list kernel per step.
 //
-// A fixed number of resident workgroups strides over the work items of all cases.  An
-// item is either a strip of columns marched row by row (step2d_tile, one lane per
+// A fixed number of resident workgroups each take one run of consecutive work items,
+// the runs cut on the host so that every workgroup has about the same number of
+// iterations (items are split between rows where a run ends).  An item is either a strip of columns marched row by row (step2d_tile, one lane per
 // column: best when the width is close to a multiple of the wave size) or a band of
 // whole rows marched in padded row-major order (step2d_flat: every lane busy for any
 // width, at some extra index arithmetic); the host picks per case.  The n launches of a call are captured in one hipGraph and
@@ -52,12 +53,10 @@ __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS>()))
   extern __shared__ unsigned char smem_raw[];
   if (a.pend)
     for (int cs = blockIdx.x; cs < a.ncases; cs += gridDim.x) fold_case<St>(cases[cs], a, cs);
-  // rounds of gridDim.x consecutive items; within a round, consecutive items go to one
-  // XCD (neighbouring tiles of a case share halo lines in its L2)
-  const int slot = xcd_tile(blockIdx.x, gridDim.x);
-  for (int base = 0; base < a.nitems; base += gridDim.x) {
-    const int it = base + slot;
-    if (it >= a.nitems) break;
+  // consecutive runs go to one XCD: the rows where one run ends and the next begins are
+  // read by both, through that XCD's L2
+  const int2 run = a.runs[xcd_tile(blockIdx.x, gridDim.x)];
+  for (int it = run.x; it < run.x + run.y; ++it) {
     const int4 w = a.items[it];
     if (w.y < 0)   // a band of whole rows, marched in padded row-major order
       step2d_flat<St, DL>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);

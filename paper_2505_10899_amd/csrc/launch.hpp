@@ -40,6 +40,7 @@ struct BatchArgs {
   const int4* items;        // (case, x0, y0, y1) of every work item, case-major; x0 < 0: a
                             // flattened band of rows [y0, y1), else a strip of columns from x0
   int nitems;
+  const int2* runs;         // (first item, item count) of each resident workgroup slot
   const int2* case_items;   // (first item, item count) per case
   int ncases;
   double* part_w;           // [12][nitems] partials written by this launch
