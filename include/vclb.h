@@ -273,8 +273,10 @@ int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out);
 int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
 
 /* Launch shape of the batched step: bx in {64, 128, 256, 512} lanes per workgroup, and work
-   items of about ty * 256 nodes (ty in 1..1024).  get_tile also returns the number of
-   resident workgroups launched per step. */
+   items of at most about ty * 256 nodes (ty in 1..1024; 1024 keeps cases up to 512 x 512
+   whole).  As many workgroups as can be resident are launched, each given one run of
+   consecutive items with about equal work (an item is split between rows where a run
+   ends); get_tile also returns that workgroup count.  Default: bx 512, ty 1024. */
 int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty);
 int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks);
 
@@ -283,7 +285,7 @@ int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* 
    rows marched in padded row-major order (every lane busy, some extra index arithmetic);
    the others run as strips of bx columns, one lane per column.  Below 101 only cases
    whose padded row fits in bx lanes qualify for bands; 101 puts every case that fits in
-   bands, 0 every case in strips (default 90). */
+   bands, 0 every case in strips (default 100). */
 int vclb_batch_set_schedule(vclb_batch* b, int32_t flat_pct);
 int vclb_batch_get_schedule(const vclb_batch* b, int32_t* flat_pct);
 

@@ -822,7 +822,7 @@ struct vclb_batch {
   std::vector<int4> items;
   std::vector<int2> case_items;
   std::vector<int2> runs;
-  int bx = 128, ty = 32, blocks = 0, cap = 0, lag = 1, flat_pct = 90;
+  int bx = 512, ty = 1024, blocks = 0, cap = 0, lag = 1, flat_pct = 100;
   int reduce_every = 1;
   int64_t nodes = 0;
   bool pend = false;
@@ -1149,7 +1149,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
     vclb_batch_destroy(b);
     return hip_fail(e, "batch set-up");
   }
-  int rc = batch_set_tile(b, 256, 32, 90);
+  int rc = batch_set_tile(b, 512, 1024, 100);   // whole-case items, 512-lane workgroups
   if (rc) {
     vclb_batch_destroy(b);
     return rc;
