@@ -146,9 +146,11 @@ int vclb_case_create(const vclb_params* p, void* workspace, size_t workspace_byt
                      vclb_case** out);
 void vclb_case_destroy(vclb_case* c);
 
-/* Tile of the fused step kernel: bx threads (lanes = x columns, a multiple of 64,
-   64..1024) marching over ty rows (y for D2Q9, z for D3Q19; >= 1), by3 rows of y per
-   block for D3Q19 (ignored for D2Q9).  Returns EINVAL for shapes outside the limits. */
+/* Tile of the fused step kernel.  D2Q9: bx lanes (x columns; a multiple of 64 in
+   64..256) marching ty >= 1 rows of y (by3 ignored).  D3Q19: a bx x by3 section of (x, y)
+   columns (bx * by3 a multiple of 64, at most 256) marching the planes of z, which
+   ceil(nz / ty) workgroups per section share evenly.  Returns EINVAL for shapes outside
+   these limits. */
 int vclb_case_set_tile(vclb_case* c, int32_t bx, int32_t ty, int32_t by3);
 int vclb_case_get_tile(const vclb_case* c, int32_t* bx, int32_t* ty, int32_t* by3);
 

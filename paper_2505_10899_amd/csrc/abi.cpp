@@ -318,13 +318,15 @@ vclb::Tile default_tile(const vclb_params& p, int ncu) {
   } else {
     // 32 x 8 columns per workgroup (a halo ring of a third of the tile, one wave per two
     // rows of 32): the fastest section measured on a 96 x 96 x 384 case.  Each workgroup
-    // is bound by its own memory round trips (two per CU fit the registers), so the
-    // columns are cut along z into as many segments as fill those slots once, with 8 to
-    // 64 planes each.
+    // is bound by its own memory round trips, so the columns are cut along z into as many
+    // segments as fill 2 (FP64, FP32) or 3 (FP16S) workgroups per CU once, with 8 to 64
+    // planes each.  Three fit the registers with 4-byte arithmetic, but in FP32 the
+    // longer segments of two per CU measured faster (fewer halo planes per segment).
     t.bx = 32;
     t.by3 = 8;
     const long cols = long((p.nx + 31) / 32) * ((p.ny + 7) / 8);
-    const long segs = std::max(1L, 2L * ncu / cols);
+    const long per_cu = p.storage == VCLB_FP16S ? 3 : 2;
+    const long segs = std::max(1L, per_cu * ncu / cols);
     t.ty = int(std::max(8L, std::min(64L, (p.nz + segs - 1) / segs)));
   }
   return t;
@@ -334,9 +336,11 @@ int check_tile(const vclb_params& p, const vclb::Tile& t) {
   if (p.lattice == VCLB_D2Q9) {
     if (t.bx < 64 || t.bx > 256 || t.bx % 64 != 0 || t.ty < 1) return fail(VCLB_EINVAL, "bad 2D tile");
   } else {
-    if (t.bx < 1 || t.by3 < 1 || t.bx * t.by3 > 512 || (t.bx * t.by3) % 64 != 0 || t.ty < 1)
-      return fail(VCLB_EINVAL, "bad 3D tile (bx * by3 must be a multiple of 64, at most 512)");
-    const size_t lds = size_t(2) * 4 * (t.bx + 2) * (t.by3 + 2) * arith_bytes(p.storage);
+    if (t.bx < 1 || t.by3 < 1 || t.bx * t.by3 > 256 || (t.bx * t.by3) % 64 != 0 || t.ty < 1)
+      return fail(VCLB_EINVAL, "bad 3D tile (bx * by3 must be a multiple of 64, at most 256)");
+    const size_t lds = p.storage == VCLB_FP64   ? vclb::step3d_lds_bytes<vclb::StoreF64>(t.bx, t.by3)
+                       : p.storage == VCLB_FP32 ? vclb::step3d_lds_bytes<vclb::StoreF32>(t.bx, t.by3)
+                                                : vclb::step3d_lds_bytes<vclb::StoreF16S>(t.bx, t.by3);
     if (lds > 65536) return fail(VCLB_EINVAL, "3D tile needs more than 64 KiB of LDS");
   }
   return VCLB_OK;

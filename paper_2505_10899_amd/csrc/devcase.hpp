@@ -183,8 +183,9 @@ __device__ __forceinline__ double block_sum_fields(const double (&v)[NF], int nf
 // slot; k_finalize sums the slots in workgroup order after the kernel has finished
 // (no device-scope fence inside the step: on gfx950 it would write back and invalidate
 // the XCD's whole L2, which the neighbouring tiles are still reading).
-__device__ __forceinline__ void write_partials(const Acc& a, int nl, double* part, long stride, long index) {
-  __shared__ double red[16 * kMaxLabels * 12];
+// red: LDS scratch of at least (waves of the workgroup) x 24 doubles
+__device__ __forceinline__ void write_partials(const Acc& a, int nl, double* part, long stride, long index,
+                                               double* red) {
   constexpr int NF = kMaxLabels * 12;
   const int nf = nl * 12;
   double v[NF];
@@ -196,10 +197,18 @@ __device__ __forceinline__ void write_partials(const Acc& a, int nl, double* par
   // field-major [field][workgroup]: the second pass reads each field coalesced
   if (int(threadIdx.x) < nf) part[long(threadIdx.x) * stride + index] = s;
 }
+__device__ __forceinline__ void write_partials(const Acc& a, int nl, double* part, long stride, long index) {
+  __shared__ double red[16 * kMaxLabels * 12];
+  write_partials(a, nl, part, stride, index, red);
+}
 
 template <class Case>
 __device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool reduce) {
   if (reduce) write_partials(a, c.nl, c.part_w, gridDim.x, blockIdx.x);
+}
+template <class Case>
+__device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool reduce, double* red) {
+  if (reduce) write_partials(a, c.nl, c.part_w, gridDim.x, blockIdx.x, red);
 }
 
 // store one node's post-collision state (with the moving-wall term on f for the
@@ -248,9 +257,8 @@ __device__ __forceinline__ void prescribed(const DevCase<L, St>& c, int x, int y
 // Second pass of the volume reductions: sum the pending partials of an earlier launch
 // in a fixed order (deterministic) into c.pend_dest.  Run by one whole workgroup.
 template <class Case>
-__device__ __forceinline__ void fold_pending(const Case& c) {
+__device__ __forceinline__ void fold_pending(const Case& c, double* red) {
   constexpr int NF = kMaxLabels * 12;
-  __shared__ double red[16 * NF];
   const int nf = c.nl * 12;
   const int nb = c.pend_nb;
   double v[NF];
@@ -268,6 +276,11 @@ __device__ __forceinline__ void fold_pending(const Case& c) {
     if (f == 0) c.pend_dest[k * kObsFields + 12] = double(c.pend_step);
   }
   __syncthreads();
+}
+template <class Case>
+__device__ __forceinline__ void fold_pending(const Case& c) {
+  __shared__ double red[16 * kMaxLabels * 12];
+  fold_pending(c, red);
 }
 
 // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs, so

@@ -55,16 +55,31 @@ __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, c
   });
 }
 
+// Workgroups per CU the register budget is sized for (256 lanes each): with 4-byte
+// arithmetic the next plane's pulled g waits in LDS instead of registers, so three fit
+// (at most 168 VGPRs); FP64 keeps it in registers at two.
 template <class St>
-__global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, int BY, int nby, int nbz,
-                                                 int reduce) {
+constexpr bool stage3d() {
+  return sizeof(typename St::R) == 4;
+}
+template <class St>
+constexpr int step3d_min_blocks() {
+  return stage3d<St>() ? 3 : 2;
+}
+
+// NL: labels of the volume reductions (1 or 2), fixed per case
+template <class St, int NL>
+__global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCase<D3Q19, St> c, int BX, int BY,
+                                                                        int nby, int nbz, int reduce) {
   using L = D3Q19;
   using R = typename St::R;
   constexpr int Q = L::Q;
+  constexpr bool STAGE = stage3d<St>();
   extern __shared__ unsigned char smem_raw[];
   const int PW = BX + 2, PH = BY + 2, PS = PW * PH;
   R* sphi = reinterpret_cast<R*>(smem_raw);
   R* spsi = sphi + 4 * PS;
+  R* sg = spsi + 4 * PS;   // STAGE: [2][Q][nthr], the pulled g of planes z and z + 1, per lane
   const int nthr = BX * BY;
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
@@ -86,6 +101,7 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
   const int nx = c.nx, ny = c.ny, nz = c.nz, nxy = nx * ny;
   const int ring = 2 * PW + 2 * BY;
   auto slot = [](int r) -> int { return (r + 4) & 3; };
+  // pull plane z into g, form phi and psi into the ring (with the halo ring)
   auto plane = [&](int z, R (&g)[Q]) {
     const int zr = wrapi(z, c.nz);
     const int s = slot(z) * PS;
@@ -112,25 +128,38 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       spsi[s + py * PW + px] = psi_of<R>(hp, c.np.W4, c.np.xi);
     }
   };
-  if (blockIdx.x == 0 && c.pend_nb > 0) fold_pending(c);
+  // lane-private staging of a pulled plane (consecutive lanes, consecutive words)
+  auto stage_put = [&](int z, const R (&g)[Q]) {
+    R* d = sg + (z & 1) * Q * nthr + tid;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i * nthr] = g[i];
+  };
+  auto stage_get = [&](int z, R (&g)[Q]) {
+    const R* d = sg + (z & 1) * Q * nthr + tid;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = d[i * nthr];
+  };
+  // the ring's LDS serves as reduction scratch before the march and after it
+  if (blockIdx.x == 0 && c.pend_nb > 0) fold_pending(c, reinterpret_cast<double*>(smem_raw));
   // reductions: the lane's (x, y) is fixed, so per label only sum phi, sum phi dz,
   // sum phi dz^2 and the counts are accumulated; the x and y moments follow at the end
-  double dxl[kMaxLabels], dyl[kMaxLabels];
+  double s0[NL], s1[NL], s2[NL];
+  int cnt[NL], bad[NL];
 #pragma unroll
-  for (int k = 0; k < kMaxLabels; ++k) {
-    dxl[k] = min_image(double(xw) - c.cen[k][0], c.nx, true);
-    dyl[k] = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
-  }
-  double s0[kMaxLabels], s1[kMaxLabels], s2[kMaxLabels];
-  int cnt[kMaxLabels], bad[kMaxLabels];
-#pragma unroll
-  for (int k = 0; k < kMaxLabels; ++k) {
+  for (int k = 0; k < NL; ++k) {
     s0[k] = s1[k] = s2[k] = 0.0;
     cnt[k] = bad[k] = 0;
   }
   R gcur[Q], gnext[Q];
-  plane(z0 - 1, gnext);
-  plane(z0, gcur);
+  if constexpr (STAGE) {
+    plane(z0 - 1, gnext);
+    stage_put(z0 - 1, gnext);
+    plane(z0, gnext);
+    stage_put(z0, gnext);
+  } else {
+    plane(z0 - 1, gnext);
+    plane(z0, gcur);
+  }
   for (int z = z0; z < z1; ++z) {
     // this plane's f and previous phi u are requested together with the next plane's
     // g, so that one memory round trip per plane covers both
@@ -143,8 +172,10 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.n, nn);
     }
     plane(z + 1, gnext);
+    if constexpr (STAGE) stage_put(z + 1, gnext);
     __syncthreads();
     if (active) {
+      if constexpr (STAGE) stage_get(z, gcur);
       // stencils of Eqs. 39-40 accumulated straight from the LDS ring
       StencilOut<L, R> st;
       const int s0i = slot(z) * PS + (ty + 1) * PW + tx + 1;
@@ -173,34 +204,42 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
       if constexpr (St::shifted) stg(c.phis[dst], nn, float(st.phi));
       if (reduce) {
         const double ph = double(st.phi);
-        double dz[kMaxLabels];
-#pragma unroll
-        for (int k = 0; k < kMaxLabels; ++k) dz[k] = min_image(double(z) - c.cen[k][2], c.nz, true);
         int lab = 0;
-        if (c.nl > 1) {
-          const double r0 = dxl[0] * dxl[0] + dyl[0] * dyl[0] + dz[0] * dz[0];
-          const double r1 = dxl[1] * dxl[1] + dyl[1] * dyl[1] + dz[1] * dz[1];
-          lab = (r1 < r0) ? 1 : 0;
+        if constexpr (NL > 1) {
+          double r[2];
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const double dx = min_image(double(xw) - c.cen[k][0], c.nx, true);
+            const double dy = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
+            const double dz = min_image(double(z) - c.cen[k][2], c.nz, true);
+            r[k] = dx * dx + dy * dy + dz * dz;
+          }
+          lab = (r[1] < r[0]) ? 1 : 0;
         }
         const bool fin = isfinite(ph);
 #pragma unroll
-        for (int k = 0; k < kMaxLabels; ++k) {
+        for (int k = 0; k < NL; ++k) {
+          const double dz = min_image(double(z) - c.cen[k][2], c.nz, true);
           const double w = (k == lab) ? ph : 0.0;
           s0[k] += w;
-          s1[k] += w * dz[k];
-          s2[k] += w * dz[k] * dz[k];
+          s1[k] += w * dz;
+          s2[k] += w * dz * dz;
           cnt[k] += (k == lab && ph >= 0.5) ? 1 : 0;
           bad[k] += (k == lab && !fin) ? 1 : 0;
         }
       }
     }
+    if constexpr (!STAGE) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
+      for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
+    }
   }
   Acc acc;
+  acc.zero();
 #pragma unroll
-  for (int k = 0; k < kMaxLabels; ++k) {
-    const double dx = dxl[k], dy = dyl[k];
+  for (int k = 0; k < NL; ++k) {
+    const double dx = min_image(double(xw) - c.cen[k][0], c.nx, true);
+    const double dy = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
     acc.v[k][0] = s0[k];
     acc.v[k][1] = double(cnt[k]);
     acc.v[k][2] = dx * s0[k];
@@ -214,7 +253,15 @@ __global__ void __launch_bounds__(512) k_step3d(DevCase<D3Q19, St> c, int BX, in
     acc.v[k][10] = dy * s1[k];
     acc.v[k][11] = double(bad[k]);
   }
-  finish_block(c, acc, reduce != 0);
+  __syncthreads();
+  finish_block(c, acc, reduce != 0, reinterpret_cast<double*>(smem_raw));
+}
+
+template <class St>
+size_t step3d_lds_bytes(int bx, int by3) {
+  const size_t ring = size_t(2) * 4 * (bx + 2) * (by3 + 2) * sizeof(typename St::R);
+  const size_t stage = stage3d<St>() ? size_t(2) * D3Q19::Q * bx * by3 * sizeof(typename St::R) : 0;
+  return ring + stage;
 }
 
 template <class St>
@@ -222,12 +269,20 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   const int nbx = (c.nx + tile.bx - 1) / tile.bx;
   const int nby = (c.ny + tile.by3 - 1) / tile.by3;
   const int nbz = (c.nz + tile.ty - 1) / tile.ty;
-  const size_t lds = size_t(2) * 4 * (tile.bx + 2) * (tile.by3 + 2) * sizeof(typename St::R);
-  hipLaunchKernelGGL((k_step3d<St>), dim3(nbx * nby * nbz), dim3(tile.bx * tile.by3), lds, s, c, tile.bx,
-                     tile.by3, nby, nbz, reduce);
+  if (tile.bx * tile.by3 > 256) return -1;
+  const size_t lds = step3d_lds_bytes<St>(tile.bx, tile.by3);
+  if (c.nl > 1)
+    hipLaunchKernelGGL((k_step3d<St, 2>), dim3(nbx * nby * nbz), dim3(tile.bx * tile.by3), lds, s, c, tile.bx,
+                       tile.by3, nby, nbz, reduce);
+  else
+    hipLaunchKernelGGL((k_step3d<St, 1>), dim3(nbx * nby * nbz), dim3(tile.bx * tile.by3), lds, s, c, tile.bx,
+                       tile.by3, nby, nbz, reduce);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+template size_t step3d_lds_bytes<StoreF64>(int, int);
+template size_t step3d_lds_bytes<StoreF32>(int, int);
+template size_t step3d_lds_bytes<StoreF16S>(int, int);
 template int launch_step3d<StoreF64>(const DevCase<D3Q19, StoreF64>&, const Tile&, int, hipStream_t);
 template int launch_step3d<StoreF32>(const DevCase<D3Q19, StoreF32>&, const Tile&, int, hipStream_t);
 template int launch_step3d<StoreF16S>(const DevCase<D3Q19, StoreF16S>&, const Tile&, int, hipStream_t);

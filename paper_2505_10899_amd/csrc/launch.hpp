@@ -35,6 +35,8 @@ template <class L, class St>
 int launch_finalize(const DevCase<L, St>& c, hipStream_t s);
 template <class St>
 int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hipStream_t s);
+template <class St>
+size_t step3d_lds_bytes(int bx, int by3);   // LDS of the fused 3D step for a bx x by3 section
 
 struct BatchArgs {
   const int4* items;        // (case, x0, y0, y1) of every work item, case-major; x0 < 0: a
