@@ -83,10 +83,14 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
   const int nthr = BX * BY;
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
+  // x sections fastest, then y, then z segments: the sections of one z segment march
+  // together on one XCD, so the lines a section shares with its neighbours (the pulls
+  // across its edges and its halo ring) are found in that XCD's L2
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int bz = tile % nbz;
-  const int rest = tile / nbz;
-  const int byi = rest % nby, bxi = rest / nby;
+  const int nbx = int(gridDim.x) / (nby * nbz);
+  const int bxi = tile % nbx;
+  const int rest = tile / nbx;
+  const int byi = rest % nby, bz = rest / nby;
   // the nbz workgroups of a column share its planes evenly (they differ by at most one)
   const int x0 = bxi * BX, y0 = byi * BY;
   const int z0 = int(long(bz) * c.nz / nbz), z1 = int(long(bz + 1) * c.nz / nbz);
