@@ -197,6 +197,9 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   d.n = long(p.nx) * p.ny * p.nz;
   d.wall = p.bc_y == VCLB_WALL;
   d.nl = std::max(1, p.nlabels);
+  d.unit_rates = 1;
+  for (int k = 0; k < L::Q; ++k)
+    if ((!L::g_flux_row[k] && c.sg[k] != 1.0) || (!L::f_stress_row[k] && c.sf[k] != 1.0)) d.unit_rates = 0;
   for (int k = 0; k < vclb::kMaxLabels; ++k)
     for (int a = 0; a < 3; ++a) {
       double v;

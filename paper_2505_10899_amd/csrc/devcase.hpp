@@ -21,6 +21,7 @@ struct DevCase {
   long n;                       // nx * ny * nz
   int wall;                     // bounce-back walls bound y
   int nl;                       // labels (1..kMaxLabels)
+  int unit_rates;               // every rate outside the g flux and f stress rows is 1
   double cen[kMaxLabels][3];    // label centres
   S* pop[2][2];                 // [g = 0, f = 1][buffer]; f is null in vortex mode
   R* J;                         // previous phi u, D * n

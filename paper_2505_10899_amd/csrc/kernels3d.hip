@@ -67,8 +67,9 @@ constexpr int step3d_min_blocks() {
   return stage3d<St>() ? 3 : 2;
 }
 
-// NL: labels of the volume reductions (1 or 2), fixed per case
-template <class St, int NL>
+// NL: labels of the volume reductions (1 or 2), fixed per case; UNIT: the case's rates
+// outside the g flux and f stress rows are all 1
+template <class St, int NL, bool UNIT>
 __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCase<D3Q19, St> c, int BX, int BY,
                                                                         int nby, int nbz, int reduce) {
   using L = D3Q19;
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
         if (L::cz[i] != 0) { st.gphi[2] += R(3.0 * L::w[i] * L::cz[i]) * ph; st.gpsi[2] += R(3.0 * L::w[i] * L::cz[i]) * ps; }
       }
       NodeOut<L, R> out;
-      node_update_mom_s<L, R, true, St::shifted>(c.np, st, gcur, f, J, out);
+      node_update_mom_s<L, R, true, St::shifted, UNIT>(c.np, st, gcur, f, J, out);
       const int dst = par ^ 1;
 #pragma unroll
       for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + i * c.n, nn, gcur[i]);
@@ -275,12 +276,14 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   const int nbz = (c.nz + tile.ty - 1) / tile.ty;
   if (tile.bx * tile.by3 > 256) return -1;
   const size_t lds = step3d_lds_bytes<St>(tile.bx, tile.by3);
-  if (c.nl > 1)
-    hipLaunchKernelGGL((k_step3d<St, 2>), dim3(nbx * nby * nbz), dim3(tile.bx * tile.by3), lds, s, c, tile.bx,
-                       tile.by3, nby, nbz, reduce);
-  else
-    hipLaunchKernelGGL((k_step3d<St, 1>), dim3(nbx * nby * nbz), dim3(tile.bx * tile.by3), lds, s, c, tile.bx,
-                       tile.by3, nby, nbz, reduce);
+  const dim3 grid(nbx * nby * nbz), block(tile.bx * tile.by3);
+  if (c.nl > 1) {
+    if (c.unit_rates) hipLaunchKernelGGL((k_step3d<St, 2, true>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
+    else hipLaunchKernelGGL((k_step3d<St, 2, false>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
+  } else {
+    if (c.unit_rates) hipLaunchKernelGGL((k_step3d<St, 1, true>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
+    else hipLaunchKernelGGL((k_step3d<St, 1, false>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

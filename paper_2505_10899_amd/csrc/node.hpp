@@ -316,8 +316,23 @@ __device__ __forceinline__ void add_int_times(R& acc, R x) {
   else if constexpr (C != 0) acc += R(C) * x;
 }
 
-// m = M v
-template <class L, class R>
+// Row selections for to_moments: every row, or only the rows whose relaxation rate is not
+// fixed at 1 when the other rates are (then m*_k = m_k^eq + src_k / 2 needs no m_k): the
+// g flux rows (and the conserved row, kept as is in deviation variables), the f stress rows.
+struct AllRows {
+  static constexpr bool need(int) { return true; }
+};
+template <class L>
+struct GRateRows {
+  static constexpr bool need(int k) { return k == 0 || L::g_flux_row[k]; }
+};
+template <class L>
+struct FRateRows {
+  static constexpr bool need(int k) { return L::f_stress_row[k]; }
+};
+
+// m = M v (rows outside `Rows` are left at zero)
+template <class L, class R, class Rows = AllRows>
 __device__ __forceinline__ void to_moments(const R (&v)[L::Q], R (&m)[L::Q]) {
   R sp[L::Q], dp[L::Q];   // pair sums and differences, at the lead index
   static_for<0, L::Q>([&](auto I) {
@@ -332,11 +347,13 @@ __device__ __forceinline__ void to_moments(const R (&v)[L::Q], R (&m)[L::Q]) {
     constexpr int par = row_parity<L>(k);
     static_assert(par != 0, "moment rows must have a definite parity");
     R acc = R(0);
-    add_int_times<L::M[k][0]>(acc, v[0]);
-    static_for<1, L::Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      if constexpr (pair_lead<L>(i)) add_int_times<L::M[k][i]>(acc, par > 0 ? sp[i] : dp[i]);
-    });
+    if constexpr (Rows::need(k)) {
+      add_int_times<L::M[k][0]>(acc, v[0]);
+      static_for<1, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (pair_lead<L>(i)) add_int_times<L::M[k][i]>(acc, par > 0 ? sp[i] : dp[i]);
+      });
+    }
     m[k] = acc;
   });
 }
@@ -407,7 +424,9 @@ struct StencilOut {
   R u[L::D];   // prescribed velocity (vortex mode only)
 };
 
-template <class L, class R, bool COUPLED, bool SH>
+// UNIT: every rate outside the g flux rows and the f stress rows is exactly 1 (the
+// defaults); those rows then relax straight to m_eq + src / 2 without forming m.
+template <class L, class R, bool COUPLED, bool SH, bool UNIT = false>
 __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, const StencilOut<L, R>& st,
                                                   R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
   constexpr int Q = L::Q, D = L::D;
@@ -467,7 +486,8 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
   // conserved row is not relaxed
   {
     R m[Q];
-    to_moments<L, R>(g, m);
+    if constexpr (UNIT) to_moments<L, R, GRateRows<L>>(g, m);
+    else to_moments<L, R>(g, m);
     const R H = mu + p.lam * phi;
     static_for<0, Q>([&](auto K) {
       constexpr int k = decltype(K)::value;
@@ -479,8 +499,12 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
         else eq = R(w0) * H + R(rest) * (phi - H);
         eq += R(3) * mom_lin<L, R, k>(Jn);
         const R src = mom_lin<L, R, k>(V);
-        const R s = p.sgr[k];
-        m[k] = m[k] - s * (m[k] - eq) + (R(1) - R(0.5) * s) * src;
+        if constexpr (UNIT && !GRateRows<L>::need(k)) {
+          m[k] = eq + R(0.5) * src;
+        } else {
+          const R s = p.sgr[k];
+          m[k] = m[k] - s * (m[k] - eq) + (R(1) - R(0.5) * s) * src;
+        }
       }
     });
     from_moments<L, R>(m, g);
@@ -488,7 +512,8 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
   // f (Eq. 25) in moment space
   if constexpr (COUPLED) {
     R fm[Q];
-    to_moments<L, R>(f, fm);
+    if constexpr (UNIT) to_moments<L, R, FRateRows<L>>(f, fm);
+    else to_moments<L, R>(f, fm);
     R uu = R(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) uu += u[d] * u[d];
@@ -499,8 +524,12 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
       const R eq = R(3.0 * (w0 - rest)) * press +
                    rho * (R(3) * mom_lin<L, R, k>(u) + R(4.5) * mom_quad<L, R, k>(u, u) - R(1.5 * w0) * uu);
       const R src = R(3) * mom_lin<L, R, k>(Fs) + R(3) * mom_quad<L, R, k>(u, grho);
-      const R s = p.sfr[k];
-      fm[k] = fm[k] - s * (fm[k] - eq) + (R(1) - R(0.5) * s) * src;
+      if constexpr (UNIT && !FRateRows<L>::need(k)) {
+        fm[k] = eq + R(0.5) * src;
+      } else {
+        const R s = p.sfr[k];
+        fm[k] = fm[k] - s * (fm[k] - eq) + (R(1) - R(0.5) * s) * src;
+      }
     });
     from_moments<L, R>(fm, f);
   }

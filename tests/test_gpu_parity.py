@@ -168,10 +168,19 @@ def _small_case(variant):
     if variant == "d3q19":
         p = W.CaseParams(nx=16, ny=12, nz=20, lattice="D3Q19", sigma=0.005, nu=0.05, rho_light=0.1)
         return p, W.cylinder_phi(p, 7.5, 5.5, 4.0, 0.1, 20.0), None
+    if variant == "d3q19_rates":   # rates off their defaults outside the flux and stress rows
+        sg = [0.0] * 19
+        sf = [0.0] * 19
+        sg[1], sg[2], sg[10], sg[16] = 1.3, 1.1, 0.9, 1.6
+        sf[1], sf[4], sf[12], sf[18] = 1.2, 1.5, 0.8, 1.4
+        p = W.CaseParams(nx=16, ny=12, nz=20, lattice="D3Q19", sigma=0.005, nu=0.05, rho_light=0.1,
+                         s_g=tuple(sg), s_f=tuple(sf))
+        return p, W.cylinder_phi(p, 7.5, 5.5, 4.0, 0.1, 20.0), None
     raise ValueError(variant)
 
 
-VARIANTS = ["periodic_ragged", "walls_moving", "vortex", "classical_lambda0", "mrt_rates", "narrow_tall", "d3q19"]
+VARIANTS = ["periodic_ragged", "walls_moving", "vortex", "classical_lambda0", "mrt_rates", "narrow_tall", "d3q19",
+            "d3q19_rates"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
