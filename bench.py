@@ -106,7 +106,7 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     for c, (p, phi0, u0) in zip(b.cases, cases):
         c.init(phi0, u0)
     N = b.nodes()
-    v0 = np.array([c.reduce()["sum_phi"].sum() for c in b.cases])
+    v0 = b.reduce()["sum_phi"].sum(axis=1)
     if fixed:                      # (bx, ty, flat_pct) given: no autotuning (profiling runs)
         b.set_tile(fixed[0], fixed[1])
         b.set_schedule(fixed[2])
@@ -134,7 +134,7 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     e1.record(s)
     torch.cuda.synchronize()
     launch_ms = e0.elapsed_time(e1) / launch_steps
-    v1 = np.array([c.reduce()["sum_phi"].sum() for c in b.cases])
+    v1 = b.reduce()["sum_phi"].sum(axis=1)
     t_end = b.cases[0].time()
     drift = float(np.max(np.abs(v1 - v0) / np.abs(v0)))
     bpn = BYTES_PER_NODE[("D2Q9", True)][storage]

@@ -294,6 +294,19 @@ int vclb_batch_get_schedule(const vclb_batch* b, int32_t* flat_pct);
 /* Record each case's volume reductions every `every` steps (0: off; default 1). */
 int vclb_batch_set_reduce_every(vclb_batch* b, int32_t every);
 
+/* Volume reductions (Eq. 35's phi summed per label, with its first and second moments)
+   of every case's current state in one call: out[k * VCLB_MAX_LABELS + l] for case k and
+   label l (host memory, ncases * VCLB_MAX_LABELS entries; labels beyond a case's count
+   are zero).  Synchronises the stream.  Returns VCLB_ENONFINITE (after filling out) if
+   any case saw a NaN/Inf, VCLB_ESTATE if a case is not initialised. */
+int vclb_batch_reduce(vclb_batch* b, vclb_obs* out, void* stream);
+
+/* The recorded per-step reductions of steps [t_first, t_first + count) of every case:
+   out[(j * ncases + k) * VCLB_MAX_LABELS + l] for step t_first + j (host memory).
+   VCLB_ESTATE if a step of some case is not in its history (older than VCLB_HISTORY
+   steps or not recorded). */
+int vclb_batch_history(vclb_batch* b, int64_t t_first, int32_t count, vclb_obs* out, void* stream);
+
 /* Advance every case by nsteps (all cases must be initialised and at the same step).
    use_graph != 0: the launches are captured into one hipGraph on a library stream
    ordered after `stream`.  Asynchronous with respect to the host. */

@@ -1220,6 +1220,89 @@ int vclb_batch_set_reduce_every(vclb_batch* b, int32_t every) {
   return VCLB_OK;
 }
 
+int vclb_batch_reduce(vclb_batch* b, vclb_obs* out, void* stream) {
+  if (!b || !out) return fail(VCLB_EINVAL, "NULL argument");
+  for (vclb_case* c : b->cases)
+    if (!c->inited) return fail(VCLB_ESTATE, "reduce before every case is initialised");
+  hipStream_t s = as_stream(stream);
+  const size_t row = size_t(VCLB_MAX_LABELS) * vclb::kObsFields;
+  std::vector<double> v(size_t(b->n) * row, 0.0);
+  for (int k = 0; k < b->n; ++k) {
+    vclb_case* c = b->cases[size_t(k)];
+    if (int rc0 = flush_pending(c, s)) return rc0;
+    const int rc = dispatch(*c, [&](auto dc, auto) {
+      using DC = decltype(dc);
+      return vclb::launch_reduce_state<typename DevTraits<DC>::L, typename DevTraits<DC>::St>(dc, s);
+    });
+    if (rc) return fail(VCLB_EHIP, "reduce kernel launch failed");
+    const int nl = std::max(1, c->p.nlabels);
+    HIP_TRY(hipMemcpyAsync(v.data() + size_t(k) * row, c->ws + c->lay.cur, size_t(nl) * vclb::kObsFields * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  bool bad = false;
+  for (int k = 0; k < b->n; ++k) {
+    const vclb_case* c = b->cases[size_t(k)];
+    const int nl = std::max(1, c->p.nlabels);
+    vclb_obs* o = out + size_t(k) * VCLB_MAX_LABELS;
+    std::memset(o, 0, sizeof(vclb_obs) * VCLB_MAX_LABELS);
+    unpack_obs(v.data() + size_t(k) * row, nl, o);
+    for (int l = 0; l < VCLB_MAX_LABELS; ++l) {
+      o[l].step = c->t_host;
+      o[l].label = l;
+      bad = bad || o[l].nonfinite;
+    }
+  }
+  if (bad) return fail(VCLB_ENONFINITE, "phi has a NaN/Inf");
+  return VCLB_OK;
+}
+
+int vclb_batch_history(vclb_batch* b, int64_t t_first, int32_t count, vclb_obs* out, void* stream) {
+  if (!b || !out || count < 0 || t_first < 0) return fail(VCLB_EINVAL, "bad argument");
+  if (count > vclb::kHistory) return fail(VCLB_EINVAL, "count exceeds the history length");
+  if (count == 0) return VCLB_OK;
+  for (vclb_case* c : b->cases)
+    for (int64_t t = t_first; t < t_first + count; ++t)
+      if (c->recorded[size_t(t % vclb::kHistory)] != t) return fail(VCLB_ESTATE, "step not in the history");
+  hipStream_t s = as_stream(stream);
+  // per case, its slots of the device ring in step order (at most two copies: the ring wraps)
+  std::vector<std::vector<double>> rows(size_t(b->n));
+  for (int k = 0; k < b->n; ++k) {
+    vclb_case* c = b->cases[size_t(k)];
+    if (int rc0 = flush_pending(c, s)) return rc0;
+    const size_t drow = size_t(std::max(1, c->p.nlabels)) * vclb::kObsFields;
+    rows[size_t(k)].resize(size_t(count) * drow);
+    for (int32_t j = 0; j < count;) {
+      const int64_t slot = (t_first + j) % vclb::kHistory;
+      const int32_t run = int32_t(std::min<int64_t>(count - j, vclb::kHistory - slot));
+      HIP_TRY(hipMemcpyAsync(rows[size_t(k)].data() + size_t(j) * drow,
+                             c->ws + c->lay.hist + size_t(slot) * drow * sizeof(double), size_t(run) * drow * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      j += run;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  bool bad = false;
+  for (int32_t j = 0; j < count; ++j)
+    for (int k = 0; k < b->n; ++k) {
+      const vclb_case* c = b->cases[size_t(k)];
+      const int nl = std::max(1, c->p.nlabels);
+      vclb_obs* o = out + (size_t(j) * b->n + k) * VCLB_MAX_LABELS;
+      std::memset(o, 0, sizeof(vclb_obs) * VCLB_MAX_LABELS);
+      unpack_obs(rows[size_t(k)].data() + size_t(j) * nl * vclb::kObsFields, nl, o);
+      for (int l = 0; l < nl; ++l) {
+        if (o[l].step != t_first + j) return fail(VCLB_ESTATE, "history slot overwritten");
+        bad = bad || o[l].nonfinite;
+      }
+      for (int l = nl; l < VCLB_MAX_LABELS; ++l) {
+        o[l].step = t_first + j;
+        o[l].label = l;
+      }
+    }
+  if (bad) return fail(VCLB_ENONFINITE, "phi had a NaN/Inf");
+  return VCLB_OK;
+}
+
 int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stream) {
   if (!b || nsteps < 0) return fail(VCLB_EINVAL, "bad batch step arguments");
   const int64_t t0 = b->cases[0]->t_host;

@@ -92,6 +92,8 @@ _SIGS = [
     ("vclb_batch_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     ("vclb_batch_get_tile", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     ("vclb_batch_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("vclb_batch_reduce", ctypes.c_int, [ctypes.c_void_p, _P(Obs), ctypes.c_void_p]),
+    ("vclb_batch_history", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
     ("vclb_batch_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("vclb_batch_get_schedule", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32)]),
     ("vclb_batch_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
@@ -482,6 +484,30 @@ class Batch:
 
     def set_reduce_every(self, every: int):
         check(lib().vclb_batch_set_reduce_every(self.h, int(every)))
+
+    def reduce(self, stream=None) -> dict:
+        """Volume reductions of every case's current state in one call: arrays shaped
+        (ncases, MAX_LABELS, ...); labels beyond a case's count are zero."""
+        n = len(self.cases)
+        arr = (Obs * (n * MAX_LABELS))()
+        rc = lib().vclb_batch_reduce(self.h, arr, _stream_handle(stream))
+        if rc not in (VCLB_OK, VCLB_ENONFINITE):
+            check(rc)
+        d = _obs_to_dict(arr, n * MAX_LABELS)
+        out = {k: v.reshape((n, MAX_LABELS) + v.shape[1:]) for k, v in d.items()}
+        out["rc"] = rc
+        return out
+
+    def history(self, t_first: int, count: int, stream=None) -> dict:
+        """Recorded per-step reductions of every case, arrays shaped (count, ncases,
+        MAX_LABELS, ...)."""
+        n = len(self.cases)
+        arr = (Obs * (count * n * MAX_LABELS))()
+        rc = lib().vclb_batch_history(self.h, int(t_first), int(count), arr, _stream_handle(stream))
+        if rc not in (VCLB_OK, VCLB_ENONFINITE):
+            check(rc)
+        d = _obs_to_dict(arr, count * n * MAX_LABELS)
+        return {k: v.reshape((count, n, MAX_LABELS) + v.shape[1:]) for k, v in d.items()}
 
     def set_schedule(self, flat_pct: int):
         check(lib().vclb_batch_set_schedule(self.h, int(flat_pct)))

@@ -160,3 +160,13 @@ def test_adjoint_entry_points_reject_without_gpu():
     assert L.vclb_adjoint_record(h, phi, None, v.HOST, 10, 0, None) == v.VCLB_EINVAL
     assert L.vclb_adjoint_run(h, seed, 0.1, None, v.DEVICE, out, None) == v.VCLB_EINVAL
     L.vclb_case_destroy(h)
+
+
+def test_batch_entry_points_reject_null_without_gpu():
+    v = _vclb()
+    L = v.lib()
+    out = (v.Obs * 4)()
+    assert L.vclb_batch_reduce(None, out, None) == v.VCLB_EINVAL
+    assert L.vclb_batch_history(None, 0, 1, out, None) == v.VCLB_EINVAL
+    assert L.vclb_batch_step(None, 1, 1, None) == v.VCLB_EINVAL
+    assert L.vclb_batch_set_reduce_every(None, 1) == v.VCLB_EINVAL

@@ -81,6 +81,33 @@ def test_batch_graph_equals_eager_and_history():
         assert abs(r["sum_phi"][0] - h["sum_phi"][-1, 0]) <= 1e-5 * abs(r["sum_phi"][0])
 
 
+def test_batch_reduce_and_history_match_each_case():
+    """The batch-level reductions equal each case's own reduce() and history()."""
+    v = _v()
+    cases = small_batch("fp64", n=5, seed=5)
+    b = v.Batch([p for p, _, _ in cases])
+    for c, (p, phi0, u0) in zip(b.cases, cases):
+        c.init(phi0, u0)
+    b.step(9)
+    r = b.reduce()
+    h = b.history(2, 7)
+    assert r["rc"] == v.VCLB_OK
+    assert r["sum_phi"].shape == (len(cases), v.MAX_LABELS)
+    assert h["sum_phi"].shape == (7, len(cases), v.MAX_LABELS)
+    for k, c in enumerate(b.cases):
+        nl = c.nlabels
+        rk = c.reduce()
+        hk = c.history(2, 7)
+        for f in ("sum_phi", "count_half", "sum_phi_d", "sum_phi_dd"):
+            assert np.array_equal(r[f][k, :nl], rk[f]), (k, f)
+            assert np.array_equal(h[f][:, k, :nl], hk[f]), (k, f)
+        assert np.all(r["sum_phi"][k, nl:] == 0.0)
+        assert np.all(h["step"][:, k, :] == np.arange(2, 9)[:, None])
+    assert b.history(0, 9)["sum_phi"].shape[0] == 9
+    with pytest.raises(v.VclbError):
+        b.history(5, 10)                       # steps 9..14 were never taken
+
+
 def test_batch_autotune_restores_state_and_uses_cache(tmp_path):
     v = _v()
     cases = small_batch("fp32", n=4, seed=11)
