@@ -189,7 +189,7 @@ def run_adjoint(nsteps: int = 4000, every: int = 200):
 
 
 # ----------------------------------------------------------------------------- single cases
-def run_single(name: str, storage: str, steps: int, warmup: int):
+def run_single(name: str, storage: str, steps: int, warmup: int, tune: bool = True):
     import torch
     import workloads as W
     from paper_2505_10899_amd import vclb
@@ -198,6 +198,8 @@ def run_single(name: str, storage: str, steps: int, warmup: int):
     else:
         p, phi0, u0 = W.rayleigh_plateau(storage)
     c = vclb.Case(p).init(phi0, u0)
+    if tune:
+        c.autotune(None, steps=3)
     c.step(warmup)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
@@ -258,6 +260,8 @@ def main(argv=None):
                     help="storage=bx,ty,flat_pct[;...]: fixed batched launch shapes instead of autotuning")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-single-tune", action="store_true",
+                    help="single cases keep their default tiles (profiling runs: one tile per kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (a known-size reference "
@@ -315,7 +319,7 @@ def main(argv=None):
         single = {}
         for name, st in (("two_droplets_4096", "fp32"), ("two_droplets_4096", "fp64"),
                          ("two_droplets_4096", "fp16s"), ("rayleigh_plateau_96x96x384", "fp32")):
-            single[f"{name}_{st}"] = run_single(name, st, min(a.steps, 100), 10)
+            single[f"{name}_{st}"] = run_single(name, st, min(a.steps, 100), 10, tune=not a.no_single_tune)
             log(f"single {name} {st}: {single[f'{name}_{st}']}")
         out["single_case"] = single
     if a.copy_probe:

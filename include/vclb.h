@@ -154,6 +154,15 @@ void vclb_case_destroy(vclb_case* c);
 int vclb_case_set_tile(vclb_case* c, int32_t bx, int32_t ty, int32_t by3);
 int vclb_case_get_tile(const vclb_case* c, int32_t* bx, int32_t* ty, int32_t* by3);
 
+/* Pick the tile of the fused step by timing `steps` steps of each candidate on the
+   current state (saved and restored, as are the step counter and the recorded history),
+   or take it from the JSON-lines file cache_path when that holds an entry for this case's
+   lattice, storage, mode, shape, boundary and label count; a measured choice is appended
+   to cache_path (NULL: no file).  D2Q9 candidates: bx in {64, 128, 256} x ty in
+   {8, ..., 128}; D3Q19: six column sections with their planes cut to fill 1..4
+   workgroups per CU.  Synchronises the stream; VCLB_ESTATE before init. */
+int vclb_case_autotune(vclb_case* c, const char* cache_path, int32_t steps, void* stream);
+
 /* Initial state from phi0 (N doubles) and u0 (D*N doubles, NULL for u = 0; ignored in
    vortex mode): g = g_eq(phi0, mu0, u0) (Eq. 31), f = f_eq(p = 0, rho(phi0), u0) (Eq. 22),
    previous phi u = phi0 u0; step counter 0. */

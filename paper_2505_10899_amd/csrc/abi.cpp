@@ -611,6 +611,116 @@ static int do_steps(vclb_case* c, int64_t nsteps, void* stream, bool fused) {
 }
 
 int vclb_step(vclb_case* c, int64_t nsteps, void* stream) { return do_steps(c, nsteps, stream, true); }
+
+int vclb_case_autotune(vclb_case* c, const char* cache_path, int32_t steps, void* stream) {
+  if (!c || steps < 1) return fail(VCLB_EINVAL, "bad autotune arguments");
+  if (!c->inited) return fail(VCLB_ESTATE, "autotune needs an initialised case (its state is restored)");
+  const vclb_params& p = c->p;
+  const std::string desc = "case:" + std::to_string(p.lattice) + ":" + std::to_string(p.storage) + ":" +
+                           std::to_string(p.mode) + ":" + std::to_string(p.nx) + "x" + std::to_string(p.ny) + "x" +
+                           std::to_string(p.nz) + (p.bc_y == VCLB_WALL ? "w" : "p") + std::to_string(std::max(1, p.nlabels));
+  char key[32];
+  std::snprintf(key, sizeof(key), "%016llx", static_cast<unsigned long long>(fnv1a(desc.data(), desc.size())));
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[4096];
+      int bx = 0, ty = 0, by3 = 0;
+      while (std::fgets(line, sizeof(line), f)) {
+        if (!std::strstr(line, key)) continue;
+        const char* pb = std::strstr(line, "\"bx\": ");
+        const char* pt = std::strstr(line, "\"ty\": ");
+        const char* py = std::strstr(line, "\"by3\": ");
+        if (pb && pt && py) {
+          bx = std::atoi(pb + 6);
+          ty = std::atoi(pt + 6);
+          by3 = std::atoi(py + 7);
+        }
+      }
+      std::fclose(f);
+      if (bx > 0 && ty > 0 && by3 > 0) return vclb_case_set_tile(c, bx, ty, by3);
+    }
+  }
+  // candidates: 2D strips of bx lanes by ty rows; 3D sections of bx x by3 columns with
+  // their z extent cut into as many segments as fill 1..4 workgroups per CU once
+  std::vector<vclb::Tile> cands;
+  if (p.lattice == VCLB_D2Q9) {
+    for (int bx : {64, 128, 256})
+      for (int ty : {8, 16, 32, 64, 128}) cands.push_back(vclb::Tile{bx, ty, 1});
+  } else {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+    const int shapes[][2] = {{32, 8}, {64, 4}, {16, 16}, {32, 4}, {64, 2}, {16, 8}};
+    for (const auto& sh : shapes)
+      for (int per_cu : {1, 2, 3, 4}) {
+        const long cols = long((p.nx + sh[0] - 1) / sh[0]) * ((p.ny + sh[1] - 1) / sh[1]);
+        const long segs = std::max(1L, per_cu * long(ncu) / cols);
+        const int ty = int(std::max(1L, (p.nz + segs - 1) / segs));
+        vclb::Tile t{sh[0], ty, sh[1]};
+        bool dup = false;
+        for (const vclb::Tile& u : cands) dup = dup || (u.bx == t.bx && u.ty == t.ty && u.by3 == t.by3);
+        if (!dup) cands.push_back(t);
+      }
+  }
+  hipStream_t s = as_stream(stream);
+  if (int rc0 = flush_pending(c, s)) return rc0;
+  HIP_TRY(hipStreamSynchronize(s));
+  // the timing steps run on the live state, which is saved and restored afterwards
+  void* save = nullptr;
+  HIP_TRY(hipMalloc(&save, c->lay.total));
+  HIP_TRY(hipMemcpyAsync(save, c->ws, c->lay.total, hipMemcpyDeviceToDevice, s));
+  const vclb::Tile tile0 = c->tile;
+  const int64_t t0 = c->t_host;
+  const std::vector<int64_t> rec0 = c->recorded;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::vector<float> ms(cands.size(), -1.0f);
+  int rc = VCLB_OK;
+  for (size_t i = 0; i < cands.size() && e == hipSuccess && rc == VCLB_OK; ++i) {
+    const vclb::Tile& t = cands[i];
+    if (check_tile(p, t) != VCLB_OK) continue;   // outside the launch limits
+    if (vclb::fused_blocks(lattice_d(p.lattice), p.nx, p.ny, p.nz, t) > c->lay.partial_blocks) continue;
+    c->tile = t;
+    if ((rc = do_steps(c, 1, stream, true))) break;
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+    if ((rc = do_steps(c, steps, stream, true))) break;
+    if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float m = 0;
+    if ((e = hipEventElapsedTime(&m, e0, e1)) != hipSuccess) break;
+    ms[i] = m / float(steps);
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipMemcpyAsync(c->ws, save, c->lay.total, hipMemcpyDeviceToDevice, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(save);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  c->t_host = t0;
+  c->recorded = rec0;
+  c->pending = false;
+  c->tile = tile0;
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "autotune timing");
+  int best = -1;
+  for (size_t i = 0; i < cands.size(); ++i)
+    if (ms[i] > 0 && (best < 0 || ms[i] < ms[size_t(best)])) best = int(i);
+  if (best < 0) return fail(VCLB_EINVAL, "no launch shape fits this case");
+  c->tile = cands[size_t(best)];
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      const vclb::Tile& b = c->tile;
+      std::fprintf(f, "{\"key\": \"%s\", \"shape\": \"%s\", \"bx\": %d, \"ty\": %d, \"by3\": %d, \"ms_per_step\": %.6f, \"candidates\": [",
+                   key, desc.c_str(), b.bx, b.ty, b.by3, double(ms[size_t(best)]));
+      for (size_t i = 0; i < cands.size(); ++i)
+        std::fprintf(f, "%s[%d, %d, %d, %.6f]", i ? ", " : "", cands[i].bx, cands[i].ty, cands[i].by3, double(ms[i]));
+      std::fprintf(f, "]}\n");
+      std::fclose(f);
+    }
+  }
+  return VCLB_OK;
+}
 int vclb_step_plain(vclb_case* c, int64_t nsteps, void* stream) { return do_steps(c, nsteps, stream, false); }
 
 int vclb_case_time(vclb_case* c, int64_t* t, void* stream) {

@@ -93,6 +93,7 @@ _SIGS = [
     ("vclb_batch_get_tile", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     ("vclb_batch_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("vclb_batch_reduce", ctypes.c_int, [ctypes.c_void_p, _P(Obs), ctypes.c_void_p]),
+    ("vclb_case_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32, ctypes.c_void_p]),
     ("vclb_batch_history", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
     ("vclb_batch_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("vclb_batch_get_schedule", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32)]),
@@ -224,6 +225,13 @@ class Case:
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         check(lib().vclb_case_get_tile(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def autotune(self, cache_path=None, steps: int = 5, stream=None):
+        """Time the candidate tiles on the current state (restored afterwards) and keep the
+        fastest; returns (bx, ty, by3)."""
+        path = cache_path.encode() if cache_path else None
+        check(lib().vclb_case_autotune(self.h, path, int(steps), _stream_handle(stream)))
+        return self.tile()
 
     def set_reduce_every(self, every: int):
         check(lib().vclb_case_set_reduce_every(self.h, int(every)))

@@ -111,6 +111,9 @@ def test_step_before_init_and_bad_tiles():
     assert L.vclb_case_set_tile(h, 512, 8, 1) == v.VCLB_EINVAL     # above the launch bound
     assert L.vclb_case_set_tile(h, 64, 0, 1) == v.VCLB_EINVAL
     assert L.vclb_case_set_tile(h, 128, 16, 1) == 0
+    assert L.vclb_case_autotune(h, None, 2, None) == v.VCLB_ESTATE      # not initialised
+    assert L.vclb_case_autotune(h, None, 0, None) == v.VCLB_EINVAL
+    assert L.vclb_case_autotune(None, None, 2, None) == v.VCLB_EINVAL
     bx, ty, by = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     assert L.vclb_case_get_tile(h, ctypes.byref(bx), ctypes.byref(ty), ctypes.byref(by)) == 0
     assert (bx.value, ty.value) == (128, 16)

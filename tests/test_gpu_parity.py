@@ -294,6 +294,38 @@ def test_d3q19_tile_shape_does_not_change_the_state(storage):
                 assert np.array_equal(F[k], ref[k]), (tile, k)
 
 
+@pytest.mark.parametrize("variant", ["periodic_ragged", "d3q19"])
+def test_case_autotune_restores_state_and_uses_cache(variant, tmp_path):
+    v = _v()
+    say(f"case: autotune, {variant}")
+    p, phi0, u0 = _small_case(variant)
+    c = v.Case(p).init(phi0, u0)
+    c.step(4)
+    before = c.get_state()
+    h_before = c.history(0, 4)
+    cache = str(tmp_path / "tiles.jsonl")
+    tile = c.autotune(cache, steps=2)
+    say("  tile", tile)
+    after = c.get_state()
+    for a_, b_ in zip(before, after):
+        if a_ is not None:
+            assert np.array_equal(a_, b_)
+    assert c.time() == 4
+    assert np.array_equal(c.history(0, 4)["sum_phi"], h_before["sum_phi"])
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"by3"' in lines[0]
+    # the tuned tile continues the run exactly like the default one
+    ref = v.Case(p).init(phi0, u0)
+    ref.step(10)
+    c.step(6)
+    for a_, b_ in zip(ref.get_state(), c.get_state()):
+        if a_ is not None:
+            assert np.array_equal(a_, b_)
+    c2 = v.Case(p).init(phi0, u0)
+    assert c2.autotune(cache, steps=2) == tile                # read back from the cache
+    assert len(open(cache).read().strip().splitlines()) == 1
+
+
 def test_history_and_determinism():
     say("case: per-step reductions vs oracle, determinism")
     p, phi0, u0 = _small_case("periodic_ragged")
