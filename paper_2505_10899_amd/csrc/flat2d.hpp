@@ -43,34 +43,38 @@ __device__ __forceinline__ void divmod_pitch(int v, int P, float rcpP, int& q, i
 
 // Pull of the 9 populations arriving at node (x, y) of an nx x ny case from the stored
 // direction planes src[i] (uniform over the wave): periodic wrap and, behind a wall, the
-// node's own opposite population, expressed as an offset from the direction's own plane
-// (plane opp(i) lies (opp(i) - i) n entries further), so that the base stays uniform and
-// each load is a 32-bit offset from a scalar base.  ps: phi of the writer (shifted
-// storage).
+// node's own opposite population.  Every offset is a non-negative 32-bit index from a
+// uniform base, so each address is one shift-add with no sign extension: directions
+// 2, 5, 6 index from their own planes (a bounce from the bottom wall reads plane
+// opp(i) = i + 2 at s0 + 2n), directions 4, 7, 8 from the plane of opp(i) = i - 2 (their
+// own entry lies 2n further on; a bounce from the top wall reads s0 there).  ps: phi of
+// the writer (shifted storage).
 template <class St>
 __device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9], const float* __restrict__ phis,
                                            int x, int y, int nx, int ny, int n, bool wall,
                                            typename St::R (&v)[9], typename St::R* ps) {
   using R = typename St::R;
-  const int s0 = x + nx * y;
+  const unsigned s0 = unsigned(x + nx * y);
   const int xm = x == 0 ? nx - 1 : -1;                 // to column x - 1 (wrapped)
   const int xp = x == nx - 1 ? 1 - nx : 1;             // to column x + 1
   const int ym = y == 0 ? (ny - 1) * nx : -nx;         // to row y - 1 (periodic)
   const int yp = y == ny - 1 ? (1 - ny) * nx : nx;     // to row y + 1
   // writer of direction i sits at (x - cx_i, y - cy_i)
-  int nd[9] = {s0, s0 + xm, s0 + ym, s0 + xp, s0 + yp, s0 + xm + ym, s0 + xp + ym, s0 + xp + yp, s0 + xm + yp};
-  int off[9] = {nd[0], nd[1], nd[2], nd[3], nd[4], nd[5], nd[6], nd[7], nd[8]};
+  unsigned nd[9] = {s0, s0 + xm, s0 + ym, s0 + xp, s0 + yp, s0 + xm + ym, s0 + xp + ym, s0 + xp + yp, s0 + xm + yp};
+  const unsigned n2 = 2u * unsigned(n);
+  unsigned off[9] = {nd[0], nd[1], nd[2], nd[3], nd[4] + n2, nd[5], nd[6], nd[7] + n2, nd[8] + n2};
   if (wall && y == 0) {        // c_y = +1 directions 2, 5, 6 come back from 4, 7, 8 of this node
     nd[2] = nd[5] = nd[6] = s0;
-    off[2] = off[5] = off[6] = s0 + 2 * n;
+    off[2] = off[5] = off[6] = s0 + n2;
   }
   if (wall && y == ny - 1) {   // c_y = -1 directions 4, 7, 8 come back from 2, 5, 6
     nd[4] = nd[7] = nd[8] = s0;
-    off[4] = off[7] = off[8] = s0 - 2 * n;
+    off[4] = off[7] = off[8] = s0;
   }
+  const typename St::S* base[9] = {src[0], src[1], src[2], src[3], src[2], src[5], src[6], src[5], src[6]};
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    v[i] = St::load(src[i], off[i]);
+    v[i] = St::load(base[i], off[i]);
     if constexpr (St::shifted) {
       if (ps) ps[i] = R(ldg(phis, nd[i]));
     }
@@ -129,11 +133,11 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
     const int x = ex[SU], y = ey[SU];
     const bool act = i >= DL && x >= 0 && x < nx && y >= y0 && y < y1;
     R f[Q], J[2];
-    const int nn = x + nx * y;
+    const unsigned nn = unsigned(x + nx * y);
     if (act) {
       pull9_flat<St>(fsrc, phis, x, y, nx, ny, n, wall, f, nullptr);
       J[0] = ldg(c.J, nn);
-      J[1] = ldg(c.J, n + nn);
+      J[1] = ldg(c.J + n, nn);
     }
     // front: chunk i
     {
@@ -185,7 +189,7 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
 #pragma unroll
       for (int j = 0; j < Q; ++j) St::store(c.pop[1][dst] + long(j) * n, nn, f[j]);
       stg(c.J, nn, J[0]);
-      stg(c.J, n + nn, J[1]);
+      stg(c.J + n, nn, J[1]);
       if constexpr (St::shifted) stg(c.phis[dst], nn, float(in.nphi[0]));
       if (reduce) {
         const double ph = double(in.nphi[0]);

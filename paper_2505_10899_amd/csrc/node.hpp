@@ -26,14 +26,28 @@ namespace vclb {
 // instructions; flat accesses also wait on the LDS/scalar counter and so overlap less
 // with the LDS traffic of the stencils.  These helpers cast to the global address
 // space, so that the accesses compile to global_load / global_store.
+// An unsigned index selects the 32-bit form: the caller guarantees i * sizeof(T) < 2^32,
+// so the address is a uniform 64-bit base plus a 32-bit byte offset, which the hardware
+// adds itself (global_load v, v_off, s_base): one multiply-shift per access instead of
+// a sign extension and a 64-bit add.
 #define VCLB_GLOBAL __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ T ldg(const T* p, long i) {
+template <class T, class I>
+__device__ __forceinline__ T ldg(const T* p, I i) {
   return ((const T VCLB_GLOBAL*)p)[i];
 }
-template <class T>
-__device__ __forceinline__ void stg(T* p, long i, T v) {
+template <class T, class I>
+__device__ __forceinline__ void stg(T* p, I i, T v) {
   ((T VCLB_GLOBAL*)p)[i] = v;
+}
+template <class T>
+__device__ __forceinline__ T ldg(const T* p, unsigned i) {
+  const unsigned b = i * unsigned(sizeof(T));
+  return *(const T VCLB_GLOBAL*)((const char VCLB_GLOBAL*)p + b);
+}
+template <class T>
+__device__ __forceinline__ void stg(T* p, unsigned i, T v) {
+  const unsigned b = i * unsigned(sizeof(T));
+  *(T VCLB_GLOBAL*)((char VCLB_GLOBAL*)p + b) = v;
 }
 
 // ---------------------------------------------------------------- storage codecs
@@ -41,8 +55,10 @@ struct StoreF64 {
   using S = double;
   using R = double;
   static constexpr bool shifted = false;
-  __device__ static R load(const S* p, long i) { return ldg(p, i); }
-  __device__ static void store(S* p, long i, R v) { stg(p, i, v); }
+  template <class I>
+  __device__ static R load(const S* p, I i) { return ldg(p, i); }
+  template <class I>
+  __device__ static void store(S* p, I i, R v) { stg(p, i, v); }
 };
 // FP32 storage uses the same deviation representation as FP16S (see below): the g
 // arithmetic then never rounds at the magnitude of the rest populations (~0.7), which
@@ -51,8 +67,10 @@ struct StoreF32 {
   using S = float;
   using R = float;
   static constexpr bool shifted = true;
-  __device__ static R load(const S* p, long i) { return ldg(p, i); }
-  __device__ static void store(S* p, long i, R v) { stg(p, i, v); }
+  template <class I>
+  __device__ static R load(const S* p, I i) { return ldg(p, i); }
+  template <class I>
+  __device__ static void store(S* p, I i, R v) { stg(p, i, v); }
 };
 // FP16 storage of deviations from the rest equilibrium: g_i - phi r_i with
 // r_0 = 1 + (w_0 - 1) lambda, r_i = w_i lambda (g_eq at u = 0, mu = 0); f is stored
@@ -63,10 +81,12 @@ struct StoreF16S {
   using S = __half;
   using R = float;
   static constexpr bool shifted = true;
-  __device__ static R load(const S* p, long i) {
+  template <class I>
+  __device__ static R load(const S* p, I i) {
     return __half2float(__ushort_as_half(ldg(reinterpret_cast<const unsigned short*>(p), i)));
   }
-  __device__ static void store(S* p, long i, R v) {
+  template <class I>
+  __device__ static void store(S* p, I i, R v) {
     stg(reinterpret_cast<unsigned short*>(p), i, __half_as_ushort(__float2half_rn(v)));
   }
 };
@@ -104,7 +124,14 @@ __device__ __forceinline__ R clamp01(R v) {
 template <class R>
 __device__ __forceinline__ R psi_of(R phi, R W4, R xi) {
   const R pc = clamp01(phi);
-  return W4 * log((pc + xi) / ((R(1) - pc) + xi));
+  if constexpr (sizeof(R) == 4) {
+    // hardware reciprocal and logarithm (about 1 ulp each): the quotient lies in
+    // [xi / (1 + xi), (1 + xi) / xi], far from denormals, and psi's own rounding at its
+    // magnitude (up to (W / 4) ln(1 / xi)) is larger than what they add
+    return W4 * __logf((pc + xi) * __builtin_amdgcn_rcpf((R(1) - pc) + xi));
+  } else {
+    return W4 * log((pc + xi) / ((R(1) - pc) + xi));
+  }
 }
 
 // grad (Eq. 39) and Laplacian (Eq. 40) of a field given at x + c_i, i = 0..Q-1
