@@ -129,3 +129,88 @@ def test_batch_autotune_restores_state_and_uses_cache(tmp_path):
     b.set_tile(64, 64)
     assert b.autotune(cache, steps=2)[:2] == tile[:2]        # read back from the cache
     assert len(open(cache).read().strip().splitlines()) == 1
+
+
+# --------------------------------------------------------------------------- full size
+def _sample(cases):
+    """Indices of a few cases that span the batch: largest, smallest, widest, narrowest,
+    first shear (walls) and first periodic case."""
+    n = [p.nx * p.ny for p, _, _ in cases]
+    idx = {int(np.argmax(n)), int(np.argmin(n)), int(np.argmax([p.nx for p, _, _ in cases])),
+           int(np.argmin([p.nx for p, _, _ in cases]))}
+    idx.add(next(k for k, (p, _, _) in enumerate(cases) if p.wall_y))
+    idx.add(next(k for k, (p, _, _) in enumerate(cases) if not p.wall_y))
+    return sorted(idx)
+
+
+def _full_batch(v, storage):
+    cases, _ = W.batch_cases(512, storage=storage)
+    b = v.Batch([p for p, _, _ in cases])
+    b.set_tile(512, 1024)      # the launch configuration the benchmark times
+    b.set_schedule(101)
+    return cases, b
+
+
+def test_full_batch_fp64_sampled_cases_match_oracle():
+    """All 512 cases (24.4 M nodes) in the benchmark's launch configuration; sampled cases
+    start from the oracle's exact state and, after one batched step, match the oracle's
+    step node by node within the rounding bound of the one-step parity tests."""
+    v = _v()
+    from oracle.model import Model
+    from test_gpu_parity import normal_conditioning
+    cases, b = _full_batch(v, "fp64")
+    idx = _sample(cases)
+    say("case: full batch fp64, sampled cases", [(k, cases[k][0].nx, cases[k][0].ny, cases[k][0].wall_y) for k in idx])
+    models = {}
+    for k, (c, (p, phi0, u0)) in enumerate(zip(b.cases, cases)):
+        if k in idx:
+            m = Model(p).init(phi0, u0)
+            c.set_state(m.g, m.f, m.Jprev, m.t)
+            models[k] = (m, normal_conditioning(m, m.fields()))
+        else:
+            c.init(phi0, u0)
+    b.step(1)
+    for k in idx:
+        m, cond = models[k]
+        m.step(1)
+        g, f, J = b.cases[k].get_state()
+        tol = 1e-13 + 2.0 * cond
+        ratio = max(float(np.max(np.abs(g - m.g) / tol[None])), float(np.max(np.abs(f - m.f) / tol[None])),
+                    float(np.max(np.abs(J - m.Jprev))) / 1e-13)
+        say(f"  case {k}: error / bound {ratio:.3f}")
+        assert ratio <= 1.0, k
+
+
+def test_full_batch_fp32_volume_and_sampled_fields():
+    """FP32 storage at full size in the benchmark's launch configuration: every case keeps
+    its volume to 1e-6 over 20 steps, and sampled cases match the FP64 oracle's first
+    step to FP32 rounding (phi, u and the populations)."""
+    v = _v()
+    from oracle.model import Model
+    from test_gpu_parity import normal_conditioning
+    cases, b = _full_batch(v, "fp32")
+    idx = _sample(cases)
+    say("case: full batch fp32, sampled cases", idx)
+    for c, (p, phi0, u0) in zip(b.cases, cases):
+        c.init(phi0, u0)
+    v0 = b.reduce()["sum_phi"][:, 0]
+    b.step(1)
+    for k in idx:
+        p, phi0, u0 = cases[k]
+        m = Model(p.replace(storage="fp64")).init(phi0, u0)
+        cond = normal_conditioning(m, m.fields(), eps=6e-8)
+        m.step(1)
+        g, f, J = b.cases[k].get_state()
+        tol = 1e-6 + 2.0 * cond
+        ratio = max(float(np.max(np.abs(g - m.g) / tol[None])), float(np.max(np.abs(f - m.f) / tol[None])))
+        F = b.cases[k].observe()
+        Fo = m.fields()
+        dphi = float(np.max(np.abs(F["phi"] - Fo["phi"])))
+        du = float(np.max(np.abs(F["u"] - Fo["u"])))
+        say(f"  case {k}: populations error / bound {ratio:.3f}, |dphi| {dphi:.2e}, |du| {du:.2e}")
+        assert ratio <= 1.0 and dphi <= 1e-6 and du <= 1e-6, k
+    b.step(19)
+    v1 = b.reduce()["sum_phi"][:, 0]
+    drift = float(np.max(np.abs(v1 - v0) / np.abs(v0)))
+    say(f"  max relative volume drift over 20 steps, all 512 cases: {drift:.2e}")
+    assert drift <= 1e-6

@@ -62,17 +62,18 @@ def oracle_state(m):
     return m.g, (m.f if m.p.mode == "coupled" else None), m.Jprev, m.t
 
 
-def normal_conditioning(m, F):
+def normal_conditioning(m, F, eps=2.2e-16):
     """Per-node bound on how much the source term may differ between two correct
     implementations: the unit normal grad psi / |grad psi| (Eq. 32) is ill-conditioned
     where |grad psi| is comparable to the round-off of its stencil sum (e.g. at the
-    centre of a drop), and enters multiplied by (lambda/W)(1 - tanh^2)."""
+    centre of a drop), and enters multiplied by (lambda/W)(1 - tanh^2).  eps: unit
+    round-off of the arithmetic that formed psi."""
     p = m.p
     An = p.lam / p.W * F["sech2"]
     gnorm = np.sqrt((F["gpsi"] ** 2).sum(axis=0) + p.eps_n ** 2)
     ap = m._pad(np.abs(F["psi"]))
     big = np.max([m._at(ap, c) for c in m.lat.c], axis=0)
-    dn = np.minimum(2.0, 16 * 2.2e-16 * 3 * big / gnorm)
+    dn = np.minimum(2.0, 16 * eps * 3 * big / gnorm)
     cond = An * dn
     cp = m._pad(cond)
     return np.max([m._at(cp, c) for c in m.lat.c], axis=0)
