@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS>()))
     if (w.y < 0)   // a band of whole rows, marched in padded row-major order
       step2d_flat<St, DL>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);
     else           // a strip of columns [w.y, w.y + blockDim.x), one lane per column
-      step2d_tile<St, true>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems, it, smem_raw);
+      step2d_tile<St, true, unsigned>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems, it, smem_raw);
     __syncthreads();
   }
 }

@@ -8,6 +8,8 @@
 // node update.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "devcase.hpp"
 #include "launch.hpp"
 
@@ -33,8 +35,10 @@ __device__ __forceinline__ Nbr3 nbr3(int x, int y, int z, int nx, int ny, int nz
 }
 
 // The 19 pulls at one node: 32-bit node offsets from the uniform base of each
-// direction's plane (the case has fewer than 2^31 nodes).  ps: phi of the writer.
-template <class St>
+// direction's plane (the case has fewer than 2^31 nodes), accessed with index type IX
+// (unsigned: 32-bit byte offsets, when n times the element size fits them).  ps: phi of
+// the writer.
+template <class St, class IX>
 __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, const float* __restrict__ phis,
                                        long n, const Nbr3& o, typename St::R (&out)[19], typename St::R* ps) {
   using L = D3Q19;
@@ -48,9 +52,9 @@ __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, c
     if constexpr (L::cy[i] < 0) s += o.yp;
     if constexpr (L::cz[i] > 0) s += o.zm;
     if constexpr (L::cz[i] < 0) s += o.zp;
-    out[i] = St::load(src + i * n, s);
+    out[i] = St::load(src + i * n, IX(s));
     if constexpr (St::shifted) {
-      if (ps) ps[i] = R(ldg(phis, s));
+      if (ps) ps[i] = R(ldg(phis, IX(s)));
     }
   });
 }
@@ -69,7 +73,7 @@ constexpr int step3d_min_blocks() {
 
 // NL: labels of the volume reductions (1 or 2), fixed per case; UNIT: the case's rates
 // outside the g flux and f stress rows are all 1
-template <class St, int NL, bool UNIT>
+template <class St, int NL, bool UNIT, class IX>
 __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCase<D3Q19, St> c, int BX, int BY,
                                                                         int nby, int nbz, int reduce) {
   using L = D3Q19;
@@ -111,7 +115,7 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
     const int zr = wrapi(z, c.nz);
     const int s = slot(z) * PS;
     R ps[Q];
-    pull19<St>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy), g, ps);
+    pull19<St, IX>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy), g, ps);
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     sphi[s + (ty + 1) * PW + tx + 1] = ph;
     spsi[s + (ty + 1) * PW + tx + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
@@ -127,7 +131,7 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
       const int hx = ((x0 - 1 + px) % nx + nx) % nx;
       const int hy = ((y0 - 1 + py) % ny + ny) % ny;
       R gh[Q], hps[Q];
-      pull19<St>(gsrc, phis, c.n, nbr3(hx, hy, zr, nx, ny, nz, nxy), gh, hps);
+      pull19<St, IX>(gsrc, phis, c.n, nbr3(hx, hy, zr, nx, ny, nz, nxy), gh, hps);
       const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       sphi[s + py * PW + px] = hp;
       spsi[s + py * PW + px] = psi_of<R>(hp, c.np.W4, c.np.xi);
@@ -172,9 +176,9 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
     const int nn = o.s0;
     R f[Q], J[L::D];
     if (active) {
-      pull19<St>(fsrc, phis, c.n, o, f, nullptr);
+      pull19<St, IX>(fsrc, phis, c.n, o, f, nullptr);
 #pragma unroll
-      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.n, nn);
+      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.n, IX(nn));
     }
     plane(z + 1, gnext);
     if constexpr (STAGE) stage_put(z + 1, gnext);
@@ -201,12 +205,12 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
       node_update_mom_s<L, R, true, St::shifted, UNIT>(c.np, st, gcur, f, J, out);
       const int dst = par ^ 1;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + i * c.n, nn, gcur[i]);
+      for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + i * c.n, IX(nn), gcur[i]);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, nn, f[i]);
+      for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, IX(nn), f[i]);
 #pragma unroll
-      for (int d = 0; d < L::D; ++d) stg(c.J + d * c.n, nn, J[d]);
-      if constexpr (St::shifted) stg(c.phis[dst], nn, float(st.phi));
+      for (int d = 0; d < L::D; ++d) stg(c.J + d * c.n, IX(nn), J[d]);
+      if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi));
       if (reduce) {
         const double ph = double(st.phi);
         int lab = 0;
@@ -277,13 +281,23 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   if (tile.bx * tile.by3 > 256) return -1;
   const size_t lds = step3d_lds_bytes<St>(tile.bx, tile.by3);
   const dim3 grid(nbx * nby * nbz), block(tile.bx * tile.by3);
-  if (c.nl > 1) {
-    if (c.unit_rates) hipLaunchKernelGGL((k_step3d<St, 2, true>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
-    else hipLaunchKernelGGL((k_step3d<St, 2, false>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
-  } else {
-    if (c.unit_rates) hipLaunchKernelGGL((k_step3d<St, 1, true>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
-    else hipLaunchKernelGGL((k_step3d<St, 1, false>), grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
-  }
+  auto go = [&](auto nl, auto unit, auto ix) {
+    hipLaunchKernelGGL((k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix)>), grid, block, lds, s,
+                       c, tile.bx, tile.by3, nby, nbz, reduce);
+  };
+  using One = std::integral_constant<int, 1>;
+  using Two = std::integral_constant<int, 2>;
+  // 32-bit byte offsets when every per-plane offset fits them (8-byte elements at most)
+  auto pick_ix = [&](auto nl, auto unit) {
+    if (c.n < (1L << 29)) go(nl, unit, 0u);
+    else go(nl, unit, 0L);
+  };
+  auto pick_unit = [&](auto nl) {
+    if (c.unit_rates) pick_ix(nl, std::true_type{});
+    else pick_ix(nl, std::false_type{});
+  };
+  if (c.nl > 1) pick_unit(Two{});
+  else pick_unit(One{});
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

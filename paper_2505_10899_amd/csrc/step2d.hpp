@@ -13,7 +13,9 @@ namespace vclb {
 struct Col3 { int c, m, p; };
 struct Row3 { int c, m, p; bool lo, hi; };
 
-template <class St>
+// IX: index type of the accesses; unsigned when every node index times the element size
+// fits 32 bits (32-bit byte offsets from uniform bases), else long.
+template <class St, class IX>
 __device__ __forceinline__ void pull9(const typename St::S* const (&src)[9], const float* __restrict__ phis,
                                       const Col3& x, const Row3& y, typename St::R (&v)[9],
                                       typename St::R* ps) {
@@ -33,9 +35,9 @@ __device__ __forceinline__ void pull9(const typename St::S* const (&src)[9], con
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    v[i] = St::load(base[i], off[i]);
+    v[i] = St::load(base[i], IX(off[i]));
     if constexpr (St::shifted) {
-      if (ps) ps[i] = R(ldg(phis, off[i]));
+      if (ps) ps[i] = R(ldg(phis, IX(off[i])));
     }
   }
 }
@@ -53,7 +55,7 @@ struct Acc2 {
 // (plus one halo column on each side, computed by lanes 0 and 1), then applies the
 // stencils from LDS and updates the current row: every population is read from HBM
 // once, except the two halo columns and the two halo rows of the tile.
-template <class St, bool COUPLED>
+template <class St, bool COUPLED, class IX>
 __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, int x0, int y0, int y1, bool reduce,
                                             double* __restrict__ part, long part_stride, long part_index,
                                             unsigned char* smem_raw) {
@@ -103,13 +105,13 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
   auto phi_row = [&](int r, R (&g)[Q]) {
     const Row3 rw = row3(r);
     R ps[Q];
-    pull9<St>(gsrc, phis, col, rw, g, ps);
+    pull9<St, IX>(gsrc, phis, col, rw, g, ps);
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     sphi[slot(r) * W + lane + 1] = ph;
     spsi[slot(r) * W + lane + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
     if (halo_lane) {
       R gh[Q], hps[Q];
-      pull9<St>(gsrc, phis, hcol, rw, gh, hps);
+      pull9<St, IX>(gsrc, phis, hcol, rw, gh, hps);
       const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       sphi[slot(r) * W + hidx] = hp;
       spsi[slot(r) * W + hidx] = psi_of<R>(hp, c.np.W4, c.np.xi);
@@ -133,9 +135,9 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
     // so that one memory round trip per row covers both
     const int nn = xw + nx * y;
     R f[Q], J[2];
-    if constexpr (COUPLED) pull9<St>(fsrc, phis, col, row3(y), f, nullptr);
-    J[0] = ldg(c.J, nn);
-    J[1] = ldg(c.J, n + nn);
+    if constexpr (COUPLED) pull9<St, IX>(fsrc, phis, col, row3(y), f, nullptr);
+    J[0] = ldg(c.J, IX(nn));
+    J[1] = ldg(c.J + n, IX(nn));
     phi_row(y + 1, gnext);
     __syncthreads();
     if (active_x) {
@@ -155,7 +157,7 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
       NodeOut<L, R> out;
       node_update<L, R, COUPLED, St::shifted>(c.np, in, gcur, f, J, out);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + long(i) * n, nn, gcur[i]);
+      for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + long(i) * n, IX(nn), gcur[i]);
       if constexpr (COUPLED) {
         if (wall && y == 0) {
 #pragma unroll
@@ -168,11 +170,11 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
             if (L::cy[i] > 0) f[i] += c.np.wt[i] * out.rho;
         }
 #pragma unroll
-        for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + long(i) * n, nn, f[i]);
+        for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + long(i) * n, IX(nn), f[i]);
       }
-      stg(c.J, nn, J[0]);
-      stg(c.J, n + nn, J[1]);
-      if constexpr (St::shifted) stg(c.phis[dst], nn, float(in.nphi[0]));
+      stg(c.J, IX(nn), J[0]);
+      stg(c.J + n, IX(nn), J[1]);
+      if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(in.nphi[0]));
       if (reduce) {
         const double ph = double(in.nphi[0]);
         double dy[kMaxLabels];
