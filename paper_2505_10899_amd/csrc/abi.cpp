@@ -941,6 +941,7 @@ struct vclb_batch {
   std::vector<int2> runs;
   int bx = 512, ty = 1024, blocks = 0, cap = 0, lag = 1, flat_pct = 100;
   int reduce_every = 1;
+  bool unit = true;                   // every case has unit rates outside the g flux / f stress rows
   int64_t nodes = 0;
   bool pend = false;
   int pend_buf = 0;
@@ -1088,7 +1089,9 @@ int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
   std::vector<int4> items;
   std::vector<int2> ci, runs;
   build_items(b, bx, ty, flat_pct, items, ci);
-  int per_cu = dispatch_storage(b->storage, [&](auto st) { return vclb::batch_max_blocks_per_cu<decltype(st)>(bx, cap, lag); });
+  int per_cu = dispatch_storage(b->storage, [&](auto st) {
+    return vclb::batch_max_blocks_per_cu<decltype(st)>(bx, cap, lag, b->unit);
+  });
   int dev = 0, ncu = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1126,6 +1129,7 @@ vclb::BatchArgs batch_args(const vclb_batch* b, int64_t t, int reduce) {
   a.reduce = reduce;
   a.cap = b->cap;
   a.lag = b->lag;
+  a.unit = b->unit ? 1 : 0;
   return a;
 }
 
@@ -1244,6 +1248,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
     using St = decltype(st);
     for (int k = 0; k < ncases; ++k) {
       auto d = make_dev<vclb::D2Q9, St>(*b->cases[size_t(k)]);
+      b->unit = b->unit && d.unit_rates != 0;
       std::memcpy(table.data() + b->dcase_stride * size_t(k), &d, sizeof(d));
     }
     // the device reads entry k as cases[k]: check that indexing the table that way finds

@@ -11,6 +11,8 @@
 // items in a fixed order into that case's observation history.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "devcase.hpp"
 #include "launch.hpp"
 #include "flat2d.hpp"
@@ -39,16 +41,17 @@ __device__ __forceinline__ void fold_case(const DevCase<D2Q9, St>& c, const Batc
 }
 
 // Workgroups per CU the register budget is sized for: FP32 arithmetic fits 4 waves per
-// SIMD, except the lag-3 FIFO (a little more than 128 VGPRs: 3); FP64 fits 2.
-template <class St, int DL, int BS>
+// SIMD, except the lag-3 FIFO with general rates (a little more than 128 VGPRs: 3); FP64
+// fits 2, or 3 for the short lag with unit rates (at most 168 VGPRs).
+template <class St, int DL, int BS, bool UNIT>
 constexpr int batch_min_blocks() {
-  constexpr int waves = sizeof(typename St::R) == 8 ? 2 : (DL == 3 ? 3 : 4);   // per SIMD
+  constexpr int waves = sizeof(typename St::R) == 8 ? (UNIT && DL == 1 ? 3 : 2) : (DL == 3 && !UNIT ? 3 : 4);
   constexpr int per_block = BS / 256;                                          // waves per SIMD
   return waves / per_block > 0 ? waves / per_block : 1;
 }
 
-template <class St, int DL, int BS>
-__global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS>()))
+template <class St, int DL, int BS, bool UNIT>
+__global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS, UNIT>()))
     k_batch_step2d(const DevCase<D2Q9, St>* __restrict__ cases, BatchArgs a) {
   extern __shared__ unsigned char smem_raw[];
   if (a.pend)
@@ -59,9 +62,10 @@ __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS>()))
   for (int it = run.x; it < run.x + run.y; ++it) {
     const int4 w = a.items[it];
     if (w.y < 0)   // a band of whole rows, marched in padded row-major order
-      step2d_flat<St, DL>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);
+      step2d_flat<St, DL, UNIT>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);
     else           // a strip of columns [w.y, w.y + blockDim.x), one lane per column
-      step2d_tile<St, true, unsigned>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems, it, smem_raw);
+      step2d_tile<St, true, unsigned, UNIT>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems, it,
+                                            smem_raw);
     __syncthreads();
   }
 }
@@ -78,19 +82,28 @@ size_t batch_lds_bytes(int cap, int bx) {
   return flat > rows ? flat : rows;
 }
 
+// the kernel instantiation for a launch shape (bx lanes, lag, unit rates); fn receives a
+// pointer to it
+template <class St, class Fn>
+int with_batch_kernel(int bx, int lag, bool unit, Fn&& fn) {
+  if (lag != 1 && lag != 3) return -1;
+  auto pick = [&](auto big) -> int {
+    constexpr int BS = decltype(big)::value ? 512 : 256;
+    if (lag == 1) return unit ? fn(k_batch_step2d<St, 1, BS, true>) : fn(k_batch_step2d<St, 1, BS, false>);
+    return unit ? fn(k_batch_step2d<St, 3, BS, true>) : fn(k_batch_step2d<St, 3, BS, false>);
+  };
+  return bx <= 256 ? pick(std::false_type{}) : pick(std::true_type{});
+}
+
 template <class St>
 int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s) {
   const size_t lds = batch_lds_bytes<St>(a.cap, bx);
   const auto* cs = static_cast<const DevCase<D2Q9, St>*>(cases);
-  if (bx <= 256) {
-    if (a.lag == 1) hipLaunchKernelGGL((k_batch_step2d<St, 1, 256>), dim3(blocks), dim3(bx), lds, s, cs, a);
-    else if (a.lag == 3) hipLaunchKernelGGL((k_batch_step2d<St, 3, 256>), dim3(blocks), dim3(bx), lds, s, cs, a);
-    else return -1;
-  } else {
-    if (a.lag == 1) hipLaunchKernelGGL((k_batch_step2d<St, 1, 512>), dim3(blocks), dim3(bx), lds, s, cs, a);
-    else if (a.lag == 3) hipLaunchKernelGGL((k_batch_step2d<St, 3, 512>), dim3(blocks), dim3(bx), lds, s, cs, a);
-    else return -1;
-  }
+  const int rc = with_batch_kernel<St>(bx, a.lag, a.unit != 0, [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(bx), lds, s, cs, a);
+    return 0;
+  });
+  if (rc) return rc;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -102,18 +115,13 @@ int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s) {
 }
 
 template <class St>
-int batch_max_blocks_per_cu(int bx, int cap, int lag) {
+int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit) {
   int nb = 0;
   const size_t lds = batch_lds_bytes<St>(cap, bx);
-  hipError_t e;
-  if (bx <= 256)
-    e = lag == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 1, 256>, bx, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 3, 256>, bx, lds);
-  else
-    e = lag == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 1, 512>, bx, lds)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step2d<St, 3, 512>, bx, lds);
-  if (e != hipSuccess) return 0;
-  return nb;
+  const int rc = with_batch_kernel<St>(bx, lag, unit, [&](auto kern) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, bx, lds) == hipSuccess ? 0 : -1;
+  });
+  return rc ? 0 : nb;
 }
 
 template int launch_batch_step<StoreF64>(const void*, const BatchArgs&, int, int, hipStream_t);
@@ -122,9 +130,9 @@ template int launch_batch_step<StoreF16S>(const void*, const BatchArgs&, int, in
 template int launch_batch_fold<StoreF64>(const void*, const BatchArgs&, hipStream_t);
 template int launch_batch_fold<StoreF32>(const void*, const BatchArgs&, hipStream_t);
 template int launch_batch_fold<StoreF16S>(const void*, const BatchArgs&, hipStream_t);
-template int batch_max_blocks_per_cu<StoreF64>(int, int, int);
-template int batch_max_blocks_per_cu<StoreF32>(int, int, int);
-template int batch_max_blocks_per_cu<StoreF16S>(int, int, int);
+template int batch_max_blocks_per_cu<StoreF64>(int, int, int, bool);
+template int batch_max_blocks_per_cu<StoreF32>(int, int, int, bool);
+template int batch_max_blocks_per_cu<StoreF16S>(int, int, int, bool);
 template size_t batch_lds_bytes<StoreF64>(int, int);
 template size_t batch_lds_bytes<StoreF32>(int, int);
 template size_t batch_lds_bytes<StoreF16S>(int, int);

@@ -81,7 +81,8 @@ __device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9]
   }
 }
 
-template <class St, int DL>
+// UNIT: the case's rates outside the g flux and f stress rows are all 1
+template <class St, int DL, bool UNIT>
 __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, int y0, int y1, bool reduce,
                                             int cap, double* __restrict__ part, long part_stride, long part_index,
                                             unsigned char* smem_raw) {
@@ -173,7 +174,7 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
         in.npsi[j] = spsi[s];
       }
       NodeOut<L, R> out;
-      node_update<L, R, true, St::shifted>(c.np, in, e[SU], f, J, out);
+      node_update_d2q9<R, true, St::shifted, UNIT>(c.np, in, e[SU], f, J, out);
 #pragma unroll
       for (int j = 0; j < Q; ++j) St::store(c.pop[0][dst] + long(j) * n, nn, e[SU][j]);
       if (wall && y == 0) {

@@ -7,6 +7,8 @@
 // pop_i(x) = post_i(x - c_i) from the buffer the previous step wrote.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "devcase.hpp"
 #include "launch.hpp"
 #include "step2d.hpp"
@@ -252,7 +254,7 @@ __global__ void __launch_bounds__(256) k_reduce_state(DevCase<L, St> c) {
 }
 
 // ---------------------------------------------------------------- fused 2D step (A1-A11)
-template <class St, bool COUPLED, class IX>
+template <class St, bool COUPLED, class IX, bool UNIT>
 __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4)
     k_step2d(DevCase<D2Q9, St> c, int TY, int nseg, int reduce) {
   extern __shared__ unsigned char smem_raw[];
@@ -263,8 +265,8 @@ __global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4)
   const int nstrips = gridDim.x / nseg;
   const int seg = tile / nstrips, strip = tile - seg * nstrips;
   const int y0 = seg * TY;
-  step2d_tile<St, COUPLED, IX>(c, c.t, strip * int(blockDim.x), y0, min(y0 + TY, c.ny), reduce != 0, c.part_w,
-                               gridDim.x, blockIdx.x, smem_raw);
+  step2d_tile<St, COUPLED, IX, UNIT>(c, c.t, strip * int(blockDim.x), y0, min(y0 + TY, c.ny), reduce != 0,
+                                     c.part_w, gridDim.x, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------- second reduction pass
@@ -314,13 +316,19 @@ int launch_step_fused(const DevCase<L, St>& c, const Tile& tile, int reduce, hip
     const int nstrips = (c.nx + tile.bx - 1) / tile.bx;
     const int nseg = (c.ny + tile.ty - 1) / tile.ty;
     const size_t lds = size_t(2) * 4 * (tile.bx + 2) * sizeof(typename St::R);
-    // 32-bit byte offsets when every per-plane offset fits them (8-byte elements at most)
-    if (c.n < (1L << 29))
-      hipLaunchKernelGGL((k_step2d<St, COUPLED, unsigned>), dim3(nstrips * nseg), dim3(tile.bx), lds, s, c,
+    // 32-bit byte offsets when every per-plane offset fits them (8-byte elements at most);
+    // the unit-rate update when the case's rates allow it
+    const dim3 grid(nstrips * nseg), block(tile.bx);
+    auto go = [&](auto ix, auto unit) {
+      hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), decltype(unit)::value>), grid, block, lds, s, c,
                          tile.ty, nseg, reduce);
-    else
-      hipLaunchKernelGGL((k_step2d<St, COUPLED, long>), dim3(nstrips * nseg), dim3(tile.bx), lds, s, c, tile.ty,
-                         nseg, reduce);
+    };
+    auto pick = [&](auto ix) {
+      if (c.unit_rates) go(ix, std::true_type{});
+      else go(ix, std::false_type{});
+    };
+    if (c.n < (1L << 29)) pick(0u);
+    else pick(0L);
     return hipGetLastError() == hipSuccess ? 0 : -3;
   } else {
     return launch_step3d<St>(c, tile, reduce, s);

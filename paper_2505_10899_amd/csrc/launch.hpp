@@ -53,6 +53,7 @@ struct BatchArgs {
   int reduce;               // record the reductions of this step
   int cap;                  // LDS ring entries of the flattened march (power of two)
   int lag;                  // its lag in chunks (1 or 3)
+  int unit;                 // every case has unit rates outside the g flux and f stress rows
 };
 
 template <class St>
@@ -62,7 +63,7 @@ size_t batch_lds_bytes(int cap, int bx);
 template <class St>
 int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s);
 template <class St>
-int batch_max_blocks_per_cu(int bx, int cap, int lag);
+int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit);
 
 // Lag (in chunks of B lanes) of the flattened batched march for rows of padded pitch
 // P = nx + 2: 1 or 3 (the register FIFO holds lag + 1 chunks), 0 if the rows are too

@@ -218,7 +218,10 @@ __device__ __forceinline__ void d2q9_from_moments(const R (&m)[9], R (&v)[9]) {
 // of the equilibria and sources are in closed form (M g_eq, M f_eq, M G and M F evaluated from
 // Eqs. 21-24, 31-32), so that each population set costs one forward and one inverse
 // moment transform.
-template <class R, bool COUPLED, bool SH>
+// UNIT: every rate outside the g flux rows (3-6) and the f stress rows (7-8) is exactly 1
+// (the defaults); those rows then relax straight to m_eq + src / 2 and their m is never
+// formed.
+template <class R, bool COUPLED, bool SH, bool UNIT = false>
 __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, const NodeIn<D2Q9, R>& in,
                                                  R (&g)[9], R (&f)[9], R (&J)[2], NodeOut<D2Q9, R>& out) {
   const R* q = in.nphi;
@@ -264,7 +267,20 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   // source moments (0, 0, 0, Vx/3, -Vx/3, Vy/3, -Vy/3, 0, 0).
   {
     R m[9];
-    d2q9_moments<R>(g, m);
+    if constexpr (UNIT) {
+      // only the conserved row (kept as is in deviation variables) and the flux rows
+      const R d13 = g[1] - g[3], d24 = g[2] - g[4];
+      const R x58 = (g[5] - g[7]) + (g[8] - g[6]);
+      const R y58 = (g[5] - g[7]) + (g[6] - g[8]);
+      m[0] = SH ? g[0] + ((g[1] + g[3]) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8])) : R(0);
+      m[1] = m[2] = m[7] = m[8] = R(0);
+      m[3] = d13 + x58;
+      m[4] = R(-2) * d13 + x58;
+      m[5] = d24 + y58;
+      m[6] = R(-2) * d24 + y58;
+    } else {
+      d2q9_moments<R>(g, m);
+    }
     R eq[9];
     if constexpr (SH) {
       eq[0] = m[0];
@@ -282,7 +298,8 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       if (SH && k == 0) continue;
-      m[k] = m[k] - p.sgr[k] * (m[k] - eq[k]) + (R(1) - R(0.5) * p.sgr[k]) * src[k];
+      if (UNIT && !D2Q9::g_flux_row[k]) m[k] = eq[k] + R(0.5) * src[k];
+      else m[k] = m[k] - p.sgr[k] * (m[k] - eq[k]) + (R(1) - R(0.5) * p.sgr[k]) * src[k];
     }
     d2q9_from_moments<R>(m, g);
   }
@@ -296,8 +313,10 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
     const R src[9] = {ug, R(0), -ug, Fx, -Fx, Fy, -Fy, R(2.0 / 3.0) * (ux * grx - uy * gry),
                       R(1.0 / 3.0) * (ux * gry + uy * grx)};
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
-      fm[k] = fm[k] - p.sfr[k] * (fm[k] - eq[k]) + (R(1) - R(0.5) * p.sfr[k]) * src[k];
+    for (int k = 0; k < 9; ++k) {
+      if (UNIT && !D2Q9::f_stress_row[k]) fm[k] = eq[k] + R(0.5) * src[k];
+      else fm[k] = fm[k] - p.sfr[k] * (fm[k] - eq[k]) + (R(1) - R(0.5) * p.sfr[k]) * src[k];
+    }
     d2q9_from_moments<R>(fm, f);
   }
   out.rho = rho;
@@ -586,7 +605,6 @@ __device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const Nod
   if constexpr (L::Q == 9) node_update_d2q9<R, COUPLED, SH>(p, in, g, f, J, out);
   else node_update_mom<L, R, COUPLED, SH>(p, in, g, f, J, out);
 }
-
 // Velocity of the prescribed single vortex, Eqs. 43-44, at node (x, y) and step t.
 template <class R>
 __device__ __forceinline__ void vortex_u(R U0, double T, int x, int y, int nx, int ny, long t, R& ux, R& uy) {

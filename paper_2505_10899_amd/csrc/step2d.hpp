@@ -55,7 +55,8 @@ struct Acc2 {
 // (plus one halo column on each side, computed by lanes 0 and 1), then applies the
 // stencils from LDS and updates the current row: every population is read from HBM
 // once, except the two halo columns and the two halo rows of the tile.
-template <class St, bool COUPLED, class IX>
+// UNIT: the case's rates outside the g flux and f stress rows are all 1
+template <class St, bool COUPLED, class IX, bool UNIT>
 __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, int x0, int y0, int y1, bool reduce,
                                             double* __restrict__ part, long part_stride, long part_index,
                                             unsigned char* smem_raw) {
@@ -155,7 +156,7 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
         in.u[1] = uy;
       }
       NodeOut<L, R> out;
-      node_update<L, R, COUPLED, St::shifted>(c.np, in, gcur, f, J, out);
+      node_update_d2q9<R, COUPLED, St::shifted, UNIT>(c.np, in, gcur, f, J, out);
 #pragma unroll
       for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + long(i) * n, IX(nn), gcur[i]);
       if constexpr (COUPLED) {

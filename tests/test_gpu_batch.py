@@ -58,6 +58,30 @@ def test_batch_matches_cases_run_alone(storage, flat_pct, bx):
         assert np.allclose(ha["sum_phi"], hb["sum_phi"], rtol=1e-12 if storage == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("flat_pct", [0, 101])
+def test_batch_with_custom_rates_matches_cases_run_alone(flat_pct):
+    """A case with rates off their defaults switches the whole batch to the general-rate
+    kernel; every case must still reproduce its own run (which picks per case)."""
+    v = _v()
+    cases = small_batch("fp64", n=4, seed=9)
+    p0, phi0, u0 = cases[1]
+    cases[1] = (p0.replace(s_g=(0, 1.3, 1.1, 0, 0, 0, 0, 1.7, 0.9), s_f=(1.2, 1.4, 1.6, 0.8, 1.5, 0.8, 1.5, 0, 0)),
+                phi0, u0)
+    say("case: batch with one custom-rate case, flat_pct", flat_pct)
+    b = v.Batch([p for p, _, _ in cases])
+    b.set_tile(256, 16)
+    b.set_schedule(flat_pct)
+    for c, (p, phi0, u0) in zip(b.cases, cases):
+        c.init(phi0, u0)
+    b.step(20)
+    for k, (p, phi0, u0) in enumerate(cases):
+        alone = v.Case(p, tile=(64, 16)).init(phi0, u0)
+        alone.step(20)
+        err = max(np.max(np.abs(a_ - b_)) for a_, b_ in zip(alone.get_state(), b.cases[k].get_state()))
+        say(f"  case {k}: max |batch - alone| = {err:.3e}")
+        assert err <= 1e-13, k
+
+
 def test_batch_graph_equals_eager_and_history():
     v = _v()
     cases = small_batch("fp32", n=5, seed=3)
