@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) k_reduce_state(DevCase<L, St> c) {
 
 // ---------------------------------------------------------------- fused 2D step (A1-A11)
 template <class St, bool COUPLED, class IX, bool UNIT>
-__global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? 2 : 4)
+__global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? (UNIT ? 3 : 2) : 4)
     k_step2d(DevCase<D2Q9, St> c, int TY, int nseg, int reduce) {
   extern __shared__ unsigned char smem_raw[];
   if (blockIdx.x == 0 && c.pend_nb > 0) fold_pending(c);
