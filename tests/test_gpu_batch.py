@@ -82,6 +82,38 @@ def test_batch_with_custom_rates_matches_cases_run_alone(flat_pct):
         assert err <= 1e-13, k
 
 
+@pytest.mark.parametrize("flat_pct,bx", [(101, 512), (0, 256), (101, 64)])
+def test_batch_extreme_sizes_matches_cases_run_alone(flat_pct, bx):
+    """One large case among tiny ones: the run partition splits the large case over
+    many workgroups (bands of a few rows) and packs the tiny ones together, and a case
+    one node wide or two rows high still steps exactly as alone."""
+    v = _v()
+    specs = [(300, 260, False), (1, 40, False), (3, 130, True), (8, 8, False), (70, 2, True), (5, 9, False)]
+    cases = []
+    for nx, ny, wall in specs:
+        p = W.CaseParams(nx=nx, ny=ny, rho_light=0.2, wall_y=wall,
+                         wall_u_bottom=(-0.02, 0.0, 0.0) if wall else (0.0, 0.0, 0.0),
+                         wall_u_top=(0.02, 0.0, 0.0) if wall else (0.0, 0.0, 0.0))
+        R = max(1.5, 0.3 * min(nx, ny))
+        cases.append((p, W.drops_phi(p, [((nx - 1) / 2.0, (ny - 1) / 2.0, 0.0, R)]),
+                      W.couette_u(p) if wall else None))
+    say("case: extreme sizes", specs, "flat_pct", flat_pct, "bx", bx)
+    b = v.Batch([p for p, _, _ in cases])
+    b.set_tile(bx, 1024)
+    b.set_schedule(flat_pct)
+    for c, (p, phi0, u0) in zip(b.cases, cases):
+        c.init(phi0, u0)
+    b.step(12)
+    for k, (p, phi0, u0) in enumerate(cases):
+        alone = v.Case(p, tile=(64, 16)).init(phi0, u0)
+        alone.step(12)
+        err = max(np.max(np.abs(a_ - b_)) for a_, b_ in zip(alone.get_state(), b.cases[k].get_state()))
+        say(f"  case {k} {p.nx}x{p.ny}: max |batch - alone| = {err:.3e}")
+        assert err <= 1e-13, k
+        ha, hb = alone.history(0, 12), b.cases[k].history(0, 12)
+        assert np.allclose(ha["sum_phi"], hb["sum_phi"], rtol=1e-12)
+
+
 def test_batch_graph_equals_eager_and_history():
     v = _v()
     cases = small_batch("fp32", n=5, seed=3)
