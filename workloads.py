@@ -192,6 +192,44 @@ def shear_droplet(storage: str = "fp64", nx: int = 512, ny: int = 256, R: float 
     return p, phi0, couette_u(p)
 
 
+# ---------------------------------------------------------------------------
+# the paper's four test problems at their own sizes (Sect. 4), with lam = 0 giving the
+# classical model they are compared with.  Common parameters of Sect. 4.1: W = 3,
+# density and viscosity ratio 1, M = 0.1, sigma = 0.01; the rest (radii, wall speed,
+# viscosity) is not stated and takes the readings noted per builder.
+# ---------------------------------------------------------------------------
+
+def paper_two_drops(lam: float = 0.5, storage: str = "fp64", r1: float = 24.0,
+                    r2: float = 8.0) -> Tuple[CaseParams, np.ndarray, None]:
+    """Sect. 4.1: two drops centred on the base (y = 0) of a 200 x 100 box at x = 80 and
+    x = 160 (periodic, so each drop also wraps across y = 0); radii not given (24 and 8
+    here, the large and small drops of the two-drop case); nu = 0.1.  Labels: the two
+    centres."""
+    p = CaseParams(nx=200, ny=100, W=3.0, sigma=0.01, mobility=0.1, nu=0.1, rho_heavy=1.0, rho_light=1.0,
+                   lam=lam, storage=storage, label_centres=[(80.0, 0.0, 0.0), (160.0, 0.0, 0.0)])
+    return p, drops_phi(p, [(80.0, 0.0, 0.0, r1), (160.0, 0.0, 0.0, r2)]), None
+
+
+def paper_vortex(lam: float = 0.5, storage: str = "fp64", n: int = 6) -> Tuple[CaseParams, np.ndarray, None]:
+    """Sect. 4.2: disk R = 45 at (0.5 L, 0.75 L) in a 200 x 200 box under Eqs. 43-44 with
+    U0 = 0.04 and T = n L / U0 (n = 6: 30000 steps)."""
+    L = 200
+    p = CaseParams(nx=L, ny=L, mode="vortex", W=3.0, sigma=0.01, mobility=0.1, U0=0.04, T=n * L / 0.04,
+                   lam=lam, storage=storage)
+    return p, drops_phi(p, [(0.5 * L, 0.75 * L, 0.0, 45.0)]), None
+
+
+def paper_shear_drop(lam: float = 0.5, storage: str = "fp64", r: float = 8.0,
+                     U: float = 0.02) -> Tuple[CaseParams, np.ndarray, np.ndarray]:
+    """Sect. 4.4: drop of radius 8 at the centre of a 128 x 64 box between walls moving
+    at -U and +U (U not given: 0.02, the wall speed of the shear cases); nu = 0.1; initial
+    velocity the Couette profile."""
+    p = CaseParams(nx=128, ny=64, W=3.0, sigma=0.01, mobility=0.1, nu=0.1, rho_heavy=1.0, rho_light=1.0, lam=lam,
+                   wall_y=True, wall_u_bottom=(-U, 0.0, 0.0), wall_u_top=(U, 0.0, 0.0), storage=storage,
+                   label_centres=[(63.5, 31.5, 0.0)])
+    return p, drops_phi(p, [(63.5, 31.5, 0.0, r)]), couette_u(p)
+
+
 BATCH_SEED = 10899
 
 
