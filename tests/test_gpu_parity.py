@@ -327,6 +327,32 @@ def test_case_autotune_restores_state_and_uses_cache(variant, tmp_path):
     assert len(open(cache).read().strip().splitlines()) == 1
 
 
+def test_full_size_column_one_step_against_oracle():
+    """The 3D workload at full size (96 x 96 x 384 D3Q19, 3.5 M nodes) in the launch
+    configuration the benchmark times (the autotuned tile): one step from init, compared
+    node by node with the oracle's step.  FP64 storage must stay within the one-step
+    rounding bound, FP32 storage within that bound scaled to FP32 rounding."""
+    v = _v()
+    p64, phi0, u0 = W.rayleigh_plateau("fp64")
+    say("case: rayleigh_plateau 96x96x384, oracle init + one step")
+    m = Model(p64).init(phi0, u0)
+    F0 = m.fields()
+    cond = {"fp64": (1e-13, normal_conditioning(m, F0)), "fp32": (1e-6, normal_conditioning(m, F0, eps=6e-8))}
+    del F0
+    m.step(1)
+    for storage in ("fp64", "fp32"):
+        c = v.Case(p64.replace(storage=storage)).init(phi0, u0)
+        tile = c.autotune(None, steps=2)
+        c.step(1)
+        g, f, J = c.get_state()
+        base, cd = cond[storage]
+        tol = base + 2.0 * cd
+        ratio = max(float(np.max(np.abs(g - m.g) / tol[None])), float(np.max(np.abs(f - m.f) / tol[None])))
+        say(f"  {storage}, tile {tile}: populations error / bound {ratio:.3f}, raw {max_abs(g, m.g):.2e}")
+        assert ratio <= 1.0, storage
+        del g, f, J, c
+
+
 def test_history_and_determinism():
     say("case: per-step reductions vs oracle, determinism")
     p, phi0, u0 = _small_case("periodic_ragged")
