@@ -98,8 +98,11 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
   const int P = nx + 2;
   const float rcpP = 1.0f / float(P);
   const int mask = cap - 1;
-  R* sphi = reinterpret_cast<R*>(smem_raw);
-  R* spsi = sphi + cap;
+  // phi and psi of a virtual node side by side: one 2-word LDS access per stencil point
+  struct alignas(2 * sizeof(R)) PhiPsi {
+    R phi, psi;
+  };
+  PhiPsi* sring = reinterpret_cast<PhiPsi*>(smem_raw);
   const int par = int(t & 1);
   const int dst = par ^ 1;
   const S* gsrc[9];
@@ -153,8 +156,7 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
         R ps[Q];
         pull9_flat<St>(gsrc, phis, xr, yr, nx, ny, n, wall, e[SF], ps);
         const R ph = phi_of_pulled<L, St>(e[SF], ps, c.np.rest);
-        sphi[vf & mask] = ph;
-        spsi[vf & mask] = psi_of<R>(ph, c.np.W4, c.np.xi);
+        sring[vf & mask] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
       }
       rf += dr;
       qf += dq;
@@ -170,8 +172,9 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         const int s = (vu + L::cx[j] + P * L::cy[j]) & mask;
-        in.nphi[j] = sphi[s];
-        in.npsi[j] = spsi[s];
+        const PhiPsi v = sring[s];
+        in.nphi[j] = v.phi;
+        in.npsi[j] = v.psi;
       }
       NodeOut<L, R> out;
       node_update_d2q9<R, true, St::shifted, UNIT>(c.np, in, e[SU], f, J, out);
