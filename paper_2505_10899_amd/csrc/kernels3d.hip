@@ -82,9 +82,12 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
   constexpr bool STAGE = stage3d<St>();
   extern __shared__ unsigned char smem_raw[];
   const int PW = BX + 2, PH = BY + 2, PS = PW * PH;
-  R* sphi = reinterpret_cast<R*>(smem_raw);
-  R* spsi = sphi + 4 * PS;
-  R* sg = spsi + 4 * PS;   // STAGE: [2][Q][nthr], the pulled g of planes z and z + 1, per lane
+  // phi and psi of a node side by side: one 2-word LDS access per stencil point
+  struct alignas(2 * sizeof(R)) PhiPsi {
+    R phi, psi;
+  };
+  PhiPsi* sring = reinterpret_cast<PhiPsi*>(smem_raw);
+  R* sg = reinterpret_cast<R*>(sring + 4 * PS);   // STAGE: [2][Q][nthr], the pulled g of planes z and z + 1, per lane
   const int nthr = BX * BY;
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
@@ -117,8 +120,7 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
     R ps[Q];
     pull19<St, IX>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy), g, ps);
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
-    sphi[s + (ty + 1) * PW + tx + 1] = ph;
-    spsi[s + (ty + 1) * PW + tx + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
+    sring[s + (ty + 1) * PW + tx + 1] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
     // halo cells spread evenly over the waves (thread hstep * k takes cell k), so that no
     // wave carries a second full pull while the others wait at the barrier
     const int hstep = nthr >= ring ? nthr / ring : 1;
@@ -133,8 +135,7 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
       R gh[Q], hps[Q];
       pull19<St, IX>(gsrc, phis, c.n, nbr3(hx, hy, zr, nx, ny, nz, nxy), gh, hps);
       const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
-      sphi[s + py * PW + px] = hp;
-      spsi[s + py * PW + px] = psi_of<R>(hp, c.np.W4, c.np.xi);
+      sring[s + py * PW + px] = PhiPsi{hp, psi_of<R>(hp, c.np.W4, c.np.xi)};
     }
   };
   // lane-private staging of a pulled plane (consecutive lanes, consecutive words)
@@ -188,14 +189,15 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
       // stencils of Eqs. 39-40 accumulated straight from the LDS ring
       StencilOut<L, R> st;
       const int s0i = slot(z) * PS + (ty + 1) * PW + tx + 1;
-      st.phi = sphi[s0i];
+      st.phi = sring[s0i].phi;
       st.lap = R(0);
 #pragma unroll
       for (int d = 0; d < 3; ++d) st.gphi[d] = st.gpsi[d] = R(0);
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const int s = slot(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
-        const R ph = sphi[s], ps = spsi[s];
+        const PhiPsi v = sring[s];
+        const R ph = v.phi, ps = v.psi;
         st.lap += R(6.0 * L::w[i]) * (ph - st.phi);
         if (L::cx[i] != 0) { st.gphi[0] += R(3.0 * L::w[i] * L::cx[i]) * ph; st.gpsi[0] += R(3.0 * L::w[i] * L::cx[i]) * ps; }
         if (L::cy[i] != 0) { st.gphi[1] += R(3.0 * L::w[i] * L::cy[i]) * ph; st.gpsi[1] += R(3.0 * L::w[i] * L::cy[i]) * ps; }

@@ -66,8 +66,11 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
   constexpr int Q = 9;
   const int BX = blockDim.x;
   const int W = BX + 2;
-  R* sphi = reinterpret_cast<R*>(smem_raw);
-  R* spsi = sphi + 4 * W;
+  // phi and psi of a node side by side: one 2-word LDS access per stencil point
+  struct alignas(2 * sizeof(R)) PhiPsi {
+    R phi, psi;
+  };
+  PhiPsi* sring = reinterpret_cast<PhiPsi*>(smem_raw);
   const int nx = c.nx, ny = c.ny, n = int(c.n);
   const int lane = threadIdx.x;
   const int xg = x0 + lane;
@@ -108,14 +111,12 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
     R ps[Q];
     pull9<St, IX>(gsrc, phis, col, rw, g, ps);
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
-    sphi[slot(r) * W + lane + 1] = ph;
-    spsi[slot(r) * W + lane + 1] = psi_of<R>(ph, c.np.W4, c.np.xi);
+    sring[slot(r) * W + lane + 1] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
     if (halo_lane) {
       R gh[Q], hps[Q];
       pull9<St, IX>(gsrc, phis, hcol, rw, gh, hps);
       const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
-      sphi[slot(r) * W + hidx] = hp;
-      spsi[slot(r) * W + hidx] = psi_of<R>(hp, c.np.W4, c.np.xi);
+      sring[slot(r) * W + hidx] = PhiPsi{hp, psi_of<R>(hp, c.np.W4, c.np.xi)};
     }
   };
   // reductions: label displacement along x is fixed for the lane
@@ -146,8 +147,9 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int si = slot(y + L::cy[i]) * W + lane + 1 + L::cx[i];
-        in.nphi[i] = sphi[si];
-        in.npsi[i] = spsi[si];
+        const PhiPsi v = sring[si];
+        in.nphi[i] = v.phi;
+        in.npsi[i] = v.psi;
       }
       if constexpr (!COUPLED) {
         R ux, uy;
