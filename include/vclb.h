@@ -292,9 +292,10 @@ int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty);
 int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks);
 
 /* How each case is cut into work items.  A case whose width leaves more than
-   (100 - flat_pct)% of the lanes of one-lane-per-column waves idle runs as bands of whole
-   rows marched in padded row-major order (every lane busy, some extra index arithmetic);
-   the others run as strips of bx columns, one lane per column.  Below 101 only cases
+   (100 - flat_pct)% of the lanes of its strips idle (strips of bx columns, one lane per
+   column, each on a bx-lane workgroup) runs as bands of whole rows marched in padded
+   row-major order (every lane busy, some extra index arithmetic); the others run as
+   strips.  Below 101 only cases
    whose padded row fits in bx lanes qualify for bands; 101 puts every case that fits in
    bands, 0 every case in strips (default 100). */
 int vclb_batch_set_schedule(vclb_batch* b, int32_t flat_pct);

@@ -965,12 +965,12 @@ int dispatch_storage(int storage, Fn&& fn) {
 
 // work items of a tile shape: per case, bands of ty rows, x strips of bx columns fastest
 // Whether case p runs as flattened bands: when one lane per column would leave more
-// than (100 - flat_pct)% of the lanes of its row waves idle and its rows fit the
-// flattened march with bx lanes.  Below 101 only cases that need the short lag (a row
-// fits in one chunk) qualify: the long lag holds more populations in flight and costs
-// the whole kernel a wave of occupancy.
+// than (100 - flat_pct)% of the lanes of its strips idle (strips of bx columns, each on
+// a bx-lane workgroup) and its rows fit the flattened march with bx lanes.  Below 101
+// only cases that need the short lag (a row fits in one chunk) qualify: the long lag
+// holds more populations in flight and costs the whole kernel a wave of occupancy.
 bool batch_case_flat(const vclb_params& p, int bx, int flat_pct) {
-  const int lanes = (p.nx + 63) / 64 * 64;
+  const long lanes = long((p.nx + bx - 1) / bx) * bx;
   const int lag = vclb::flat_lag(p.nx + 2, bx);
   if (lag == 0 || 100L * p.nx >= long(flat_pct) * lanes) return false;
   return flat_pct > 100 || lag == 1;
