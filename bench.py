@@ -9,7 +9,8 @@ of the whole hot path over every case: pull streaming with bounce-back/moving wa
 phi and psi with their LDS halo, the gradient/Laplacian/normal stencils, chemical
 potential, velocity and pressure, g and f collisions with the level-set source, and
 the per-case FP64 volume reductions, as one work-list kernel per step; a call's steps
-are replayed from one hipGraph.  The tile is chosen by the library's autotuner.  The
+are replayed from one hipGraph.  The tile is chosen by the library's autotuner, and the
+runs of work items are then re-cut to the measured speed of each workgroup slot.  The
 batch is timed for each storage precision; `value` is the FP32-storage rate (FP32
 arithmetic), FP16-shifted and FP64 are under `variants`.
 
@@ -97,7 +98,8 @@ def timer():
 
 
 # ----------------------------------------------------------------------------- batch
-def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_steps: int, fixed=None):
+def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_steps: int, fixed=None,
+              balance: bool = True):
     import torch
     import workloads as W
     from paper_2505_10899_amd import vclb
@@ -114,7 +116,10 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     else:
         tile = b.autotune(None, steps=tune_steps)
     sched = b.schedule()
-    log(f"batch {storage}: {len(cases)} cases, {N} nodes, autotuned tile {tile}, flat_pct {sched}")
+    # re-cut the runs to the measured speed of each workgroup slot (state restored)
+    gain = b.balance(rounds=3, steps=3) if balance else 1.0
+    log(f"batch {storage}: {len(cases)} cases, {N} nodes, tile {tile}, flat_pct {sched}, "
+        f"slot balancing: slowest slot {gain:.3f}x faster")
     b.step(warmup, graph=True)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
@@ -142,7 +147,7 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     del b
     return dict(nodes=N, ms_per_step=ms, wall_s=wall, mlups=N / (ms * 1e-3) / 1e6, launch_ms=launch_ms,
                 bytes_per_node=bpn, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=list(tile), flat_pct=sched,
-                max_rel_volume_drift=drift, drift_steps=int(t_end))
+                balance_gain=gain, max_rel_volume_drift=drift, drift_steps=int(t_end))
 
 
 # ----------------------------------------------------------------------------- adjoint
@@ -263,6 +268,8 @@ def main(argv=None):
     ap.add_argument("--no-single-tune", action="store_true",
                     help="single cases keep their default tiles (profiling runs: one tile per kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-balance", action="store_true",
+                    help="keep runs of equal modelled cost (no per-slot speed balancing)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (a known-size reference "
                          "for the HBM byte counters)")
@@ -283,7 +290,7 @@ def main(argv=None):
         for item in filter(None, a.batch_tile.split(";")):
             k, v = item.split("=")
             fixed[k.strip()] = tuple(int(x) for x in v.split(","))
-        r = run_batch(st, a.steps, a.warmup, a.launch_steps, a.tune_steps, fixed.get(st))
+        r = run_batch(st, a.steps, a.warmup, a.launch_steps, a.tune_steps, fixed.get(st), balance=not a.no_balance)
         res[st] = r
         log(f"batch {st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, launch {r['launch_ms']:.3f} ms, "
             f"{r['achieved_GBs']:.0f} GB/s ({100 * r['frac']:.1f}% of HBM peak), drift {r['max_rel_volume_drift']:.2e}")
@@ -306,6 +313,7 @@ def main(argv=None):
                           "launch_ms": round(v["launch_ms"], 5), "achieved_GBs": round(v["achieved_GBs"], 1),
                           "frac_hbm_peak": round(v["frac"], 4), "bytes_per_node": v["bytes_per_node"],
                           "tile": v["tile"], "flat_pct": v["flat_pct"],
+                          "slot_balance_gain": round(v["balance_gain"], 4),
                           "max_rel_volume_drift": v["max_rel_volume_drift"],
                           "drift_over_steps": v["drift_steps"],
                           "speedup_vs_fp64": (round(v["mlups"] / res["fp64"]["mlups"], 3) if "fp64" in res else None)}

@@ -286,8 +286,9 @@ int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
 /* Launch shape of the batched step: bx in {64, 128, 256, 512} lanes per workgroup, and work
    items of at most about ty * 256 nodes (ty in 1..1024; 1024 keeps cases up to 512 x 512
    whole).  As many workgroups as can be resident are launched, each given one run of
-   consecutive items with about equal work (an item is split between rows where a run
-   ends); get_tile also returns that workgroup count.  Default: bx 512, ty 1024. */
+   consecutive items with about equal work, or work in proportion to the slot weights
+   vclb_batch_balance measured (an item is split between rows where a run ends);
+   get_tile also returns that workgroup count.  Default: bx 512, ty 1024. */
 int vclb_batch_set_tile(vclb_batch* b, int32_t bx, int32_t ty);
 int vclb_batch_get_tile(const vclb_batch* b, int32_t* bx, int32_t* ty, int32_t* blocks);
 
@@ -327,6 +328,22 @@ int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stre
    file cache_path when that holds an entry for this batch; a measured choice is appended
    to cache_path (NULL: no file). */
 int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, void* stream);
+
+/* Fit the cut of the batch into runs to the speed of each resident workgroup slot.  The
+   slots of one launch do not advance at one rate (on one device the spread is about
+   +-10%, set by where a slot's workgroup runs, not by the cases it is given), so runs of
+   equal modelled cost finish at different times.  This times every slot over its run
+   for `steps` launches on the current state (saved and restored, host synchronised),
+   gives each slot a weight in proportion to its measured speed, re-cuts the runs with
+   budgets in proportion to the weights, and repeats `rounds` times (rounds in 1..16,
+   steps in 1..1000).  The cut whose slowest slot was fastest is kept, the equal one
+   included; *gain (may be NULL) receives the slowest slot's time before over after
+   (1 if nothing beat the cut it started from).  The results of a step do not depend on
+   the cut (each node's update is the same); the per-case reductions are summed in
+   another grouping, so they may differ in the last bits.  The weights stay in force
+   while the launch shape is unchanged: set_tile or set_schedule with another shape, or
+   autotune, drop them. */
+int vclb_batch_balance(vclb_batch* b, int32_t rounds, int32_t steps, double* gain, void* stream);
 
 #ifdef __cplusplus
 }

@@ -933,6 +933,7 @@ struct vclb_batch {
   int4* d_items = nullptr;
   int2* d_case_items = nullptr;
   int2* d_runs = nullptr;             // (first item, count) per resident workgroup slot
+  unsigned* d_ticks = nullptr;        // per slot: clock ticks of its run (balancing launches)
   size_t runs_cap = 0;
   double* part[2] = {nullptr, nullptr};
   size_t items_cap = 0;
@@ -940,6 +941,11 @@ struct vclb_batch {
   std::vector<int2> case_items;
   std::vector<int2> runs;
   int bx = 512, ty = 1024, blocks = 0, cap = 0, lag = 1, flat_pct = 100;
+  // relative speed of each run slot (mean 1; empty: all equal) and the launch shape it
+  // was measured with
+  std::vector<double> weight;
+  int wbx = 0, wty = 0, wfp = -1;
+  bool ticking = false;               // launches record per-slot ticks
   int reduce_every = 1;
   bool unit = true;                   // every case has unit rates outside the g flux / f stress rows
   int64_t nodes = 0;
@@ -999,59 +1005,72 @@ void build_items(vclb_batch* b, int bx, int ty, int flat_pct, std::vector<int4>&
   }
 }
 
-// Cut the case-major item list into nb runs of consecutive items, one per resident
-// workgroup, with about equal iteration counts: a flattened band of r rows costs
+// Modelled cost of a work item in march iterations: a flattened band of r rows costs
 // ceil((r + 2) P / bx) + lag chunk iterations, a strip band r + 2 row iterations (both
-// pull two halo rows).  An item that straddles the end of a run is split between rows.
-// The smallest per-run budget that fits in nb runs is found by bisection.
-void partition_runs(const vclb_batch* b, int bx, int lag, int nb, std::vector<int4>& items, std::vector<int2>& ci,
-                    std::vector<int2>& runs) {
-  struct Cost { double over, row; };
-  auto cost_of = [&](const int4& w) -> Cost {
-    if (w.y < 0) {
-      const double P = b->cases[size_t(w.x)]->p.nx + 2.0;
-      return {2.0 * P / bx + lag + 0.5, P / bx};
-    }
-    return {2.0, 1.0};
-  };
-  // fn(piece, new_run) for each piece of the cut with budget T; returns the runs used
+// pull two halo rows); returned as a per-item overhead plus a cost per row.
+struct ItemCost {
+  double over, row;
+};
+ItemCost item_cost(const vclb_batch* b, const int4& w, int bx, int lag) {
+  if (w.y < 0) {
+    const double P = b->cases[size_t(w.x)]->p.nx + 2.0;
+    return {2.0 * P / bx + lag + 0.5, P / bx};
+  }
+  return {2.0, 1.0};
+}
+
+// Cut the case-major item list into nb runs of consecutive items, one per resident
+// workgroup slot, each with a modelled cost in proportion to its slot's weight (all
+// equal when weight is empty).  An item that straddles the end of a run is split between
+// rows.  The smallest budget scale that fits in nb runs is found by bisection.
+void partition_runs(const vclb_batch* b, int bx, int lag, int nb, const std::vector<double>& weight,
+                    std::vector<int4>& items, std::vector<int2>& ci, std::vector<int2>& runs) {
+  auto wt = [&](int r) { return r < int(weight.size()) ? weight[size_t(r)] : 1.0; };
+  // fn(piece, new_run) for each piece of the cut with budget scale T (run r holds at
+  // most T wt(r)); returns the runs used
   auto cut = [&](double T, auto&& fn) -> int {
     int used = 0;
-    double fill = 0.0;
+    bool open = false;
+    double fill = 0.0, budget = 0.0;
     for (const int4& w : items) {
-      const Cost c = cost_of(w);
+      const ItemCost c = item_cost(b, w, bx, lag);
       int y = w.z;
       while (y < w.w) {
+        if (!open) {   // start the next run
+          budget = T * wt(used);
+          ++used;
+          fill = 0.0;
+          open = true;
+        }
+        const bool first = fill == 0.0;
         const int left = w.w - y;
-        if (fill + c.over + left * c.row <= T) {
-          fn(int4{w.x, w.y, y, w.w}, fill == 0.0);
-          if (fill == 0.0) ++used;
+        if (fill + c.over + left * c.row <= budget) {
+          fn(int4{w.x, w.y, y, w.w}, first);
           fill += c.over + left * c.row;
           break;
         }
-        int rr = int((T - fill - c.over) / c.row);
-        if (rr < 1 && fill > 0.0) {   // no room left here: the next run starts with this item
-          fill = 0.0;
+        int rr = int((budget - fill - c.over) / c.row);
+        if (rr < 1 && !first) {   // no room left here: the next run starts with this item
+          open = false;
           continue;
         }
         rr = std::max(1, std::min(rr, left));
-        fn(int4{w.x, w.y, y, y + rr}, fill == 0.0);
-        if (fill == 0.0) ++used;
+        fn(int4{w.x, w.y, y, y + rr}, first);
         y += rr;
-        fill = 0.0;   // the run is full
+        open = false;   // the run is full
       }
     }
     return used;
   };
-  double total = 0.0, biggest = 0.0;
+  double total = 0.0, wmin = 1.0;
   for (const int4& w : items) {
-    const Cost c = cost_of(w);
+    const ItemCost c = item_cost(b, w, bx, lag);
     total += c.over + (w.w - w.z) * c.row;
-    biggest = std::max(biggest, c.over + c.row);
   }
-  double lo = std::max(total / nb, biggest), hi = total + 1.0;
+  for (int r = 0; r < nb; ++r) wmin = std::min(wmin, wt(r));
+  double lo = 0.0, hi = (total + 1.0) / std::max(wmin, 1e-3);
   auto none = [](const int4&, bool) {};
-  for (int k = 0; k < 60 && hi - lo > 1e-3 * lo; ++k) {
+  for (int k = 0; k < 64 && hi - lo > 1e-4 * hi; ++k) {
     const double mid = 0.5 * (lo + hi);
     if (cut(mid, none) <= nb) hi = mid;
     else lo = mid;
@@ -1097,7 +1116,9 @@ int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   if (per_cu < 1) per_cu = 1;
   const int nb = int(std::min<long>(long(per_cu) * ncu, long(b->runs_cap)));
-  partition_runs(b, bx, lag, nb, items, ci, runs);
+  // slot weights hold for the launch shape they were measured with
+  if (b->weight.size() != size_t(nb) || b->wbx != bx || b->wty != ty || b->wfp != flat_pct) b->weight.clear();
+  partition_runs(b, bx, lag, nb, b->weight, items, ci, runs);
   if (items.size() > b->items_cap) return fail(VCLB_EINVAL, "too many work items");
   HIP_TRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->d_case_items, ci.data(), ci.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -1112,6 +1133,18 @@ int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
   b->case_items = std::move(ci);
   b->runs = std::move(runs);
   return VCLB_OK;
+}
+
+// modelled cost (march iterations) of each run slot of the current cut
+std::vector<double> run_costs(const vclb_batch* b) {
+  std::vector<double> cost(b->runs.size(), 0.0);
+  for (size_t r = 0; r < b->runs.size(); ++r)
+    for (int i = b->runs[r].x; i < b->runs[r].x + b->runs[r].y; ++i) {
+      const int4& w = b->items[size_t(i)];
+      const ItemCost c = item_cost(b, w, b->bx, b->lag);
+      cost[r] += c.over + (w.w - w.z) * c.row;
+    }
+  return cost;
 }
 
 vclb::BatchArgs batch_args(const vclb_batch* b, int64_t t, int reduce) {
@@ -1130,6 +1163,7 @@ vclb::BatchArgs batch_args(const vclb_batch* b, int64_t t, int reduce) {
   a.cap = b->cap;
   a.lag = b->lag;
   a.unit = b->unit ? 1 : 0;
+  a.ticks = b->ticking ? b->d_ticks : nullptr;
   return a;
 }
 
@@ -1213,6 +1247,8 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
   total += align_up(size_t(ncases) * sizeof(int2));
   const size_t o_runs = total;
   total += align_up(runs_cap * sizeof(int2));
+  const size_t o_ticks = total;
+  total += align_up(runs_cap * sizeof(unsigned));
   size_t o_part[2];
   for (int i = 0; i < 2; ++i) {
     o_part[i] = total;
@@ -1230,6 +1266,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
   b->d_items = reinterpret_cast<int4*>(b->ws + o_items);
   b->d_case_items = reinterpret_cast<int2*>(b->ws + o_ci);
   b->d_runs = reinterpret_cast<int2*>(b->ws + o_runs);
+  b->d_ticks = reinterpret_cast<unsigned*>(b->ws + o_ticks);
   b->runs_cap = runs_cap;
   for (int i = 0; i < 2; ++i) b->part[i] = reinterpret_cast<double*>(b->ws + o_part[i]);
   for (int k = 0; k < ncases; ++k) {
@@ -1457,6 +1494,100 @@ int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stre
       if (b->reduce_every > 0 && t % b->reduce_every == 0) c->recorded[size_t(t % vclb::kHistory)] = t;
     c->t_host = t0 + nsteps;
   }
+  return VCLB_OK;
+}
+
+int vclb_batch_balance(vclb_batch* b, int32_t rounds, int32_t steps, double* gain, void* stream) {
+  if (!b || rounds < 1 || rounds > 16 || steps < 1 || steps > 1000) return fail(VCLB_EINVAL, "bad balance arguments");
+  if (gain) *gain = 1.0;
+  for (vclb_case* c : b->cases)
+    if (!c->inited) return fail(VCLB_ESTATE, "balance needs initialised cases (their state is restored)");
+  hipStream_t s = as_stream(stream);
+  batch_release_graph(b);
+  HIP_TRY(hipStreamSynchronize(s));
+  size_t bytes = 0;
+  for (vclb_case* c : b->cases) bytes += c->lay.total;
+  void* save = nullptr;
+  HIP_TRY(hipMalloc(&save, bytes));
+  size_t o = 0;
+  for (vclb_case* c : b->cases) {
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(save) + o, c->ws, c->lay.total, hipMemcpyDeviceToDevice, s));
+    o += c->lay.total;
+  }
+  const int64_t t0 = b->cases[0]->t_host;
+  int64_t t = t0;
+  const int nb = b->blocks;
+  std::vector<unsigned> tk(size_t(nb), 0u);
+  // steps + 1 launches with per-slot ticks (the first not counted): each slot's mean
+  // ticks, and the mean over launches of the slowest slot's
+  auto measure = [&](std::vector<double>& mean, double& span) -> int {
+    mean.assign(size_t(nb), 0.0);
+    span = 0.0;
+    for (int k = 0; k <= steps; ++k) {
+      for (vclb_case* c : b->cases) c->t_host = t;
+      b->ticking = true;
+      const int rc = batch_enqueue(b, 1, false, s);
+      b->ticking = false;
+      if (rc) return rc;
+      ++t;
+      HIP_TRY(hipMemcpyAsync(tk.data(), b->d_ticks, size_t(nb) * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (k == 0) continue;
+      unsigned mx = 0;
+      for (int r = 0; r < nb; ++r) {
+        mean[size_t(r)] += double(tk[size_t(r)]) / steps;
+        mx = std::max(mx, tk[size_t(r)]);
+      }
+      span += double(mx) / steps;
+    }
+    return VCLB_OK;
+  };
+  std::vector<double> mean, best_w = b->weight;
+  double span = 0.0, best = 0.0, first = 0.0;
+  int rc = measure(mean, best);
+  first = best;
+  for (int round = 0; rc == VCLB_OK && round < rounds; ++round) {
+    // a slot's speed: the modelled cost of its run over the time it took
+    const std::vector<double> cost = run_costs(b);
+    std::vector<double> w(size_t(nb), 0.0);
+    double sum = 0.0;
+    int cnt = 0;
+    for (int r = 0; r < nb; ++r)
+      if (cost[size_t(r)] > 0.0 && mean[size_t(r)] > 0.0) {
+        w[size_t(r)] = cost[size_t(r)] / mean[size_t(r)];
+        sum += w[size_t(r)];
+        ++cnt;
+      }
+    if (cnt == 0) break;
+    for (double& x : w) x = x > 0.0 ? x * cnt / sum : 1.0;
+    b->weight = w;
+    b->wbx = b->bx;
+    b->wty = b->ty;
+    b->wfp = b->flat_pct;
+    if ((rc = batch_set_tile(b, b->bx, b->ty, b->flat_pct))) break;
+    if ((rc = measure(mean, span))) break;
+    if (span < best) {
+      best = span;
+      best_w = w;
+    }
+  }
+  o = 0;
+  for (vclb_case* c : b->cases) {
+    (void)hipMemcpyAsync(c->ws, static_cast<char*>(save) + o, c->lay.total, hipMemcpyDeviceToDevice, s);
+    c->t_host = t0;
+    o += c->lay.total;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(save);
+  if (rc) {
+    b->weight.clear();
+    (void)batch_set_tile(b, b->bx, b->ty, b->flat_pct);
+    return rc;
+  }
+  // keep the fastest cut seen (the uniform one if no weighting beat it)
+  b->weight = best_w;
+  if ((rc = batch_set_tile(b, b->bx, b->ty, b->flat_pct))) return rc;
+  if (gain && best > 0.0) *gain = first / best;
   return VCLB_OK;
 }
 

@@ -2,7 +2,8 @@
 //
 // A fixed number of resident workgroups each take one run of consecutive work items,
 // the runs cut on the host so that every workgroup has about the same number of
-// iterations (items are split between rows where a run ends).  An item is either a strip of columns marched row by row (step2d_tile, one lane per
+// iterations, or iterations in proportion to the speed its slot was measured at (items
+// are split between rows where a run ends).  An item is either a strip of columns marched row by row (step2d_tile, one lane per
 // column: best when the width is close to a multiple of the wave size) or a band of
 // whole rows marched in padded row-major order (step2d_flat: every lane busy for any
 // width, at some extra index arithmetic); the host picks per case.  The n launches of a call are captured in one hipGraph and
@@ -58,7 +59,9 @@ __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS, UNIT>()))
     for (int cs = blockIdx.x; cs < a.ncases; cs += gridDim.x) fold_case<St>(cases[cs], a, cs);
   // consecutive runs go to one XCD: the rows where one run ends and the next begins are
   // read by both, through that XCD's L2
-  const int2 run = a.runs[xcd_tile(blockIdx.x, gridDim.x)];
+  const int slot = xcd_tile(blockIdx.x, gridDim.x);
+  const int2 run = a.runs[slot];
+  const unsigned long long t_begin = a.ticks ? wall_clock64() : 0ull;
   for (int it = run.x; it < run.x + run.y; ++it) {
     const int4 w = a.items[it];
     if (w.y < 0)   // a band of whole rows, marched in padded row-major order
@@ -68,6 +71,8 @@ __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS, UNIT>()))
                                             smem_raw);
     __syncthreads();
   }
+  // balancing launches record how long this slot took over its run (constant-rate clock)
+  if (a.ticks && threadIdx.x == 0) a.ticks[slot] = unsigned(wall_clock64() - t_begin);
 }
 
 template <class St>

@@ -54,6 +54,8 @@ struct BatchArgs {
   int cap;                  // LDS ring entries of the flattened march (power of two)
   int lag;                  // its lag in chunks (1 or 3)
   int unit;                 // every case has unit rates outside the g flux and f stress rows
+  unsigned* ticks;          // if set: per run slot, the wall-clock ticks its workgroup spent
+                            // on its run (balancing launches only)
 };
 
 template <class St>

@@ -99,6 +99,8 @@ _SIGS = [
     ("vclb_batch_get_schedule", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32)]),
     ("vclb_batch_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]),
     ("vclb_batch_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32, ctypes.c_void_p]),
+    ("vclb_batch_balance", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double),
+                                           ctypes.c_void_p]),
     ("vclb_state_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("vclb_state_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("vclb_obs_derived", ctypes.c_int, [_P(Obs), ctypes.c_int32, _P(ctypes.c_double)]),
@@ -533,3 +535,10 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         check(lib().vclb_batch_autotune(self.h, path, int(steps), _stream_handle(stream)))
         return self.tile()
+
+    def balance(self, rounds: int = 3, steps: int = 3, stream=None) -> float:
+        """Re-cut the runs to the measured speed of each workgroup slot (state restored);
+        returns the slowest slot's time before over after."""
+        g = ctypes.c_double(1.0)
+        check(lib().vclb_batch_balance(self.h, int(rounds), int(steps), ctypes.byref(g), _stream_handle(stream)))
+        return g.value

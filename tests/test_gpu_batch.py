@@ -1,7 +1,7 @@
 """GPU tests of the batched path: uneven cases advanced together must reproduce each
 case advanced alone with the same tile (the single-case path is itself checked against
-the oracle), the hipGraph replay must equal eager launches, and the autotuner must leave
-the state untouched."""
+the oracle), the hipGraph replay must equal eager launches, and the autotuner and the
+slot balancing must leave the state untouched."""
 import os
 import sys
 
@@ -187,6 +187,46 @@ def test_batch_autotune_restores_state_and_uses_cache(tmp_path):
     assert len(open(cache).read().strip().splitlines()) == 1
 
 
+@pytest.mark.parametrize("storage,flat_pct,bx", [("fp64", 101, 64), ("fp16s", 0, 256), ("fp32", 100, 512)])
+def test_batch_balance_restores_state_and_keeps_results(storage, flat_pct, bx):
+    """Slot balancing times launches on the state and restores it; stepping with the re-cut
+    runs gives bit-identical states to stepping with runs of equal modelled cost (each
+    node's update does not depend on the cut), and the reductions agree to rounding."""
+    v = _v()
+    cases = small_batch(storage, n=8, seed=5)
+    say("case: balance", storage, "flat_pct", flat_pct, "bx", bx, [(p.nx, p.ny) for p, _, _ in cases])
+
+    def make():
+        b = v.Batch([p for p, _, _ in cases])
+        b.set_tile(bx, 16)
+        b.set_schedule(flat_pct)
+        for c, (p, phi0, u0) in zip(b.cases, cases):
+            c.init(phi0, u0)
+        return b
+
+    plain, tuned = make(), make()
+    plain.step(3)
+    tuned.step(3)
+    before = [c.get_state() for c in tuned.cases]
+    gain = tuned.balance(rounds=3, steps=2)
+    say(f"  slowest slot before / after: {gain:.3f}")
+    assert gain >= 1.0
+    for x, c in zip(before, tuned.cases):
+        for a, y in zip(x, c.get_state()):
+            assert np.array_equal(a, y)
+    assert all(c.time() == 3 for c in tuned.cases)
+    assert tuned.tile()[:2] == (bx, 16) and tuned.schedule() == flat_pct
+    plain.step(20)
+    tuned.step(20)
+    for k in range(len(cases)):
+        for a, y in zip(plain.cases[k].get_state(), tuned.cases[k].get_state()):
+            assert np.array_equal(a, y), k
+    hp, ht = plain.history(3, 20), tuned.history(3, 20)
+    assert np.allclose(hp["sum_phi"], ht["sum_phi"], rtol=1e-12, atol=0.0)
+    with pytest.raises(v.VclbError):
+        tuned.balance(rounds=0)
+
+
 # --------------------------------------------------------------------------- full size
 def _sample(cases):
     """Indices of a few cases that span the batch: largest, smallest, widest, narrowest,
@@ -230,6 +270,7 @@ def test_full_batch_fp64_sampled_cases_match_oracle():
             models[k] = (m, normal_conditioning(m, m.fields()))
         else:
             c.init(phi0, u0)
+    say(f"  slot balancing (as the benchmark does): gain {b.balance(rounds=3, steps=3):.3f}")
     b.step(1)
     for k in idx:
         m, cond = models[k]
@@ -262,6 +303,7 @@ def test_full_batch_reduced_precision_volume_and_sampled_fields(storage):
     say(f"case: full batch {storage}, sampled cases", idx)
     for c, (p, phi0, u0) in zip(b.cases, cases):
         c.init(phi0, u0)
+    say(f"  slot balancing (as the benchmark does): gain {b.balance(rounds=3, steps=3):.3f}")
     v0 = b.reduce()["sum_phi"][:, 0]
     b.step(1)
     for k in idx:
