@@ -324,7 +324,9 @@ int vclb_batch_history(vclb_batch* b, int64_t t_first, int32_t count, vclb_obs* 
 int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stream);
 
 /* Pick the batched tile and schedule (bx, ty, flat_pct) by timing `steps` steps of every
-   candidate on the current state (saved and restored), or take them from the JSON-lines
+   candidate on the current state (saved and restored), then the four fastest twice more
+   with 2 * steps steps each, in alternation, keeping each one's best time (the leading
+   shapes often lie within timing noise of each other); or take them from the JSON-lines
    file cache_path when that holds an entry for this batch; a measured choice is appended
    to cache_path (NULL: no file). */
 int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, void* stream);

@@ -120,15 +120,29 @@ __device__ __forceinline__ R clamp01(R v) {
   return v < R(0) ? R(0) : (v > R(1) ? R(1) : v);
 }
 
+// 1 / x and 1 / sqrt(x) for positive normal x: in FP32 the hardware instructions (about
+// 1 ulp each, no denormal scaling, no Newton step in FP64), in FP64 correctly rounded
+// division and the library rsqrt
+template <class R>
+__device__ __forceinline__ R recip(R x) {
+  if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(x);
+  else return R(1) / x;
+}
+template <class R>
+__device__ __forceinline__ R rsqrt_of(R x) {
+  if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rsqf(x);
+  else return rsqrt(x);
+}
+
 // psi of Eq. 37 on the clipped order parameter
 template <class R>
 __device__ __forceinline__ R psi_of(R phi, R W4, R xi) {
   const R pc = clamp01(phi);
   if constexpr (sizeof(R) == 4) {
-    // hardware reciprocal and logarithm (about 1 ulp each): the quotient lies in
-    // [xi / (1 + xi), (1 + xi) / xi], far from denormals, and psi's own rounding at its
-    // magnitude (up to (W / 4) ln(1 / xi)) is larger than what they add
-    return W4 * __logf((pc + xi) * __builtin_amdgcn_rcpf((R(1) - pc) + xi));
+    // hardware reciprocal and base-2 logarithm (about 1 ulp each; ln = ln 2 log2): the
+    // quotient lies in [xi / (1 + xi), (1 + xi) / xi], far from denormals, and psi's own
+    // rounding at its magnitude (up to (W / 4) ln(1 / xi)) is larger than what they add
+    return (W4 * R(0.693147180559945309)) * __builtin_amdgcn_logf((pc + xi) * __builtin_amdgcn_rcpf((R(1) - pc) + xi));
   } else {
     return W4 * log((pc + xi) / ((R(1) - pc) + xi));
   }
@@ -246,7 +260,7 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   R fm[9];
   if constexpr (COUPLED) {
     d2q9_moments<R>(f, fm);
-    const R irho = R(1) / rho;
+    const R irho = recip(rho);
     ux = (fm[3] + R(0.5) * Fx) * irho;                                           // Eq. 28
     uy = (fm[5] + R(0.5) * Fy) * irho;
     const R P = fm[0] - f[0];
@@ -260,7 +274,7 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   const R dJx = Jx - J[0], dJy = Jy - J[1];
   J[0] = Jx;
   J[1] = Jy;
-  const R inv = rsqrt(gsx * gsx + gsy * gsy + p.eps2);
+  const R inv = rsqrt_of(gsx * gsx + gsy * gsy + p.eps2);
   const R Vx = R(3) * dJx + An * (gsx * inv), Vy = R(3) * dJy + An * (gsy * inv);  // Eq. 32: G_i = w_i c_i . V
   // g (Eq. 33): equilibrium moments (phi, -4 phi + 2H, 4 phi - 3H, Jx, -Jx, Jy, -Jy, 0, 0), H = mu + lambda phi;
   // in deviation variables (subtract M r phi) they are (0, 2 mu, -3 mu, Jx, -Jx, Jy, -Jy, 0, 0).
@@ -505,7 +519,7 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
       if (D == 3 && L::cz[i] != 0) jj[2] += R(L::cz[i]) * f[i];
     }
     R uu = R(0), ug = R(0);
-    const R irho = R(1) / rho;
+    const R irho = recip(rho);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       u[d] = (jj[d] + R(0.5) * Fs[d]) * irho;                                       // Eq. 28
@@ -521,7 +535,7 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
   R n2 = p.eps2;
 #pragma unroll
   for (int d = 0; d < D; ++d) n2 += gpsi[d] * gpsi[d];
-  const R inv = rsqrt(n2);
+  const R inv = rsqrt_of(n2);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     Jn[d] = phi * u[d];

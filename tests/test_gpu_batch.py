@@ -239,29 +239,33 @@ def _sample(cases):
     return sorted(idx)
 
 
-# the launch configurations the benchmark's autotuner picks on this batch (bands for
-# every case, or strips for the cases whose width is a multiple of 64)
-FULL_SCHEDULE = {"fp64": 100, "fp32": 100, "fp16s": 101}
+# the launch configurations the benchmark's autotuner chooses between on this batch
+# (their times lie within noise of each other): 512-lane workgroups, whole-case items
+# (ty 1024) or items of about 16k nodes (ty 64), and bands for the cases that fit the
+# two-slot FIFO with strips for the wider ones (flat_pct 100) or bands for every case
+# (101, the four-slot FIFO kernel)
+FULL_SHAPES = [(1024, 100), (1024, 101), (64, 100)]
 
 
-def _full_batch(v, storage):
+def _full_batch(v, storage, ty, flat_pct):
     cases, _ = W.batch_cases(512, storage=storage)
     b = v.Batch([p for p, _, _ in cases])
-    b.set_tile(512, 1024)
-    b.set_schedule(FULL_SCHEDULE[storage])
+    b.set_tile(512, ty)
+    b.set_schedule(flat_pct)
     return cases, b
 
 
-def test_full_batch_fp64_sampled_cases_match_oracle():
+@pytest.mark.parametrize("ty,flat_pct", FULL_SHAPES[:2])
+def test_full_batch_fp64_sampled_cases_match_oracle(ty, flat_pct):
     """All 512 cases (24.4 M nodes) in the benchmark's launch configuration; sampled cases
     start from the oracle's exact state and, after one batched step, match the oracle's
     step node by node within the rounding bound of the one-step parity tests."""
     v = _v()
     from oracle.model import Model
     from test_gpu_parity import normal_conditioning
-    cases, b = _full_batch(v, "fp64")
+    cases, b = _full_batch(v, "fp64", ty, flat_pct)
     idx = _sample(cases)
-    say("case: full batch fp64, sampled cases", [(k, cases[k][0].nx, cases[k][0].ny, cases[k][0].wall_y) for k in idx])
+    say(f"case: full batch fp64, ty {ty}, flat_pct {flat_pct}, sampled cases", [(k, cases[k][0].nx, cases[k][0].ny, cases[k][0].wall_y) for k in idx])
     models = {}
     for k, (c, (p, phi0, u0)) in enumerate(zip(b.cases, cases)):
         if k in idx:
@@ -288,8 +292,9 @@ def test_full_batch_fp64_sampled_cases_match_oracle():
 REDUCED = {"fp32": (6e-8, 1e-6, 1e-6, 1e-6, 1e-6), "fp16s": (4.9e-4, 5e-5, 1e-4, 5e-5, 1e-4)}
 
 
+@pytest.mark.parametrize("ty,flat_pct", FULL_SHAPES)
 @pytest.mark.parametrize("storage", ["fp32", "fp16s"])
-def test_full_batch_reduced_precision_volume_and_sampled_fields(storage):
+def test_full_batch_reduced_precision_volume_and_sampled_fields(storage, ty, flat_pct):
     """FP32 and FP16S storage at full size in the benchmark's launch configuration: every
     case keeps its volume (to 1e-6 in FP32, 1e-4 in FP16S) over 20 steps, and sampled
     cases match the FP64 oracle's first step to the storage's rounding (phi, u and the
@@ -298,9 +303,9 @@ def test_full_batch_reduced_precision_volume_and_sampled_fields(storage):
     from oracle.model import Model
     from test_gpu_parity import normal_conditioning
     eps, floor, tol_phi, tol_u, tol_drift = REDUCED[storage]
-    cases, b = _full_batch(v, storage)
+    cases, b = _full_batch(v, storage, ty, flat_pct)
     idx = _sample(cases)
-    say(f"case: full batch {storage}, sampled cases", idx)
+    say(f"case: full batch {storage}, ty {ty}, flat_pct {flat_pct}, sampled cases", idx)
     for c, (p, phi0, u0) in zip(b.cases, cases):
         c.init(phi0, u0)
     say(f"  slot balancing (as the benchmark does): gain {b.balance(rounds=3, steps=3):.3f}")
