@@ -6,7 +6,11 @@ sizes (Sect. 4), each against the classical model (lam = 0, no correction term):
 - a drop of radius 8 in shear flow on a coarse grid (Sect. 4.4): it survives with the
   correction and loses half its area without it;
 - the time-reversed single vortex with n = 6 (Sect. 4.2): the disk returns closer to its
-  initial shape with the correction.
+  initial shape with the correction;
+- the Rayleigh-Plateau break-up (Sect. 4.3), on the benchmark's 3D liquid column (the
+  planar 2D layer of Eq. 45 does not break up under either model): the column pinches
+  into a drop and a satellite under both models; with the correction the volume stays
+  put and the satellite keeps its size, without it both shrink.
 
 The thresholds are set between the two models' measured values with a wide margin; the
 figures themselves are not in the text, so no printed value pins these runs."""
@@ -81,3 +85,55 @@ def test_single_vortex_returns_closer_with_the_correction():
         say(f"vortex n = 6, lam = {lam}: sum |phi(T) - phi0| per unit perimeter {err[lam]:.4f}, "
             f"area {int((phi >= 0.5).sum())} of {int((phi0 >= 0.5).sum())}")
     assert err[0.5] <= 0.6 * err[0.0]                # measured: 0.70 against 1.47
+
+
+def _drops(phi):
+    """Volumes #(phi >= 1/2) of the connected regions of a (nz, ny, nx) field, periodic in
+    z (the column's axis), largest first."""
+    from scipy import ndimage
+    lab, n = ndimage.label(phi >= 0.5)
+    parent = list(range(n + 1))
+
+    def root(k):
+        while parent[k] != k:
+            parent[k] = parent[parent[k]]
+            k = parent[k]
+        return k
+
+    lo, hi = lab[0], lab[-1]
+    both = (lo > 0) & (hi > 0)
+    for a, b in zip(lo[both], hi[both]):
+        parent[root(int(a))] = root(int(b))
+    size = np.bincount(lab.ravel(), minlength=n + 1)
+    vol = {}
+    for k in range(1, n + 1):
+        vol[root(k)] = vol.get(root(k), 0) + int(size[k])
+    return sorted(vol.values(), reverse=True)
+
+
+def test_rayleigh_plateau_column_keeps_its_drops_only_with_the_correction():
+    """96 x 96 x 384 column, R0 = 16 with a 10% perturbation over the box length (FP32):
+    it pinches near step 25 000 into one drop and one satellite under both models."""
+    v = _v()
+    out = {}
+    for lam in (0.5, 0.0):
+        p, phi0, u0 = W.rayleigh_plateau("fp32")
+        c = v.Case(p.replace(lam=lam)).init(phi0, u0)
+        c.set_reduce_every(0)
+        vol0 = int((phi0 >= 0.5).sum())
+        c.step(30000)
+        d30 = _drops(c.observe(v.FIELD_PHI)["phi"])
+        c.step(10000)
+        d40 = _drops(c.observe(v.FIELD_PHI)["phi"])
+        out[lam] = (vol0, d30, d40)
+        say(f"column, lam = {lam}: drops at 30k {d30}, at 40k {d40}; volume at 40k / initial {sum(d40) / vol0:.4f}")
+    for lam in (0.5, 0.0):
+        vol0, d30, d40 = out[lam]
+        assert len(d30) == 2 and len(d40) == 2, lam                      # one drop and one satellite
+    vol0, d30, d40 = out[0.5]
+    assert abs(sum(d40) / vol0 - 1.0) <= 0.01                            # measured: +0.3%
+    assert abs(d40[1] / d30[1] - 1.0) <= 0.005                           # satellite, measured: +0.1%
+    vol0, e30, e40 = out[0.0]
+    assert sum(e40) / vol0 <= 0.985                                      # measured: 0.969
+    assert e40[1] < e30[1]                                               # measured: -0.8% in 10k steps
+    assert d40[1] >= 1.05 * e40[1]                                       # measured: 1.11
