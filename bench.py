@@ -104,9 +104,7 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     import workloads as W
     from paper_2505_10899_amd import vclb
     cases, _ = W.batch_cases(512, storage=storage)
-    b = vclb.Batch([p for p, _, _ in cases])
-    for c, (p, phi0, u0) in zip(b.cases, cases):
-        c.init(phi0, u0)
+    b = vclb.Batch([p for p, _, _ in cases]).init([(phi0, u0) for _, phi0, u0 in cases])
     N = b.nodes()
     v0 = b.reduce()["sum_phi"].sum(axis=1)
     if fixed:                      # (bx, ty, flat_pct) given: no autotuning (profiling runs)

@@ -280,6 +280,15 @@ void vclb_batch_destroy(vclb_batch* b);
    history / get_state work on it.  Do not destroy it or call vclb_step on it. */
 int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out);
 
+/* Initial state of every case, as vclb_case_init on each in order: phi0s[k] (and u0s[k],
+   if u0s is not NULL; a NULL entry means u = 0) are case k's fields, all host or all
+   device memory (ptr_kind); the two pointer arrays themselves are host memory with
+   ncases entries.  Every phi0s[k] is checked for NULL before any case is touched; an
+   error from case k's init leaves cases 0..k-1 initialised and is returned with the
+   case index in vclb_last_error. */
+int vclb_batch_init(vclb_batch* b, const double* const* phi0s, const double* const* u0s, int ptr_kind,
+                    void* stream);
+
 /* Total nodes of all cases. */
 int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
 

@@ -1334,6 +1334,19 @@ int vclb_batch_case(vclb_batch* b, int32_t k, vclb_case** out) {
   return VCLB_OK;
 }
 
+int vclb_batch_init(vclb_batch* b, const double* const* phi0s, const double* const* u0s, int ptr_kind,
+                    void* stream) {
+  if (!b || !phi0s) return fail(VCLB_EINVAL, "batch or phi0s is NULL");
+  if (ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
+  for (int k = 0; k < b->n; ++k)
+    if (!phi0s[k]) return fail(VCLB_EINVAL, "phi0 of case " + std::to_string(k) + " is NULL");
+  for (int k = 0; k < b->n; ++k) {
+    const int rc = vclb_case_init(b->cases[size_t(k)], phi0s[k], u0s ? u0s[k] : nullptr, ptr_kind, stream);
+    if (rc) return fail(rc, "case " + std::to_string(k) + ": " + g_last_error);
+  }
+  return VCLB_OK;
+}
+
 int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes) {
   if (!b || !nodes) return fail(VCLB_EINVAL, "NULL argument");
   *nodes = b->nodes;

@@ -89,6 +89,8 @@ _SIGS = [
     ("vclb_batch_destroy", None, [ctypes.c_void_p]),
     ("vclb_batch_case", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_void_p)]),
     ("vclb_batch_nodes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64)]),
+    ("vclb_batch_init", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_void_p), _P(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.c_void_p]),
     ("vclb_batch_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     ("vclb_batch_get_tile", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     ("vclb_batch_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -478,6 +480,25 @@ class Batch:
                 self.h = None
         except Exception:
             pass
+
+    def init(self, fields, stream=None):
+        """Initial state of every case from a list of (phi0, u0) pairs (u0 may be None),
+        in one library call."""
+        if len(fields) != len(self.cases):
+            raise VclbError(VCLB_EINVAL, "one (phi0, u0) pair per case")
+        phis, us = [], []
+        for phi0, u0 in fields:
+            phi = _as_device_f64(phi0, self.device)
+            if not torch.isfinite(phi).all():
+                raise VclbError(VCLB_ENONFINITE, "phi0 has a NaN/Inf")
+            phis.append(phi)
+            us.append(_as_device_f64(u0, self.device) if u0 is not None else None)
+        n = len(phis)
+        pp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in phis])
+        up = (ctypes.c_void_p * n)(*[t.data_ptr() if t is not None else 0 for t in us])
+        check(lib().vclb_batch_init(self.h, pp, up, DEVICE, _stream_handle(stream)))
+        torch.cuda.current_stream().synchronize()
+        return self
 
     def nodes(self) -> int:
         n = ctypes.c_int64()

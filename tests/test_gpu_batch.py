@@ -187,6 +187,32 @@ def test_batch_autotune_restores_state_and_uses_cache(tmp_path):
     assert len(open(cache).read().strip().splitlines()) == 1
 
 
+def test_batch_init_equals_per_case_init():
+    """vclb_batch_init gives every case the state vclb_case_init gives it, bit for bit."""
+    v = _v()
+    cases = small_batch("fp32", n=5, seed=3)
+    say("case: batch init of", [(p.nx, p.ny, p.wall_y, u0 is not None) for p, _, u0 in cases])
+    one = v.Batch([p for p, _, _ in cases])
+    for c, (p, phi0, u0) in zip(one.cases, cases):
+        c.init(phi0, u0)
+    all_ = v.Batch([p for p, _, _ in cases]).init([(phi0, u0) for _, phi0, u0 in cases])
+    for k in range(len(cases)):
+        assert all_.cases[k].time() == 0
+        for a, b in zip(one.cases[k].get_state(), all_.cases[k].get_state()):
+            assert np.array_equal(a, b), k
+    one.step(5)
+    all_.step(5)
+    for k in range(len(cases)):
+        for a, b in zip(one.cases[k].get_state(), all_.cases[k].get_state()):
+            assert np.array_equal(a, b), k
+    with pytest.raises(v.VclbError):
+        all_.init([(cases[0][1], None)])                     # one pair per case
+    bad = cases[1][1].copy()
+    bad.flat[7] = np.nan
+    with pytest.raises(v.VclbError):
+        all_.init([(phi0, u0) if k != 1 else (bad, u0) for k, (_, phi0, u0) in enumerate(cases)])
+
+
 @pytest.mark.parametrize("storage,flat_pct,bx", [("fp64", 101, 64), ("fp16s", 0, 256), ("fp32", 100, 512)])
 def test_batch_balance_restores_state_and_keeps_results(storage, flat_pct, bx):
     """Slot balancing times launches on the state and restores it; stepping with the re-cut
