@@ -294,6 +294,10 @@ def main(argv=None):
             f"{r['achieved_GBs']:.0f} GB/s ({100 * r['frac']:.1f}% of HBM peak), drift {r['max_rel_volume_drift']:.2e}")
     head = "fp32" if "fp32" in res else storages[0]
     h = res[head]
+    from paper_2505_10899_amd import vclb
+    probe = {m: round(vclb.bandwidth_probe(m), 1) for m in ("copy", "read", "write")}
+    log(f"bandwidth probe (2 GiB, 10 launches): copy {probe['copy']:.0f} GB/s (read + write), "
+        f"read {probe['read']:.0f}, write {probe['write']:.0f}")
     traffic = recorded_traffic(head)
     out = {
         "metric": METRIC, "value": round(h["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
@@ -306,7 +310,10 @@ def main(argv=None):
                      "unit": "GB/s", "frac": round(h["frac"], 4), "traffic": traffic,
                      "kernel": KERNEL[head], "bytes_per_node": h["bytes_per_node"],
                      "bytes_per_launch": h["bytes_per_node"] * h["nodes"],
-                     "launch_ms": round(h["launch_ms"], 5)},
+                     "launch_ms": round(h["launch_ms"], 5),
+                     "achievable_copy_GBs": probe["copy"],
+                     "frac_of_copy": round(h["achieved_GBs"] / probe["copy"], 4)},
+        "bandwidth_probe_GBs": probe,
         "variants": {st: {"MLUPS": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                           "launch_ms": round(v["launch_ms"], 5), "achieved_GBs": round(v["achieved_GBs"], 1),
                           "frac_hbm_peak": round(v["frac"], 4), "bytes_per_node": v["bytes_per_node"],

@@ -130,6 +130,18 @@ const char* vclb_last_error(void);
 /* Library version as MAJOR * 10000 + MINOR * 100 + PATCH. */
 int vclb_version(void);
 
+/* Achievable HBM bandwidth on this device: the practical ceiling that the step kernels'
+   rates are compared with (the kernels move their populations at HBM speed; the method
+   itself fixes no bandwidth).  Runs one warm-up and then `reps` launches (1..1000) of a
+   plain grid-stride kernel over 16-byte vectors, timed with events on `stream` (which it
+   synchronises), and stores bytes moved per second, in GB/s, in *gbs.  mode 0 copies
+   `bytes` from src to dst (counts 2 * bytes per launch), 1 reads src (dst: a device sink
+   of at least 4 bytes, left untouched in practice), 2 fills dst (src unused, may be
+   NULL).  bytes: a positive multiple of 16; buffers: device memory, 16-byte aligned,
+   owned by the caller.  blocks: workgroups of 256 lanes (0: 4 per compute unit). */
+int vclb_bandwidth_probe(int32_t mode, void* dst, const void* src, size_t bytes, int32_t reps, int32_t blocks,
+                         double* gbs, void* stream);
+
 /* Check parameters without any HIP call.  Fills the defaults of zero rates. */
 int vclb_params_validate(const vclb_params* p);
 

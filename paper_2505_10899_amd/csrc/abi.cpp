@@ -371,6 +371,42 @@ const char* vclb_last_error(void) { return g_last_error.c_str(); }
 
 int vclb_version(void) { return 10000; }
 
+int vclb_bandwidth_probe(int32_t mode, void* dst, const void* src, size_t bytes, int32_t reps, int32_t blocks,
+                         double* gbs, void* stream) {
+  if (mode < 0 || mode > 2) return fail(VCLB_EINVAL, "mode is 0 (copy), 1 (read) or 2 (write)");
+  if (!gbs || reps < 1 || reps > 1000 || blocks < 0) return fail(VCLB_EINVAL, "bad probe arguments");
+  if (bytes == 0 || bytes % 16 != 0) return fail(VCLB_EINVAL, "bytes must be a positive multiple of 16");
+  if (!dst || (mode != 2 && !src)) return fail(VCLB_EINVAL, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(dst) % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 != 0)
+    return fail(VCLB_EINVAL, "buffers must be 16-byte aligned");
+  hipStream_t s = as_stream(stream);
+  if (blocks == 0) {
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    blocks = 4 * ncu;
+  }
+  const long n16 = long(bytes / 16);
+  if (vclb::launch_probe(mode, dst, src, n16, blocks, s)) return fail(VCLB_EHIP, "probe launch failed");   // warm-up
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = VCLB_OK;
+  hipError_t e = hipEventRecord(e0, s);
+  for (int r = 0; e == hipSuccess && rc == VCLB_OK && r < reps; ++r) rc = vclb::launch_probe(mode, dst, src, n16, blocks, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return fail(VCLB_EHIP, "probe launch failed");
+  if (e != hipSuccess) return hip_fail(e, "probe timing");
+  const double moved = double(bytes) * (mode == 0 ? 2.0 : 1.0) * reps;
+  *gbs = ms > 0.0f ? moved / (double(ms) * 1e-3) / 1e9 : 0.0;
+  return VCLB_OK;
+}
+
 int vclb_params_validate(const vclb_params* p) { return validate(p); }
 
 int vclb_case_workspace_bytes(const vclb_params* p, size_t* bytes) {

@@ -89,6 +89,8 @@ _SIGS = [
     ("vclb_batch_destroy", None, [ctypes.c_void_p]),
     ("vclb_batch_case", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_void_p)]),
     ("vclb_batch_nodes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64)]),
+    ("vclb_bandwidth_probe", ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                             ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double), ctypes.c_void_p]),
     ("vclb_batch_init", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_void_p), _P(ctypes.c_void_p), ctypes.c_int,
                                         ctypes.c_void_p]),
     ("vclb_batch_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
@@ -390,6 +392,22 @@ def _as_device_f64(a, device):
     if isinstance(a, torch.Tensor):
         return a.detach().to(device=device, dtype=torch.float64).contiguous().reshape(-1)
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to(device)
+
+
+def bandwidth_probe(mode: str = "copy", nbytes: int = 2 << 30, reps: int = 10, blocks: int = 0,
+                    device="cuda", stream=None) -> float:
+    """Achievable HBM bandwidth in GB/s (vclb_bandwidth_probe) over fresh buffers of
+    nbytes: "copy" (read + write counted), "read" or "write"."""
+    m = {"copy": 0, "read": 1, "write": 2}[mode]
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device=device) if m != 2 else None
+    dst = torch.empty(n if m != 1 else 4, dtype=torch.float32, device=device)
+    g = ctypes.c_double(0.0)
+    check(lib().vclb_bandwidth_probe(m, ctypes.c_void_p(dst.data_ptr()),
+                                     ctypes.c_void_p(src.data_ptr() if src is not None else 0),
+                                     ctypes.c_size_t(n * 4), int(reps), int(blocks), ctypes.byref(g),
+                                     _stream_handle(stream)))
+    return g.value
 
 
 def obs_derived(arr, nlabels: int) -> np.ndarray:

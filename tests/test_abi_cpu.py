@@ -175,3 +175,20 @@ def test_batch_entry_points_reject_null_without_gpu():
     assert L.vclb_batch_balance(None, 1, 1, None, None) == v.VCLB_EINVAL
     assert L.vclb_batch_init(None, None, None, v.HOST, None) == v.VCLB_EINVAL
     assert L.vclb_batch_set_reduce_every(None, 1) == v.VCLB_EINVAL
+
+
+def test_bandwidth_probe_validates_before_any_hip_call():
+    v = _vclb()
+    L = v.lib()
+    g = ctypes.c_double(0.0)
+    buf = (ctypes.c_double * 8)()                       # host memory: never reached
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.vclb_bandwidth_probe(3, p, p, 64, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL   # mode
+    assert L.vclb_bandwidth_probe(0, p, p, 64, 1, 0, None, None) == v.VCLB_EINVAL             # no result
+    assert L.vclb_bandwidth_probe(0, p, p, 0, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL   # no bytes
+    assert L.vclb_bandwidth_probe(0, p, p, 40, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL  # not 16 B
+    assert L.vclb_bandwidth_probe(0, p, p, 64, 0, 0, ctypes.byref(g), None) == v.VCLB_EINVAL  # reps
+    assert L.vclb_bandwidth_probe(0, None, p, 64, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL
+    assert L.vclb_bandwidth_probe(1, p, None, 64, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL
+    odd = ctypes.c_void_p(p.value + 4)
+    assert L.vclb_bandwidth_probe(0, odd, p, 48, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL  # alignment
