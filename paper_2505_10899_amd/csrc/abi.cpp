@@ -16,6 +16,7 @@
 #include "../../include/vclb.h"
 #include "adjoint.hpp"
 #include "launch.hpp"
+#include "probe.hpp"
 
 namespace {
 

@@ -67,10 +67,6 @@ int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s);
 template <class St>
 int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit);
 
-// bandwidth probe: mode 0 copies n16 16-byte vectors src -> dst, 1 reads src (dst: a
-// 4-byte sink), 2 writes dst
-int launch_probe(int mode, void* dst, const void* src, long n16, int blocks, hipStream_t s);
-
 // Lag (in chunks of B lanes) of the flattened batched march for rows of padded pitch
 // P = nx + 2: 1 or 3 (the register FIFO holds lag + 1 chunks), 0 if the rows are too
 // wide for B lanes.

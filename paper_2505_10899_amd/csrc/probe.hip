@@ -3,7 +3,7 @@
 // measures on the same device is the practical ceiling their rates are compared with.
 #include <hip/hip_runtime.h>
 
-#include "launch.hpp"
+#include "probe.hpp"
 
 namespace vclb {
 

@@ -1,0 +1,11 @@
+// Host-side launcher of the achievable-bandwidth probe (implemented in probe.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace vclb {
+
+// mode 0 copies n16 16-byte vectors src -> dst, 1 reads src (dst: a 4-byte sink), 2 fills
+// dst; `blocks` workgroups of 256 lanes
+int launch_probe(int mode, void* dst, const void* src, long n16, int blocks, hipStream_t s);
+
+}  // namespace vclb
