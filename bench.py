@@ -258,7 +258,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storages", default="fp32,fp16s,fp64")
     ap.add_argument("--launch-steps", type=int, default=50)
-    ap.add_argument("--tune-steps", type=int, default=5)
+    ap.add_argument("--tune-steps", type=int, default=10)
     ap.add_argument("--batch-tile", default="",
                     help="storage=bx,ty,flat_pct[;...]: fixed batched launch shapes instead of autotuning")
     ap.add_argument("--no-adjoint", action="store_true")

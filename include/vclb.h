@@ -304,7 +304,8 @@ int vclb_batch_init(vclb_batch* b, const double* const* phi0s, const double* con
 /* Total nodes of all cases. */
 int vclb_batch_nodes(const vclb_batch* b, int64_t* nodes);
 
-/* Launch shape of the batched step: bx in {64, 128, 256, 512} lanes per workgroup, and work
+/* Launch shape of the batched step: bx in {64, 128, 256, 512} lanes per workgroup (also
+   1024 with FP32 or FP16S storage; VCLB_EINVAL for FP64), and work
    items of at most about ty * 256 nodes (ty in 1..1024; 1024 keeps cases up to 512 x 512
    whole).  As many workgroups as can be resident are launched, each given one run of
    consecutive items with about equal work, or work in proportion to the slot weights
@@ -345,8 +346,8 @@ int vclb_batch_history(vclb_batch* b, int64_t t_first, int32_t count, vclb_obs* 
 int vclb_batch_step(vclb_batch* b, int64_t nsteps, int32_t use_graph, void* stream);
 
 /* Pick the batched tile and schedule (bx, ty, flat_pct) by timing `steps` steps of every
-   candidate on the current state (saved and restored), then the four fastest twice more
-   with 2 * steps steps each, in alternation, keeping each one's best time (the leading
+   candidate on the current state (saved and restored), then the four fastest three times
+   more with 2 * steps steps each, in alternation, keeping each one's best time (the leading
    shapes often lie within timing noise of each other); or take them from the JSON-lines
    file cache_path when that holds an entry for this batch; a measured choice is appended
    to cache_path (NULL: no file). */

@@ -1131,8 +1131,10 @@ void partition_runs(const vclb_batch* b, int bx, int lag, int nb, const std::vec
 }
 
 int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
-  if (!(bx == 64 || bx == 128 || bx == 256 || bx == 512) || ty < 1 || ty > 1024 || flat_pct < 0 || flat_pct > 101)
-    return fail(VCLB_EINVAL, "bad batch launch shape (bx in {64, 128, 256, 512}; ty in 1..1024; flat_pct in 0..101)");
+  if (!(bx == 64 || bx == 128 || bx == 256 || bx == 512 || bx == 1024) || ty < 1 || ty > 1024 || flat_pct < 0 ||
+      flat_pct > 101)
+    return fail(VCLB_EINVAL, "bad batch launch shape (bx in {64, 128, 256, 512, 1024}; ty in 1..1024; flat_pct in 0..101)");
+  if (bx == 1024 && b->storage == VCLB_FP64) return fail(VCLB_EINVAL, "1024-lane workgroups need FP32 or FP16S storage");
   int pmax = 1, lag = 1;
   for (const vclb_case* c : b->cases) {
     if (!batch_case_flat(c->p, bx, flat_pct)) continue;
@@ -1693,7 +1695,7 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   struct Cand { int bx, ty, fp; float ms; };
   std::vector<Cand> cands;
   for (int fp : {0, 90, 100, 101})
-    for (int bx : {64, 128, 256, 512})
+    for (int bx : {64, 128, 256, 512, 1024})
       for (int ty : {8, 16, 32, 64, 1024}) cands.push_back({bx, ty, fp, -1.0f});
   int rc = VCLB_OK;
   // one warm-up step, then `n` timed steps of the current shape: ms per step
@@ -1715,13 +1717,13 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
     if ((rc = time_shape(steps, cd.ms))) break;
   }
   // the leading shapes are often within timing noise of each other: time the best four
-  // again, twice each in alternation with twice the steps, and keep each one's fastest
+  // again, three times each in alternation with twice the steps, and keep each one's fastest
   std::vector<size_t> order;
   for (size_t i = 0; i < cands.size(); ++i)
     if (cands[i].ms > 0) order.push_back(i);
   std::sort(order.begin(), order.end(), [&](size_t a, size_t c) { return cands[a].ms < cands[c].ms; });
   if (order.size() > 4) order.resize(4);
-  for (int pass = 0; rc == VCLB_OK && order.size() > 1 && pass < 2; ++pass)
+  for (int pass = 0; rc == VCLB_OK && order.size() > 1 && pass < 3; ++pass)
     for (size_t i : order) {
       Cand& cd = cands[i];
       if ((rc = batch_set_tile(b, cd.bx, cd.ty, cd.fp))) break;

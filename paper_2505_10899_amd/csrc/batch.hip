@@ -43,7 +43,8 @@ __device__ __forceinline__ void fold_case(const DevCase<D2Q9, St>& c, const Batc
 
 // Workgroups per CU the register budget is sized for: FP32 arithmetic fits 4 waves per
 // SIMD, except the lag-3 FIFO with general rates (a little more than 128 VGPRs: 3); FP64
-// fits 2, or 3 for the short lag with unit rates (at most 168 VGPRs).
+// fits 2, or 3 for the short lag with unit rates (at most 168 VGPRs).  A 1024-lane
+// workgroup alone puts 4 waves on each SIMD.
 template <class St, int DL, int BS, bool UNIT>
 constexpr int batch_min_blocks() {
   constexpr int waves = sizeof(typename St::R) == 8 ? (UNIT && DL == 1 ? 3 : 2) : (DL == 3 && !UNIT ? 3 : 4);
@@ -88,16 +89,21 @@ size_t batch_lds_bytes(int cap, int bx) {
 }
 
 // the kernel instantiation for a launch shape (bx lanes, lag, unit rates); fn receives a
-// pointer to it
+// pointer to it.  1024-lane workgroups (4 waves per SIMD in one workgroup per CU) exist
+// for 4-byte arithmetic only: FP64 needs more than the 128 registers they leave a lane.
 template <class St, class Fn>
 int with_batch_kernel(int bx, int lag, bool unit, Fn&& fn) {
   if (lag != 1 && lag != 3) return -1;
-  auto pick = [&](auto big) -> int {
-    constexpr int BS = decltype(big)::value ? 512 : 256;
+  auto pick = [&](auto bs) -> int {
+    constexpr int BS = decltype(bs)::value;
     if (lag == 1) return unit ? fn(k_batch_step2d<St, 1, BS, true>) : fn(k_batch_step2d<St, 1, BS, false>);
     return unit ? fn(k_batch_step2d<St, 3, BS, true>) : fn(k_batch_step2d<St, 3, BS, false>);
   };
-  return bx <= 256 ? pick(std::false_type{}) : pick(std::true_type{});
+  if (bx > 512) {
+    if constexpr (sizeof(typename St::R) == 4) return pick(std::integral_constant<int, 1024>{});
+    else return -1;
+  }
+  return bx <= 256 ? pick(std::integral_constant<int, 256>{}) : pick(std::integral_constant<int, 512>{});
 }
 
 template <class St>

@@ -33,9 +33,10 @@ def small_batch(storage="fp64", n=6, seed=7):
 
 @pytest.mark.parametrize("storage,flat_pct,bx", [("fp64", 0, 64), ("fp64", 90, 64), ("fp64", 101, 64),
                                                  ("fp16s", 90, 64), ("fp32", 101, 64), ("fp64", 100, 512),
-                                                 ("fp32", 0, 512)])
+                                                 ("fp32", 0, 512), ("fp32", 101, 1024), ("fp16s", 0, 1024)])
 def test_batch_matches_cases_run_alone(storage, flat_pct, bx):
-    """Column strips (flat_pct 0), flattened bands (101), the mixes (90, 100), 64 and 512 lanes."""
+    """Column strips (flat_pct 0), flattened bands (101), the mixes (90, 100), 64, 512 and
+    1024 lanes."""
     v = _v()
     cases = small_batch(storage)
     say("case: batch of", [(p.nx, p.ny, p.wall_y) for p, _, _ in cases], storage, "flat_pct", flat_pct, "bx", bx)
@@ -187,6 +188,14 @@ def test_batch_autotune_restores_state_and_uses_cache(tmp_path):
     assert len(open(cache).read().strip().splitlines()) == 1
 
 
+def test_batch_rejects_1024_lanes_in_fp64():
+    v = _v()
+    b = v.Batch([p for p, _, _ in small_batch("fp64", n=2)])
+    with pytest.raises(v.VclbError):
+        b.set_tile(1024, 16)
+    assert b.tile()[0] == 512                              # the shape in force is kept
+
+
 def test_batch_init_equals_per_case_init():
     """vclb_batch_init gives every case the state vclb_case_init gives it, bit for bit."""
     v = _v()
@@ -265,33 +274,33 @@ def _sample(cases):
     return sorted(idx)
 
 
-# the launch configurations the benchmark's autotuner chooses between on this batch
-# (their times lie within noise of each other): 512-lane workgroups, whole-case items
-# (ty 1024) or items of about 16k nodes (ty 64), and bands for the cases that fit the
-# two-slot FIFO with strips for the wider ones (flat_pct 100) or bands for every case
-# (101, the four-slot FIFO kernel)
-FULL_SHAPES = [(1024, 100), (1024, 101), (64, 100)]
+# the launch configurations the benchmark's autotuner chooses between on this batch:
+# 512-lane workgroups with whole-case items (ty 1024) or items of about 16k nodes (ty 64),
+# with bands for the cases that fit the two-slot FIFO and strips for the wider ones
+# (flat_pct 100) or bands for every case (101, the four-slot FIFO kernel); and 1024-lane
+# workgroups (FP32, FP16S), which put every case in bands with the two-slot FIFO
+FULL_SHAPES = [(512, 1024, 100), (512, 1024, 101), (512, 64, 100), (1024, 1024, 101)]
 
 
-def _full_batch(v, storage, ty, flat_pct):
+def _full_batch(v, storage, bx, ty, flat_pct):
     cases, _ = W.batch_cases(512, storage=storage)
     b = v.Batch([p for p, _, _ in cases])
-    b.set_tile(512, ty)
+    b.set_tile(bx, ty)
     b.set_schedule(flat_pct)
     return cases, b
 
 
-@pytest.mark.parametrize("ty,flat_pct", FULL_SHAPES[:2])
-def test_full_batch_fp64_sampled_cases_match_oracle(ty, flat_pct):
+@pytest.mark.parametrize("bx,ty,flat_pct", FULL_SHAPES[:2])
+def test_full_batch_fp64_sampled_cases_match_oracle(bx, ty, flat_pct):
     """All 512 cases (24.4 M nodes) in the benchmark's launch configuration; sampled cases
     start from the oracle's exact state and, after one batched step, match the oracle's
     step node by node within the rounding bound of the one-step parity tests."""
     v = _v()
     from oracle.model import Model
     from test_gpu_parity import normal_conditioning
-    cases, b = _full_batch(v, "fp64", ty, flat_pct)
+    cases, b = _full_batch(v, "fp64", bx, ty, flat_pct)
     idx = _sample(cases)
-    say(f"case: full batch fp64, ty {ty}, flat_pct {flat_pct}, sampled cases", [(k, cases[k][0].nx, cases[k][0].ny, cases[k][0].wall_y) for k in idx])
+    say(f"case: full batch fp64, bx {bx}, ty {ty}, flat_pct {flat_pct}, sampled cases", [(k, cases[k][0].nx, cases[k][0].ny, cases[k][0].wall_y) for k in idx])
     models = {}
     for k, (c, (p, phi0, u0)) in enumerate(zip(b.cases, cases)):
         if k in idx:
@@ -318,9 +327,9 @@ def test_full_batch_fp64_sampled_cases_match_oracle(ty, flat_pct):
 REDUCED = {"fp32": (6e-8, 1e-6, 1e-6, 1e-6, 1e-6), "fp16s": (4.9e-4, 5e-5, 1e-4, 5e-5, 1e-4)}
 
 
-@pytest.mark.parametrize("ty,flat_pct", FULL_SHAPES)
+@pytest.mark.parametrize("bx,ty,flat_pct", FULL_SHAPES)
 @pytest.mark.parametrize("storage", ["fp32", "fp16s"])
-def test_full_batch_reduced_precision_volume_and_sampled_fields(storage, ty, flat_pct):
+def test_full_batch_reduced_precision_volume_and_sampled_fields(storage, bx, ty, flat_pct):
     """FP32 and FP16S storage at full size in the benchmark's launch configuration: every
     case keeps its volume (to 1e-6 in FP32, 1e-4 in FP16S) over 20 steps, and sampled
     cases match the FP64 oracle's first step to the storage's rounding (phi, u and the
@@ -329,9 +338,9 @@ def test_full_batch_reduced_precision_volume_and_sampled_fields(storage, ty, fla
     from oracle.model import Model
     from test_gpu_parity import normal_conditioning
     eps, floor, tol_phi, tol_u, tol_drift = REDUCED[storage]
-    cases, b = _full_batch(v, storage, ty, flat_pct)
+    cases, b = _full_batch(v, storage, bx, ty, flat_pct)
     idx = _sample(cases)
-    say(f"case: full batch {storage}, ty {ty}, flat_pct {flat_pct}, sampled cases", idx)
+    say(f"case: full batch {storage}, bx {bx}, ty {ty}, flat_pct {flat_pct}, sampled cases", idx)
     for c, (p, phi0, u0) in zip(b.cases, cases):
         c.init(phi0, u0)
     say(f"  slot balancing (as the benchmark does): gain {b.balance(rounds=3, steps=3):.3f}")
