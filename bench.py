@@ -76,9 +76,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(storage: str):
+def recorded_traffic(storage: str, bx: int):
     """HBM bytes per launch of the batched step from the committed rocprofv3 counter
-    summary, if it was taken on the current sources; else None."""
+    summary, if it was taken on the current sources and on the kernel instantiation that a
+    bx-lane tile launches (workgroups of 256, 512 or 1024 lanes); else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -87,6 +88,11 @@ def recorded_traffic(storage: str):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("source_hash") != source_hash():
+        return None
+    lanes = 1024 if bx > 512 else (512 if bx > 256 else 256)
+    kernel = kv.get(f"kernel_{storage}", "")
+    args = kernel[kernel.find("<") + 1:kernel.rfind(">")].split(",")
+    if len(args) < 3 or args[2].strip() != str(lanes):
         return None
     v = kv.get(f"traffic_bytes_per_launch_{storage}")
     return float(v) if v else None
@@ -298,7 +304,7 @@ def main(argv=None):
     probe = {m: round(vclb.bandwidth_probe(m), 1) for m in ("copy", "read", "write")}
     log(f"bandwidth probe (2 GiB, 10 launches): copy {probe['copy']:.0f} GB/s (read + write), "
         f"read {probe['read']:.0f}, write {probe['write']:.0f}")
-    traffic = recorded_traffic(head)
+    traffic = recorded_traffic(head, h["tile"][0])
     out = {
         "metric": METRIC, "value": round(h["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(h["ms_per_step"], 4),
