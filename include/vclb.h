@@ -159,7 +159,8 @@ int vclb_case_create(const vclb_params* p, void* workspace, size_t workspace_byt
 void vclb_case_destroy(vclb_case* c);
 
 /* Tile of the fused step kernel.  D2Q9: bx lanes (x columns; a multiple of 64 in
-   64..256) marching ty >= 1 rows of y (by3 ignored).  D3Q19: a bx x by3 section of (x, y)
+   64..256, or 512 or 1024 with FP32 or FP16S storage) marching ty >= 1 rows of y (by3
+   ignored).  D3Q19: a bx x by3 section of (x, y)
    columns (bx * by3 a multiple of 64, at most 256) marching the planes of z, which
    ceil(nz / ty) workgroups per section share evenly.  Returns EINVAL for shapes outside
    these limits. */
@@ -170,8 +171,8 @@ int vclb_case_get_tile(const vclb_case* c, int32_t* bx, int32_t* ty, int32_t* by
    current state (saved and restored, as are the step counter and the recorded history),
    or take it from the JSON-lines file cache_path when that holds an entry for this case's
    lattice, storage, mode, shape, boundary and label count; a measured choice is appended
-   to cache_path (NULL: no file).  D2Q9 candidates: bx in {64, 128, 256} x ty in
-   {8, ..., 128}; D3Q19: six column sections with their planes cut to fill 1..4
+   to cache_path (NULL: no file).  D2Q9 candidates: bx in {64, 128, 256} (and 512, 1024
+   with 4-byte storage) x ty in {8, ..., 128}; D3Q19: six column sections with their planes cut to fill 1..4
    workgroups per CU.  Synchronises the stream; VCLB_ESTATE before init. */
 int vclb_case_autotune(vclb_case* c, const char* cache_path, int32_t steps, void* stream);
 

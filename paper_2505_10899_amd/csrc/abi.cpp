@@ -310,13 +310,14 @@ int flush_pending(vclb_case* c, hipStream_t s) {
 vclb::Tile default_tile(const vclb_params& p, int ncu) {
   vclb::Tile t;
   if (p.lattice == VCLB_D2Q9) {
-    // one lane per x column, rounded up to whole waves, at most 256
-    int bx = std::min(256, (p.nx + 63) / 64 * 64);
+    // one lane per x column, rounded up to whole waves, at most 256 lanes, or 512 with
+    // 4-byte arithmetic (measured 2.6% faster in FP32 and 7% in FP16S on 4096 columns)
+    int bx = std::min(p.storage == VCLB_FP64 ? 256 : 512, (p.nx + 63) / 64 * 64);
     t.bx = bx;
     const long strips = (p.nx + bx - 1) / bx;
-    // long marches amortise the two halo rows; keep >= 1024 workgroups (four per CU)
-    // when the grid allows, with 8..64 rows each
-    long ty = (long(p.ny) * strips) / 1024;
+    // long marches amortise the two halo rows; keep 4 waves per SIMD resident when the
+    // grid allows (1024 workgroups of up to 256 lanes, 512 of 512), with 8..64 rows each
+    long ty = (long(p.ny) * strips) / (bx > 256 ? 512 : 1024);
     t.ty = int(std::max(8L, std::min(64L, ty)));
     t.by3 = 1;
   } else {
@@ -338,7 +339,9 @@ vclb::Tile default_tile(const vclb_params& p, int ncu) {
 
 int check_tile(const vclb_params& p, const vclb::Tile& t) {
   if (p.lattice == VCLB_D2Q9) {
-    if (t.bx < 64 || t.bx > 256 || t.bx % 64 != 0 || t.ty < 1) return fail(VCLB_EINVAL, "bad 2D tile");
+    const bool wide = (t.bx == 512 || t.bx == 1024) && p.storage != VCLB_FP64;
+    if (!((t.bx >= 64 && t.bx <= 256 && t.bx % 64 == 0) || wide) || t.ty < 1)
+      return fail(VCLB_EINVAL, "bad 2D tile (bx in {64, 128, 192, 256}, or 512 and 1024 with 4-byte storage)");
   } else {
     if (t.bx < 1 || t.by3 < 1 || t.bx * t.by3 > 256 || (t.bx * t.by3) % 64 != 0 || t.ty < 1)
       return fail(VCLB_EINVAL, "bad 3D tile (bx * by3 must be a multiple of 64, at most 256)");
@@ -681,8 +684,10 @@ int vclb_case_autotune(vclb_case* c, const char* cache_path, int32_t steps, void
   // their z extent cut into as many segments as fill 1..4 workgroups per CU once
   std::vector<vclb::Tile> cands;
   if (p.lattice == VCLB_D2Q9) {
-    for (int bx : {64, 128, 256})
+    for (int bx : {64, 128, 256, 512, 1024}) {
+      if (bx > 256 && c->p.storage == VCLB_FP64) continue;
       for (int ty : {8, 16, 32, 64, 128}) cands.push_back(vclb::Tile{bx, ty, 1});
+    }
   } else {
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)

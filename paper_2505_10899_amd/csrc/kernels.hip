@@ -254,8 +254,17 @@ __global__ void __launch_bounds__(256) k_reduce_state(DevCase<L, St> c) {
 }
 
 // ---------------------------------------------------------------- fused 2D step (A1-A11)
-template <class St, bool COUPLED, class IX, bool UNIT>
-__global__ void __launch_bounds__(256, sizeof(typename St::R) == 8 ? (UNIT ? 3 : 2) : 4)
+// Workgroups per CU the register budget is sized for, for workgroups of up to BS lanes:
+// FP32 arithmetic fits 4 waves per SIMD; FP64 2, or 3 with unit rates.  BS is 256, or 1024
+// for the wide strips of 4-byte arithmetic (4 waves per SIMD in one workgroup).
+template <class St, bool UNIT, int BS>
+constexpr int step2d_min_blocks() {
+  constexpr int waves = sizeof(typename St::R) == 8 ? (UNIT ? 3 : 2) : 4;
+  return waves / (BS / 256) > 0 ? waves / (BS / 256) : 1;
+}
+
+template <class St, bool COUPLED, class IX, bool UNIT, int BS>
+__global__ void __launch_bounds__(BS, (step2d_min_blocks<St, UNIT, BS>()))
     k_step2d(DevCase<D2Q9, St> c, int TY, int nseg, int reduce) {
   extern __shared__ unsigned char smem_raw[];
   if (blockIdx.x == 0 && c.pend_nb > 0) fold_pending(c);
@@ -321,9 +330,19 @@ int launch_step_fused(const DevCase<L, St>& c, const Tile& tile, int reduce, hip
     // measured 0.6% and 2.6% faster with 64-bit indexing.  The unit-rate update when the
     // case's rates allow it.
     const dim3 grid(nstrips * nseg), block(tile.bx);
+    // strips wider than 256 lanes (512 or 1024) take the 1024-lane instantiation, which
+    // exists for 4-byte arithmetic only
+    bool bad_shape = false;
     auto go = [&](auto ix, auto unit) {
-      hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), decltype(unit)::value>), grid, block, lds, s, c,
-                         tile.ty, nseg, reduce);
+      if (tile.bx <= 256) {
+        hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), decltype(unit)::value, 256>), grid, block, lds, s, c,
+                           tile.ty, nseg, reduce);
+      } else if constexpr (sizeof(typename St::R) == 4) {
+        hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), decltype(unit)::value, 1024>), grid, block, lds, s, c,
+                           tile.ty, nseg, reduce);
+      } else {
+        bad_shape = true;
+      }
     };
     auto pick = [&](auto ix) {
       if (c.unit_rates) go(ix, std::true_type{});
@@ -335,6 +354,7 @@ int launch_step_fused(const DevCase<L, St>& c, const Tile& tile, int reduce, hip
     } else {
       pick(0L);
     }
+    if (bad_shape) return -1;
     return hipGetLastError() == hipSuccess ? 0 : -3;
   } else {
     return launch_step3d<St>(c, tile, reduce, s);

@@ -243,14 +243,23 @@ def test_plain_path_matches_fused_step(storage):
                 assert err <= tol, (variant, err)
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp16s"])
+@pytest.mark.parametrize("storage", ["fp64", "fp16s", "fp32"])
 def test_tile_shape_does_not_change_the_state(storage):
+    """Every tile gives the same state bit for bit, including strips wider than the case
+    (512 and 1024 lanes over 200 columns, 4-byte storage only)."""
+    v = _v()
     say(f"case: tile invariance, {storage}")
     p, phi0, u0 = _small_case("periodic_ragged")
     p = p.replace(nx=200, ny=45, storage=storage)
     phi0 = W.drops_phi(p, [(60, 20, 0, 12.0), (150, 25, 0, 7.0)])
+    tiles = [(64, 1), (64, 7), (128, 16), (256, 45), (256, 64), (192, 5)]
+    if storage == "fp64":
+        with pytest.raises(v.VclbError):
+            v.Case(p).set_tile(512, 8)
+    else:
+        tiles += [(512, 8), (1024, 45)]
     ref = None
-    for tile in ((64, 1), (64, 7), (128, 16), (256, 45), (256, 64), (192, 5)):
+    for tile in tiles:
         F = run_gpu(p, phi0, u0, 30, tile=tile).observe()
         if ref is None:
             ref = F
