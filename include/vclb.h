@@ -161,9 +161,10 @@ void vclb_case_destroy(vclb_case* c);
 /* Tile of the fused step kernel.  D2Q9: bx lanes (x columns; a multiple of 64 in
    64..256, or 512 or 1024 with FP32 or FP16S storage) marching ty >= 1 rows of y (by3
    ignored).  D3Q19: a bx x by3 section of (x, y)
-   columns (bx * by3 a multiple of 64, at most 256) marching the planes of z, which
-   ceil(nz / ty) workgroups per section share evenly.  Returns EINVAL for shapes outside
-   these limits. */
+   columns (bx * by3 a multiple of 64, at most 256, or at most 768 with FP32 or FP16S
+   storage when the section's LDS fits the device's per-workgroup limit) marching the
+   planes of z, which ceil(nz / ty) workgroups per section share evenly.  Returns EINVAL
+   for shapes outside these limits. */
 int vclb_case_set_tile(vclb_case* c, int32_t bx, int32_t ty, int32_t by3);
 int vclb_case_get_tile(const vclb_case* c, int32_t* bx, int32_t* ty, int32_t* by3);
 
@@ -172,8 +173,9 @@ int vclb_case_get_tile(const vclb_case* c, int32_t* bx, int32_t* ty, int32_t* by
    or take it from the JSON-lines file cache_path when that holds an entry for this case's
    lattice, storage, mode, shape, boundary and label count; a measured choice is appended
    to cache_path (NULL: no file).  D2Q9 candidates: bx in {64, 128, 256} (and 512, 1024
-   with 4-byte storage) x ty in {8, ..., 128}; D3Q19: six column sections with their planes cut to fill 1..4
-   workgroups per CU.  Synchronises the stream; VCLB_ESTATE before init. */
+   with 4-byte storage) x ty in {8, ..., 128}; D3Q19: six column sections with their
+   planes cut to fill 1..4 workgroups per CU, and (4-byte storage) three 768-lane
+   sections at one per CU.  Synchronises the stream; VCLB_ESTATE before init. */
 int vclb_case_autotune(vclb_case* c, const char* cache_path, int32_t steps, void* stream);
 
 /* Initial state from phi0 (N doubles) and u0 (D*N doubles, NULL for u = 0; ignored in

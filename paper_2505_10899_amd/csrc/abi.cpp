@@ -343,12 +343,24 @@ int check_tile(const vclb_params& p, const vclb::Tile& t) {
     if (!((t.bx >= 64 && t.bx <= 256 && t.bx % 64 == 0) || wide) || t.ty < 1)
       return fail(VCLB_EINVAL, "bad 2D tile (bx in {64, 128, 192, 256}, or 512 and 1024 with 4-byte storage)");
   } else {
-    if (t.bx < 1 || t.by3 < 1 || t.bx * t.by3 > 256 || (t.bx * t.by3) % 64 != 0 || t.ty < 1)
-      return fail(VCLB_EINVAL, "bad 3D tile (bx * by3 must be a multiple of 64, at most 256)");
+    // sections of up to 256 lanes, or 768 with 4-byte arithmetic (one workgroup per CU,
+    // whose staged planes may use up to the CU's 160 KiB of LDS)
+    const int max_lanes = p.storage == VCLB_FP64 ? 256 : 768;
+    if (t.bx < 1 || t.by3 < 1 || t.bx * t.by3 > max_lanes || (t.bx * t.by3) % 64 != 0 || t.ty < 1)
+      return fail(VCLB_EINVAL, "bad 3D tile (bx * by3 a multiple of 64, at most 256, or 768 with 4-byte storage)");
     const size_t lds = p.storage == VCLB_FP64   ? vclb::step3d_lds_bytes<vclb::StoreF64>(t.bx, t.by3)
                        : p.storage == VCLB_FP32 ? vclb::step3d_lds_bytes<vclb::StoreF32>(t.bx, t.by3)
                                                 : vclb::step3d_lds_bytes<vclb::StoreF16S>(t.bx, t.by3);
-    if (lds > 65536) return fail(VCLB_EINVAL, "3D tile needs more than 64 KiB of LDS");
+    if (t.bx * t.by3 <= 256) {
+      if (lds > 65536) return fail(VCLB_EINVAL, "3D tile needs more than 64 KiB of LDS");
+    } else {
+      // the device's own limit on one workgroup's LDS (the only HIP query of a tile check)
+      int dev = 0, max_lds = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+          lds > size_t(max_lds))
+        return fail(VCLB_EINVAL, "wide 3D tile needs more LDS than a workgroup may have on this device");
+    }
   }
   return VCLB_OK;
 }
@@ -692,9 +704,10 @@ int vclb_case_autotune(vclb_case* c, const char* cache_path, int32_t steps, void
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       ncu = 256;
-    const int shapes[][2] = {{32, 8}, {64, 4}, {16, 16}, {32, 4}, {64, 2}, {16, 8}};
+    const int shapes[][2] = {{32, 8}, {64, 4}, {16, 16}, {32, 4}, {64, 2}, {16, 8}, {96, 8}, {48, 16}, {64, 12}};
     for (const auto& sh : shapes)
       for (int per_cu : {1, 2, 3, 4}) {
+        if (sh[0] * sh[1] > 256 && (p.storage == VCLB_FP64 || per_cu > 1)) continue;   // wide: one per CU
         const long cols = long((p.nx + sh[0] - 1) / sh[0]) * ((p.ny + sh[1] - 1) / sh[1]);
         const long segs = std::max(1L, per_cu * long(ncu) / cols);
         const int ty = int(std::max(1L, (p.nz + segs - 1) / segs));

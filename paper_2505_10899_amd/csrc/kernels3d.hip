@@ -66,16 +66,18 @@ template <class St>
 constexpr bool stage3d() {
   return sizeof(typename St::R) == 4;
 }
-template <class St>
+// Sections of up to BS lanes: 256, or 768 with 4-byte arithmetic (one workgroup putting
+// 3 waves on each SIMD, the same register budget as three of 256).
+template <class St, int BS>
 constexpr int step3d_min_blocks() {
-  return stage3d<St>() ? 3 : 2;
+  return BS > 256 ? 1 : (stage3d<St>() ? 3 : 2);
 }
 
 // NL: labels of the volume reductions (1 or 2), fixed per case; UNIT: the case's rates
 // outside the g flux and f stress rows are all 1
-template <class St, int NL, bool UNIT, class IX>
-__global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCase<D3Q19, St> c, int BX, int BY,
-                                                                        int nby, int nbz, int reduce) {
+template <class St, int NL, bool UNIT, class IX, int BS>
+__global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(DevCase<D3Q19, St> c, int BX, int BY,
+                                                                            int nby, int nbz, int reduce) {
   using L = D3Q19;
   using R = typename St::R;
   constexpr int Q = L::Q;
@@ -269,6 +271,11 @@ __global__ void __launch_bounds__(256, (step3d_min_blocks<St>())) k_step3d(DevCa
 }
 
 template <class St>
+int step3d_max_lanes() {
+  return stage3d<St>() ? 768 : 256;
+}
+
+template <class St>
 size_t step3d_lds_bytes(int bx, int by3) {
   const size_t ring = size_t(2) * 4 * (bx + 2) * (by3 + 2) * sizeof(typename St::R);
   const size_t stage = stage3d<St>() ? size_t(2) * D3Q19::Q * bx * by3 * sizeof(typename St::R) : 0;
@@ -280,12 +287,25 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   const int nbx = (c.nx + tile.bx - 1) / tile.bx;
   const int nby = (c.ny + tile.by3 - 1) / tile.by3;
   const int nbz = (c.nz + tile.ty - 1) / tile.ty;
-  if (tile.bx * tile.by3 > 256) return -1;
+  const int lanes = tile.bx * tile.by3;
+  if (lanes > step3d_max_lanes<St>()) return -1;
   const size_t lds = step3d_lds_bytes<St>(tile.bx, tile.by3);
-  const dim3 grid(nbx * nby * nbz), block(tile.bx * tile.by3);
+  const dim3 grid(nbx * nby * nbz), block(lanes);
+  int rc = 0;
   auto go = [&](auto nl, auto unit, auto ix) {
-    hipLaunchKernelGGL((k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix)>), grid, block, lds, s,
-                       c, tile.bx, tile.by3, nby, nbz, reduce);
+    if (lanes <= 256) {
+      hipLaunchKernelGGL((k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 256>), grid, block,
+                         lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
+    } else if constexpr (stage3d<St>()) {
+      // wide sections stage more than the default 64 KiB of dynamic LDS
+      auto kern = k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 768>;
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(lds)) != hipSuccess) {
+        rc = -3;
+        return;
+      }
+      hipLaunchKernelGGL(kern, grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
+    }
   };
   using One = std::integral_constant<int, 1>;
   using Two = std::integral_constant<int, 2>;
@@ -298,6 +318,7 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   };
   if (c.nl > 1) pick_unit(Two{});
   else pick_unit(One{});
+  if (rc) return rc;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
