@@ -297,12 +297,24 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
       hipLaunchKernelGGL((k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 256>), grid, block,
                          lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
     } else if constexpr (stage3d<St>()) {
-      // wide sections stage more than the default 64 KiB of dynamic LDS
+      // wide sections stage more than the default 64 KiB of dynamic LDS: raise this
+      // instantiation's limit to the device maximum once per device (the tile check has
+      // compared the section with that maximum)
       auto kern = k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 768>;
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(lds)) != hipSuccess) {
+      static int raised[64] = {};   // per instantiation and device; a repeated raise is harmless
+      int dev = 0, max_lds = 0;
+      if (hipGetDevice(&dev) != hipSuccess) {
         rc = -3;
         return;
+      }
+      if (dev >= 64 || !raised[dev]) {
+        if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                max_lds) != hipSuccess) {
+          rc = -3;
+          return;
+        }
+        if (dev < 64) raised[dev] = 1;
       }
       hipLaunchKernelGGL(kern, grid, block, lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
     }
