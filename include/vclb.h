@@ -372,6 +372,18 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
    autotune, drop them. */
 int vclb_batch_balance(vclb_batch* b, int32_t rounds, int32_t steps, double* gain, void* stream);
 
+/* The slot weights in force (1 for every slot when none are): weights[r] for run slot
+   r < min(capacity, *count), where *count receives the number of slots of the current
+   launch shape (host memory).  With vclb_batch_set_weights, a calibration measured once
+   by vclb_batch_balance can be kept and applied again later on the same device and
+   launch shape without timing anything. */
+int vclb_batch_get_weights(const vclb_batch* b, double* weights, int32_t capacity, int32_t* count);
+/* Set the slot weights (count = the slot count of the current launch shape, each in
+   [1e-3, 1e3], rescaled to mean 1; count 0 clears them) and re-cut the runs.  They stay
+   in force on the same terms as balanced ones.  Results of a step do not depend on the
+   weights. */
+int vclb_batch_set_weights(vclb_batch* b, const double* weights, int32_t count);
+
 #ifdef __cplusplus
 }
 #endif

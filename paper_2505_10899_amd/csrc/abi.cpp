@@ -1665,6 +1665,32 @@ int vclb_batch_balance(vclb_batch* b, int32_t rounds, int32_t steps, double* gai
   return VCLB_OK;
 }
 
+int vclb_batch_get_weights(const vclb_batch* b, double* weights, int32_t capacity, int32_t* count) {
+  if (!b || !count || capacity < 0 || (capacity > 0 && !weights)) return fail(VCLB_EINVAL, "bad arguments");
+  *count = b->blocks;
+  for (int r = 0; r < std::min(capacity, b->blocks); ++r)
+    weights[r] = b->weight.empty() ? 1.0 : b->weight[size_t(r)];
+  return VCLB_OK;
+}
+
+int vclb_batch_set_weights(vclb_batch* b, const double* weights, int32_t count) {
+  if (!b || count < 0 || (count > 0 && !weights)) return fail(VCLB_EINVAL, "bad arguments");
+  if (count != 0 && count != b->blocks) return fail(VCLB_EINVAL, "one weight per run slot (see vclb_batch_get_tile)");
+  for (int r = 0; r < count; ++r)
+    if (!(weights[r] >= 1e-3 && weights[r] <= 1e3)) return fail(VCLB_EINVAL, "weights must lie in [1e-3, 1e3]");
+  batch_release_graph(b);
+  b->weight.assign(weights, weights + count);
+  if (count) {
+    double sum = 0.0;
+    for (double w : b->weight) sum += w;
+    for (double& w : b->weight) w *= count / sum;   // mean 1
+  }
+  b->wbx = b->bx;
+  b->wty = b->ty;
+  b->wfp = b->flat_pct;
+  return batch_set_tile(b, b->bx, b->ty, b->flat_pct);
+}
+
 int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, void* stream) {
   if (!b || steps < 1) return fail(VCLB_EINVAL, "bad autotune arguments");
   for (vclb_case* c : b->cases)

@@ -105,6 +105,9 @@ _SIGS = [
     ("vclb_batch_autotune", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int32, ctypes.c_void_p]),
     ("vclb_batch_balance", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double),
                                            ctypes.c_void_p]),
+    ("vclb_batch_get_weights", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_int32,
+                                               _P(ctypes.c_int32)]),
+    ("vclb_batch_set_weights", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_double), ctypes.c_int32]),
     ("vclb_state_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("vclb_state_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     ("vclb_obs_derived", ctypes.c_int, [_P(Obs), ctypes.c_int32, _P(ctypes.c_double)]),
@@ -574,6 +577,21 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         check(lib().vclb_batch_autotune(self.h, path, int(steps), _stream_handle(stream)))
         return self.tile()
+
+    def weights(self) -> np.ndarray:
+        """Slot weights in force (ones when none are)."""
+        n = ctypes.c_int32(0)
+        check(lib().vclb_batch_get_weights(self.h, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_double * max(1, n.value))()
+        check(lib().vclb_batch_get_weights(self.h, buf, n.value, ctypes.byref(n)))
+        return np.array(buf[:n.value])
+
+    def set_weights(self, w):
+        """Apply slot weights (one per slot of the current launch shape; empty clears)."""
+        a = np.ascontiguousarray(w, dtype=np.float64)
+        check(lib().vclb_batch_set_weights(self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a.size else None,
+                                           int(a.size)))
+        return self
 
     def balance(self, rounds: int = 3, steps: int = 3, stream=None) -> float:
         """Re-cut the runs to the measured speed of each workgroup slot (state restored);

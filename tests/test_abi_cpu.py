@@ -174,6 +174,9 @@ def test_batch_entry_points_reject_null_without_gpu():
     assert L.vclb_batch_step(None, 1, 1, None) == v.VCLB_EINVAL
     assert L.vclb_batch_balance(None, 1, 1, None, None) == v.VCLB_EINVAL
     assert L.vclb_batch_init(None, None, None, v.HOST, None) == v.VCLB_EINVAL
+    cnt = ctypes.c_int32(0)
+    assert L.vclb_batch_get_weights(None, None, 0, ctypes.byref(cnt)) == v.VCLB_EINVAL
+    assert L.vclb_batch_set_weights(None, None, 0) == v.VCLB_EINVAL
     assert L.vclb_batch_set_reduce_every(None, 1) == v.VCLB_EINVAL
 
 

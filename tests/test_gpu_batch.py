@@ -196,6 +196,45 @@ def test_batch_rejects_1024_lanes_in_fp64():
     assert b.tile()[0] == 512                              # the shape in force is kept
 
 
+@pytest.mark.parametrize("storage,flat_pct,bx", [("fp32", 101, 64), ("fp64", 0, 256), ("fp16s", 100, 1024)])
+def test_batch_any_slot_weights_give_the_same_states(storage, flat_pct, bx):
+    """Runs cut with arbitrary, even extreme, slot weights still cover every row of every
+    case exactly once: the states match the equal cut bit for bit."""
+    v = _v()
+    cases = small_batch(storage, n=8, seed=9)
+    say("case: slot weights", storage, flat_pct, bx, [(p.nx, p.ny) for p, _, _ in cases])
+
+    def make():
+        b = v.Batch([p for p, _, _ in cases]).init([(phi0, u0) for _, phi0, u0 in cases])
+        b.set_tile(bx, 16)
+        b.set_schedule(flat_pct)
+        return b
+
+    ref = make()
+    ref.step(12)
+    n = len(ref.weights())
+    assert n == ref.tile()[2] and np.all(ref.weights() == 1.0)
+    rng = np.random.Generator(np.random.PCG64(5))
+    patterns = {"log-uniform": np.exp(rng.uniform(np.log(0.01), np.log(100.0), n)),
+                "one heavy slot": np.where(np.arange(n) == 3, 1e3, 1e-3)}
+    for name, w in patterns.items():
+        b = make()
+        b.set_weights(w)
+        got = b.weights()
+        assert np.allclose(got, w * n / w.sum(), rtol=1e-12)
+        b.step(12)
+        for k in range(len(cases)):
+            for a, c in zip(ref.cases[k].get_state(), b.cases[k].get_state()):
+                assert np.array_equal(a, c), (name, k)
+        assert np.allclose(ref.history(0, 12)["sum_phi"], b.history(0, 12)["sum_phi"], rtol=1e-12, atol=0.0)
+        b.set_weights([])
+        assert np.all(b.weights() == 1.0)
+        with pytest.raises(v.VclbError):
+            b.set_weights(np.ones(n + 1))               # one weight per slot
+        with pytest.raises(v.VclbError):
+            b.set_weights(np.zeros(n))                  # outside [1e-3, 1e3]
+
+
 def test_batch_init_equals_per_case_init():
     """vclb_batch_init gives every case the state vclb_case_init gives it, bit for bit."""
     v = _v()
