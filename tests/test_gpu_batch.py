@@ -188,6 +188,33 @@ def test_batch_autotune_restores_state_and_uses_cache(tmp_path):
     assert len(open(cache).read().strip().splitlines()) == 1
 
 
+@pytest.mark.parametrize("flat_pct", [101, 0])
+def test_batch_1024_lanes_with_wide_and_tiny_cases(flat_pct):
+    """1024-lane workgroups (FP32) over a case wider than one chunk (1100 columns: the
+    four-slot FIFO in bands, two strips of which one ragged) beside tiny ones."""
+    v = _v()
+    specs = [(1100, 40, False), (1, 40, False), (3, 130, True), (600, 30, True), (70, 2, True)]
+    cases = []
+    for nx, ny, wall in specs:
+        p = W.CaseParams(nx=nx, ny=ny, rho_light=0.2, wall_y=wall, storage="fp32",
+                         wall_u_bottom=(-0.02, 0.0, 0.0) if wall else (0.0, 0.0, 0.0),
+                         wall_u_top=(0.02, 0.0, 0.0) if wall else (0.0, 0.0, 0.0))
+        R = max(1.5, 0.3 * min(nx, ny))
+        cases.append((p, W.drops_phi(p, [((nx - 1) / 2.0, (ny - 1) / 2.0, 0.0, R)]),
+                      W.couette_u(p) if wall else None))
+    say("case: 1024 lanes, wide and tiny, fp32", specs, "flat_pct", flat_pct)
+    b = v.Batch([p for p, _, _ in cases]).init([(phi0, u0) for _, phi0, u0 in cases])
+    b.set_tile(1024, 1024)
+    b.set_schedule(flat_pct)
+    b.step(12)
+    for k, (p, phi0, u0) in enumerate(cases):
+        alone = v.Case(p, tile=(64, 16)).init(phi0, u0)
+        alone.step(12)
+        err = max(np.max(np.abs(a_ - b_)) for a_, b_ in zip(alone.get_state(), b.cases[k].get_state()))
+        say(f"  case {k} {p.nx}x{p.ny}: max |batch - alone| = {err:.3e}")
+        assert err == 0.0, k        # the same node arithmetic in both marches: bit for bit
+
+
 def test_batch_rejects_1024_lanes_in_fp64():
     v = _v()
     b = v.Batch([p for p, _, _ in small_batch("fp64", n=2)])
