@@ -268,6 +268,34 @@ def test_tile_shape_does_not_change_the_state(storage):
                 assert np.array_equal(F[k], ref[k]), (tile, k)
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.5])
+def test_d3q19_laplace_law(lam):
+    """A drop at rest in 3D settles to the pressure jump of Laplace's law, 2 sigma / R
+    (twice the 2D jump): checked on the fused D3Q19 path for R = 12 and 16 (FP64, density
+    ratio 1, 6000 steps).  Inside and outside pressures are averaged more than two
+    interface widths from the interface; R is the radius of the drop's volume sum(phi)."""
+    v = _v()
+    jumps = {}
+    for n, R0 in ((48, 12.0), (64, 16.0)):
+        c0 = (n - 1) / 2.0
+        p = W.CaseParams(nx=n, ny=n, nz=n, lattice="D3Q19", W=4.0, sigma=0.01, mobility=0.1, nu=0.1,
+                         rho_heavy=1.0, rho_light=1.0, lam=lam, storage="fp64", label_centres=[(c0, c0, c0)])
+        say(f"case: d3q19 Laplace, lam {lam}, {n}^3, R {R0}")
+        c = v.Case(p).init(W.drops_phi(p, [(c0, c0, c0, R0)]), None)
+        c.set_reduce_every(0)
+        c.step(6000)
+        F = c.observe(v.FIELD_PHI | v.FIELD_P)
+        z, y, x = np.meshgrid(*(np.arange(n) - c0,) * 3, indexing="ij")
+        r = np.sqrt(x * x + y * y + z * z)
+        R = (3.0 * F["phi"].sum() / (4.0 * np.pi)) ** (1.0 / 3.0)
+        dp = F["p"][r < R - 2 * p.W].mean() - F["p"][r > R + 2 * p.W].mean()
+        jumps[R] = dp
+        say(f"  R {R:.3f}: dp {dp:.4e} against 2 sigma / R {2 * p.sigma / R:.4e} (ratio {dp * R / (2 * p.sigma):.3f})")
+        assert abs(dp * R / (2 * p.sigma) - 1.0) <= 0.12          # measured: within 4-9%
+    (Ra, da), (Rb, db) = sorted(jumps.items())
+    assert abs((da * Ra) / (db * Rb) - 1.0) <= 0.06               # dp R constant; measured: 4%
+
+
 D3_TILES = [(16, 5, 4), (32, 7, 8), (64, 24, 2)]   # (bx, ty planes of z, by3 rows of y)
 
 
