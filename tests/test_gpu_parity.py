@@ -296,6 +296,37 @@ def test_d3q19_laplace_law(lam):
     assert abs((da * Ra) / (db * Rb) - 1.0) <= 0.06               # dp R constant; measured: 4%
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_d3q19_shear_waves_decay_at_the_viscous_rate(storage):
+    """Single-phase shear waves on the fused D3Q19 path decay as exp(-nu k^2 t): u_x
+    varying along z (streaming across planes) and u_z varying along x, with nu = 0.1 set
+    through the f stress rates (Eq. 27)."""
+    v = _v()
+    n, steps = 64, 500
+    k = 2 * np.pi / n
+    for comp, axis in ((0, "z"), (2, "x")):
+        p = W.CaseParams(nx=n if axis == "x" else 8, ny=8, nz=n if axis == "z" else 8, lattice="D3Q19",
+                         rho_light=1.0, nu=0.1, storage=storage)
+        say(f"case: d3q19 shear wave {storage}, u[{comp}] along {axis}, {p.nx}x{p.ny}x{p.nz}")
+        s_ = np.arange(n)
+        wave = 0.01 * np.sin(k * s_)
+        u0 = np.zeros((3, p.nz, p.ny, p.nx))
+        u0[comp] = wave[:, None, None] if axis == "z" else wave[None, None, :]
+        c = v.Case(p).init(np.zeros((p.nz, p.ny, p.nx)), u0)
+        c.set_reduce_every(0)
+
+        def amplitude():
+            u = c.observe(v.FIELD_U)["u"][comp]
+            prof = u.mean(axis=(1, 2)) if axis == "z" else u.mean(axis=(0, 1))
+            return abs(np.sum(prof * np.exp(-1j * k * s_)))
+
+        a0 = amplitude()
+        c.step(steps)
+        rate = -np.log(amplitude() / a0) / steps / (p.nu * k * k)
+        say(f"  decay rate / (nu k^2) = {rate:.5f}")
+        assert abs(rate - 1.0) < 5e-3
+
+
 D3_TILES = [(16, 5, 4), (32, 7, 8), (64, 24, 2)]   # (bx, ty planes of z, by3 rows of y)
 
 
