@@ -193,6 +193,9 @@ def run_adjoint(nsteps: int = 4000, every: int = 200):
                         f"{nsteps} steps, a checkpoint every {every}; J = deformation D",
             "forward_ms": round(fwd_ms, 3), "record_ms": round(rec_s * 1e3, 3), "backward_ms": round(bwd_ms, 3),
             "ratio_backward_over_forward": round(bwd_ms / fwd_ms, 4),
+            # the backward less its recompute, priced at the forward's own time per step:
+            # the reverse sweep alone (its kernels and copies) against the forward
+            "ratio_reverse_over_forward_est": round((bwd_ms - (nsteps - nck) * fwd_ms / nsteps) / fwd_ms, 4),
             "recomputed_steps": nsteps - nck,
             "D": D, "dD_dsigma": ds, "dD_dM": dm, "max_abs_dD_dphi0": gmax}
 
