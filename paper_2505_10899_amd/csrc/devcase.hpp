@@ -221,8 +221,12 @@ __device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, lon
                                            const typename St::R (&J)[L::D]) {
   using R = typename St::R;
   const int dst = par ^ 1;
+  R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) St::store(c.pop[0][dst], long(i) * c.n + n, g[i]);
+  for (int i = 0; i < L::Q; ++i) {
+    St::store(c.pop[0][dst], long(i) * c.n + n, g[i]);
+    if constexpr (St::fold) res += St::rounding(g[i]);
+  }
   if constexpr (COUPLED) {
     if (c.wall) {
       if (y == 0) {
@@ -241,7 +245,7 @@ __device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, lon
   }
 #pragma unroll
   for (int d = 0; d < L::D; ++d) stg(c.J, d * c.n + n, J[d]);
-  if constexpr (St::shifted) stg(c.phis[dst], n, float(phi));
+  if constexpr (St::shifted) stg(c.phis[dst], n, float(phi - res));
 }
 
 template <class L, class St, bool COUPLED>

@@ -178,8 +178,12 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
       }
       NodeOut<L, R> out;
       node_update_d2q9<R, true, St::shifted, UNIT>(c.np, in, e[SU], f, J, out);
+      R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
 #pragma unroll
-      for (int j = 0; j < Q; ++j) St::store(c.pop[0][dst] + long(j) * n, nn, e[SU][j]);
+      for (int j = 0; j < Q; ++j) {
+        St::store(c.pop[0][dst] + long(j) * n, nn, e[SU][j]);
+        if constexpr (St::fold) res += St::rounding(e[SU][j]);
+      }
       if (wall && y == 0) {
 #pragma unroll
         for (int j = 0; j < Q; ++j)
@@ -194,7 +198,7 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
       for (int j = 0; j < Q; ++j) St::store(c.pop[1][dst] + long(j) * n, nn, f[j]);
       stg(c.J, nn, J[0]);
       stg(c.J + n, nn, J[1]);
-      if constexpr (St::shifted) stg(c.phis[dst], nn, float(in.nphi[0]));
+      if constexpr (St::shifted) stg(c.phis[dst], nn, float(in.nphi[0] - res));
       if (reduce) {
         const double ph = double(in.nphi[0]);
         const double dx = min_image(double(x) - c.cen[0][0], nx, true);

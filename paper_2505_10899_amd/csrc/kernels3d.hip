@@ -208,13 +208,17 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
       NodeOut<L, R> out;
       node_update_mom_s<L, R, true, St::shifted, UNIT>(c.np, st, gcur, f, J, out);
       const int dst = par ^ 1;
+      R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
 #pragma unroll
-      for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + i * c.n, IX(nn), gcur[i]);
+      for (int i = 0; i < Q; ++i) {
+        St::store(c.pop[0][dst] + i * c.n, IX(nn), gcur[i]);
+        if constexpr (St::fold) res += St::rounding(gcur[i]);
+      }
 #pragma unroll
       for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, IX(nn), f[i]);
 #pragma unroll
       for (int d = 0; d < L::D; ++d) stg(c.J + d * c.n, IX(nn), J[d]);
-      if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi));
+      if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi - res));
       if (reduce) {
         const double ph = double(st.phi);
         int lab = 0;

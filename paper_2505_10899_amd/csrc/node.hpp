@@ -51,10 +51,14 @@ __device__ __forceinline__ void stg(T* p, unsigned i, T v) {
 }
 
 // ---------------------------------------------------------------- storage codecs
+// fold: the storage rounds coarsely enough that the writer phi stored beside a node's g
+// absorbs the sum of their rounding errors (rounding(v): stored value minus v)
 struct StoreF64 {
   using S = double;
   using R = double;
   static constexpr bool shifted = false;
+  static constexpr bool fold = false;
+  __device__ static R rounding(R) { return R(0); }
   template <class I>
   __device__ static R load(const S* p, I i) { return ldg(p, i); }
   template <class I>
@@ -67,6 +71,8 @@ struct StoreF32 {
   using S = float;
   using R = float;
   static constexpr bool shifted = true;
+  static constexpr bool fold = false;
+  __device__ static R rounding(R) { return R(0); }
   template <class I>
   __device__ static R load(const S* p, I i) { return ldg(p, i); }
   template <class I>
@@ -81,6 +87,13 @@ struct StoreF16S {
   using S = __half;
   using R = float;
   static constexpr bool shifted = true;
+  // A node's stored deviations, rounded to 2 bytes, change the sum of its nine g by the
+  // sum of their rounding errors; at a node in a steady state that error is the same
+  // every step, so the total of phi would drift steadily.  The writer phi stored beside
+  // them (FP32) takes that sum off, so the populations its neighbours decode add up to
+  // the node's phi again.
+  static constexpr bool fold = true;
+  __device__ static R rounding(R v) { return __half2float(__float2half_rn(v)) - v; }
   template <class I>
   __device__ static R load(const S* p, I i) {
     return __half2float(__ushort_as_half(ldg(reinterpret_cast<const unsigned short*>(p), i)));

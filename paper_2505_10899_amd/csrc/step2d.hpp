@@ -159,8 +159,12 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
       }
       NodeOut<L, R> out;
       node_update_d2q9<R, COUPLED, St::shifted, UNIT>(c.np, in, gcur, f, J, out);
+      R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
 #pragma unroll
-      for (int i = 0; i < Q; ++i) St::store(c.pop[0][dst] + long(i) * n, IX(nn), gcur[i]);
+      for (int i = 0; i < Q; ++i) {
+        St::store(c.pop[0][dst] + long(i) * n, IX(nn), gcur[i]);
+        if constexpr (St::fold) res += St::rounding(gcur[i]);
+      }
       if constexpr (COUPLED) {
         if (wall && y == 0) {
 #pragma unroll
@@ -177,7 +181,7 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
       }
       stg(c.J, IX(nn), J[0]);
       stg(c.J + n, IX(nn), J[1]);
-      if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(in.nphi[0]));
+      if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(in.nphi[0] - res));
       if (reduce) {
         const double ph = double(in.nphi[0]);
         double dy[kMaxLabels];
