@@ -161,3 +161,135 @@ class Dense2D:
                 f[k, i] = rho[k] * s if self.mode == "coupled" else 0.0
             g[k, 0] = phi0[k] + (w[0] - 1) * H
         return g, f, phi0[:, None] * u0
+
+
+# ---------------------------------------------------------------------------- 3D
+def d3q19_velocities():
+    """The 19 velocities of {-1, 0, 1}^3 with |c|^2 <= 2, enumerated in lexicographic order
+    (not the oracle's order), with the standard weights 1/3, 1/18, 1/36 by |c|^2."""
+    import itertools
+    c = np.array([v for v in itertools.product((-1, 0, 1), repeat=3) if sum(a * a for a in v) <= 2])
+    c2 = (c * c).sum(axis=1)
+    w = np.select([c2 == 0, c2 == 1, c2 == 2], [1 / 3, 1 / 18, 1 / 36])
+    return c, w
+
+
+def _projector(vectors):
+    """Euclidean orthogonal projector onto the span of the given vectors (rows)."""
+    u, sv, _ = np.linalg.svd(np.array(vectors, dtype=float).T, full_matrices=False)
+    q = u[:, sv > 1e-10 * sv[0]]
+    return q @ q.T
+
+
+class Dense3D:
+    """One model step on a tiny periodic 3D grid, built without the moment basis.
+
+    The multiple-relaxation-time operator of Eqs. 25/33 is M^{-1} S M.  With a basis whose
+    rows are mutually orthogonal, and rates that are 1 except on one subspace, it equals
+    I + (s - 1) P, with P the orthogonal projector onto that subspace.  The subspaces are
+    spanned here straight from their defining polynomials: for g the first- and
+    third-order axial fluxes c_a and |c|^2 c_a (a = x, y, z), relaxing at 1/tau_g; for f
+    the traceless second-order tensor c_a c_b - delta_ab |c|^2 / 3, relaxing at 1/tau_f
+    (Eq. 27).  Streaming is a dense permutation matrix, the stencils of Eqs. 39-40 are
+    dense matrices, and every node is visited in a Python loop."""
+
+    def __init__(self, nx, ny, nz, *, W, sigma, mobility, nu, lam, xi, eps_n, rho_h, rho_l):
+        self.n = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.c, self.w = d3q19_velocities()
+        self.Q = len(self.w)
+        self.W, self.lam, self.xi, self.eps = W, lam, xi, eps_n
+        self.beta, self.kappa = 12 * sigma / W, 1.5 * sigma * W
+        self.rho_h, self.rho_l = rho_h, rho_l
+        c = self.c.astype(float)
+        c2 = (c * c).sum(axis=1)
+        flux = [c[:, a] for a in range(3)] + [c2 * c[:, a] for a in range(3)]
+        stress = [c[:, a] * c[:, b] - (a == b) * c2 / 3 for a in range(3) for b in range(3)]
+        tg, tf = 0.5 + 3 * mobility, 0.5 + 3 * nu
+        I = np.eye(self.Q)
+        self.Ag = I + (1 / tg - 1) * _projector(flux)
+        self.Af = I + (1 / tf - 1) * _projector(stress)
+        self.Bg = I - 0.5 * self.Ag
+        self.Bf = I - 0.5 * self.Af
+        self._build()
+
+    def idx(self, x, y, z):
+        nx, ny, _ = self.n
+        return x + nx * (y + ny * z)
+
+    def _build(self):
+        nx, ny, nz = self.n
+        N, Q, c, w = self.N, self.Q, self.c, self.w
+        self.G = np.zeros((3, N, N))
+        self.L = np.zeros((N, N))
+        self.P = np.zeros((Q * N, Q * N))
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    k = self.idx(x, y, z)
+                    for i in range(Q):
+                        cx, cy, cz = c[i]
+                        nb = self.idx((x + cx) % nx, (y + cy) % ny, (z + cz) % nz)
+                        src = self.idx((x - cx) % nx, (y - cy) % ny, (z - cz) % nz)
+                        self.P[Q * k + i, Q * src + i] = 1.0
+                        if cx == cy == cz == 0:
+                            continue
+                        for d in range(3):
+                            self.G[d, k, nb] += w[i] * c[i, d] / CS2
+                        self.L[k, nb] += 2 * w[i] / CS2
+                        self.L[k, k] -= 2 * w[i] / CS2
+
+    def step(self, g, f, J):
+        """g, f: (N, Q) in this class's velocity order; J: (N, 3).  Returns the next state."""
+        c, w, Q = self.c.astype(float), self.w, self.Q
+        rest = int(np.where((self.c == 0).all(axis=1))[0][0])
+        phi = g.sum(axis=1)
+        rho = self.rho_l + (self.rho_h - self.rho_l) * phi
+        pc = np.clip(phi, 0.0, 1.0)
+        psi = self.W / 4 * np.log((pc + self.xi) / (1 - pc + self.xi))
+        th = np.tanh(2 * psi / self.W)
+        gphi = np.stack([self.G[d] @ phi for d in range(3)], axis=1)
+        gpsi = np.stack([self.G[d] @ psi for d in range(3)], axis=1)
+        mu = 4 * self.beta * phi * (phi - 1) * (phi - 0.5) - self.kappa * (self.L @ phi)
+        Fs = mu[:, None] * gphi
+        grho = (self.rho_h - self.rho_l) * gphi
+        u = (f @ c + 0.5 * Fs) / rho[:, None]
+        Jn = phi[:, None] * u
+        gs, fs = np.empty_like(g), np.empty_like(f)
+        for k in range(self.N):
+            uk = u[k]
+            nrm = gpsi[k] / np.sqrt(gpsi[k] @ gpsi[k] + self.eps ** 2)
+            V = (Jn[k] - J[k]) / CS2 + self.lam / self.W * (1 - th[k] ** 2) * nrm
+            H = mu[k] + self.lam * phi[k]
+            geq = np.array([w[i] * H + w[i] * (c[i] @ Jn[k]) / CS2 for i in range(Q)])
+            geq[rest] = phi[k] + (w[rest] - 1) * H
+            G = np.array([w[i] * (c[i] @ V) for i in range(Q)])
+            gs[k] = g[k] - self.Ag @ (g[k] - geq) + self.Bg @ G
+            s = np.array([w[i] * ((c[i] @ uk) / CS2 + (c[i] @ uk) ** 2 / (2 * CS2 ** 2) - uk @ uk / (2 * CS2))
+                          for i in range(Q)])
+            moving = [i for i in range(Q) if i != rest]
+            press = CS2 / (1 - w[rest]) * (f[k, moving].sum() + 0.5 * uk @ grho[k] + rho[k] * s[rest])
+            feq = w * press / CS2 + rho[k] * s
+            feq[rest] = (w[rest] - 1) * press / CS2 + rho[k] * s[rest]
+            Fi = np.array([w[i] * (uk @ grho[k] + (c[i] @ Fs[k]) / CS2
+                                   + (np.outer(uk, grho[k]) * (np.outer(c[i], c[i]) - CS2 * np.eye(3))).sum() / CS2)
+                           for i in range(Q)])
+            fs[k] = f[k] - self.Af @ (f[k] - feq) + self.Bf @ Fi
+        gn = (self.P @ gs.reshape(-1)).reshape(self.N, Q)
+        fn = (self.P @ fs.reshape(-1)).reshape(self.N, Q)
+        return gn, fn, Jn
+
+    def init(self, phi0, u0):
+        c, w, Q = self.c.astype(float), self.w, self.Q
+        rest = int(np.where((self.c == 0).all(axis=1))[0][0])
+        mu = 4 * self.beta * phi0 * (phi0 - 1) * (phi0 - 0.5) - self.kappa * (self.L @ phi0)
+        rho = self.rho_l + (self.rho_h - self.rho_l) * phi0
+        g, f = np.zeros((self.N, Q)), np.zeros((self.N, Q))
+        for k in range(self.N):
+            H = mu[k] + self.lam * phi0[k]
+            for i in range(Q):
+                g[k, i] = w[i] * H + w[i] * (c[i] @ (phi0[k] * u0[k])) / CS2
+                cu = c[i] @ u0[k]
+                f[k, i] = rho[k] * w[i] * (cu / CS2 + cu * cu / (2 * CS2 ** 2) - u0[k] @ u0[k] / (2 * CS2))
+            g[k, rest] = phi0[k] + (w[rest] - 1) * H
+        return g, f, phi0[:, None] * u0
