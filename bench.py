@@ -36,20 +36,31 @@ METRIC = "MLUPS & % HBM roofline, FP32/FP16-store vs FP64 GPU; adjoint/forward t
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch512.txt")
 
-# algorithmic HBM bytes per node update: every population read once and written once,
-# the previous phi u read and written, and (shifted storage) the phi of the writing
-# node written once and read once.  (lattice, coupled) -> storage -> bytes
+# Algorithmic HBM bytes per node update: every population read once and written once,
+# the previous phi u read and written, and, for the 2-byte storage only, the FP32 phi of
+# the node that wrote a set of deviations written once and read once (the 2-byte
+# deviations cannot be decoded without it).  (lattice, coupled) -> storage -> bytes
 BYTES_PER_NODE = {
-    ("D2Q9", True): {"fp64": 2 * 9 * 8 * 2 + 2 * 8 * 2,
-                     "fp32": 2 * 9 * 4 * 2 + 2 * 4 * 2 + 4 * 2,
-                     "fp16s": 2 * 9 * 2 * 2 + 2 * 4 * 2 + 4 * 2},
-    ("D2Q9", False): {"fp64": 9 * 8 * 2 + 2 * 8 * 2,
-                      "fp32": 9 * 4 * 2 + 2 * 4 * 2 + 4 * 2,
-                      "fp16s": 9 * 2 * 2 + 2 * 4 * 2 + 4 * 2},
-    ("D3Q19", True): {"fp64": 2 * 19 * 8 * 2 + 3 * 8 * 2,
-                      "fp32": 2 * 19 * 4 * 2 + 3 * 4 * 2 + 4 * 2,
-                      "fp16s": 2 * 19 * 2 * 2 + 3 * 4 * 2 + 4 * 2},
+    ("D2Q9", True): {"fp64": 2 * 9 * 8 * 2 + 2 * 8 * 2,                 # 320
+                     "fp32": 2 * 9 * 4 * 2 + 2 * 4 * 2,                 # 160
+                     "fp16s": 2 * 9 * 2 * 2 + 2 * 4 * 2 + 4 * 2},       # 96
+    ("D2Q9", False): {"fp64": 9 * 8 * 2 + 2 * 8 * 2,                    # 176
+                      "fp32": 9 * 4 * 2 + 2 * 4 * 2,                    # 88
+                      "fp16s": 9 * 2 * 2 + 2 * 4 * 2 + 4 * 2},          # 60
+    ("D3Q19", True): {"fp64": 2 * 19 * 8 * 2 + 3 * 8 * 2,               # 656
+                      "fp32": 2 * 19 * 4 * 2 + 3 * 4 * 2,               # 328
+                      "fp16s": 2 * 19 * 2 * 2 + 3 * 4 * 2 + 4 * 2},     # 184
 }
+# What the kernels of this library move per node update in their layout: FP32 storage
+# also keeps g as deviations from the writer's rest state, with the writer's phi
+# beside them (4 B written, 4 B read), to hold the total of phi to FP32 rounding.
+LAYOUT_EXTRA = {"fp64": 0, "fp32": 8, "fp16s": 0}
+
+
+def layout_bytes(lattice: str, coupled: bool, storage: str) -> int:
+    return BYTES_PER_NODE[(lattice, coupled)][storage] + LAYOUT_EXTRA[storage]
+
+
 KERNEL = {"fp64": "k_batch_step2d<StoreF64>", "fp32": "k_batch_step2d<StoreF32>",
           "fp16s": "k_batch_step2d<StoreF16S>"}
 
@@ -148,10 +159,40 @@ def run_batch(storage: str, steps: int, warmup: int, launch_steps: int, tune_ste
     drift = float(np.max(np.abs(v1 - v0) / np.abs(v0)))
     bpn = BYTES_PER_NODE[("D2Q9", True)][storage]
     gbs = N * bpn / (launch_ms * 1e-3) / 1e9
+    check = check_against_tested_shape(b, cases, storage, int(t_end))
     del b
     return dict(nodes=N, ms_per_step=ms, wall_s=wall, mlups=N / (ms * 1e-3) / 1e6, launch_ms=launch_ms,
-                bytes_per_node=bpn, achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=list(tile), flat_pct=sched,
-                balance_gain=gain, max_rel_volume_drift=drift, drift_steps=int(t_end))
+                bytes_per_node=bpn, layout_bytes_per_node=layout_bytes("D2Q9", True, storage),
+                achieved_GBs=gbs, frac=gbs / HBM_PEAK_GBS, tile=list(tile), flat_pct=sched,
+                balance_gain=gain, max_rel_volume_drift=drift, drift_steps=int(t_end), tile_check=check)
+
+
+# the launch shape the full-size parity tests of tests/test_gpu_batch.py run every
+# storage in (bx, ty, flat_pct)
+TESTED_SHAPE = (512, 1024, 100)
+
+
+def check_against_tested_shape(b, cases, storage: str, t: int) -> str:
+    """The timed batch, whatever launch shape the autotuner chose, against the same cases
+    stepped as many times in the launch shape the full-size parity tests cover: every
+    case's state (g, f, previous phi u, decoded to FP64 on the device) must be equal bit
+    for bit.  Raises if it is not."""
+    import torch
+    from paper_2505_10899_amd import vclb
+    ref = vclb.Batch([p for p, _, _ in cases]).init([(phi0, u0) for _, phi0, u0 in cases])
+    ref.set_tile(TESTED_SHAPE[0], TESTED_SHAPE[1])
+    ref.set_schedule(TESTED_SHAPE[2])
+    ref.set_reduce_every(0)
+    ref.step(t, graph=True)
+    torch.cuda.synchronize()
+    for k, (ca, cb) in enumerate(zip(b.cases, ref.cases)):
+        for xa, xb in zip(ca.state_device(), cb.state_device()):
+            if xa is not None and not torch.equal(xa, xb):
+                raise RuntimeError(f"batch {storage}: case {k} differs from the tested launch shape "
+                                   f"{TESTED_SHAPE} after {t} steps")
+    del ref
+    return (f"all {len(cases)} cases bitwise equal after {t} steps to launch shape (bx, ty, flat_pct) = "
+            f"{TESTED_SHAPE}, which the full-size parity tests cover")
 
 
 # ----------------------------------------------------------------------------- adjoint
@@ -225,7 +266,8 @@ def run_single(name: str, storage: str, steps: int, warmup: int, tune: bool = Tr
     gbs = p.n_nodes * bpn / (ms * 1e-3) / 1e9
     return {"nodes": p.n_nodes, "MLUPS": round(p.n_nodes / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
             "achieved_GBs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "bytes_per_node": bpn, "tile": list(c.tile())}
+            "bytes_per_node": bpn, "layout_bytes_per_node": layout_bytes(p.lattice, p.mode == "coupled", storage),
+            "tile": list(c.tile())}
 
 
 # ----------------------------------------------------------------------------- CPU oracle
@@ -319,6 +361,7 @@ def main(argv=None):
                      "unit": "GB/s", "frac": round(h["frac"], 4), "traffic": traffic,
                      "kernel": KERNEL[head], "bytes_per_node": h["bytes_per_node"],
                      "bytes_per_launch": h["bytes_per_node"] * h["nodes"],
+                     "layout_bytes_per_node": h["layout_bytes_per_node"],
                      "launch_ms": round(h["launch_ms"], 5),
                      "achievable_copy_GBs": probe["copy"],
                      "frac_of_copy": round(h["achieved_GBs"] / probe["copy"], 4)},
@@ -326,7 +369,8 @@ def main(argv=None):
         "variants": {st: {"MLUPS": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                           "launch_ms": round(v["launch_ms"], 5), "achieved_GBs": round(v["achieved_GBs"], 1),
                           "frac_hbm_peak": round(v["frac"], 4), "bytes_per_node": v["bytes_per_node"],
-                          "tile": v["tile"], "flat_pct": v["flat_pct"],
+                          "layout_bytes_per_node": v["layout_bytes_per_node"],
+                          "tile": v["tile"], "flat_pct": v["flat_pct"], "tile_check": v["tile_check"],
                           "slot_balance_gain": round(v["balance_gain"], 4),
                           "max_rel_volume_drift": v["max_rel_volume_drift"],
                           "drift_over_steps": v["drift_steps"],

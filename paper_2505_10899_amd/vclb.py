@@ -269,6 +269,19 @@ class Case:
                                         ctypes.c_void_p(tJ.data_ptr()), int(t), DEVICE, _stream_handle(stream)))
         return self
 
+    def state_device(self, stream=None):
+        """(g, f, J) of the current state, decoded to float64, as flat device tensors
+        (f is None in vortex mode)."""
+        Q = 9 if self.D == 2 else 19
+        g = torch.empty(Q * self.n, dtype=torch.float64, device=self.device)
+        J = torch.empty(self.D * self.n, dtype=torch.float64, device=self.device)
+        f = torch.empty(Q * self.n, dtype=torch.float64, device=self.device) if self.p.mode == "coupled" else None
+        check(lib().vclb_case_get_state(self.h, ctypes.c_void_p(g.data_ptr()),
+                                        ctypes.c_void_p(f.data_ptr() if f is not None else 0),
+                                        ctypes.c_void_p(J.data_ptr()), DEVICE, _stream_handle(stream)))
+        torch.cuda.current_stream().synchronize()
+        return g, f, J
+
     def get_state(self, stream=None):
         """(g, f, J) of the current state as float64 numpy arrays (f is None in vortex mode)."""
         Q = 9 if self.D == 2 else 19

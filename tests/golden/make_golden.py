@@ -49,6 +49,33 @@ def two_droplets_1000():
     print("round-off envelope at t = 1000:", env, "per-drop sums", env_sum, "counts", env_count)
 
 
+def offnode_free_runs():
+    """FP64 fields phi, rho, u after each 2D case's steps in ``workloads.offnode_parity_cases``
+    (drops off the lattice nodes), and the oracle's own round-off envelope there: the
+    largest change of each field when phi0 is perturbed by a relative 1e-15."""
+    out = {}
+    for name, (p, phi0, u0, steps) in W.offnode_parity_cases().items():
+        if p.lattice != "D2Q9":
+            continue                      # the 3D column is run by the test itself
+        m = Model(p).init(phi0, u0)
+        m.step(steps)
+        F = m.fields()
+        rng = np.random.default_rng(1)
+        q = Model(p).init(phi0 * (1.0 + 1e-15 * rng.standard_normal(phi0.shape)), u0)
+        q.step(steps)
+        G = q.fields()
+        for k in ("phi", "rho", "u"):
+            out[f"{name}__{k}"] = F[k]
+            out[f"{name}__env_{k}"] = float(np.max(np.abs(F[k] - G[k])))
+        out[f"{name}__steps"] = steps
+        print(name, {k: out[f"{name}__env_{k}"] for k in ("phi", "rho", "u")}, flush=True)
+    np.savez_compressed(os.path.join(HERE, "offnode_fp64_free_runs.npz"), **out)
+
+
 if __name__ == "__main__":
-    two_droplets_1000()
+    which = sys.argv[1:] or ["two_droplets_1000", "offnode_free_runs"]
+    if "two_droplets_1000" in which:
+        two_droplets_1000()
+    if "offnode_free_runs" in which:
+        offnode_free_runs()
     print("wrote", HERE)

@@ -270,3 +270,38 @@ def batch_cases(n_cases: int = 512, seed: int = BATCH_SEED, storage: str = "fp16
 def batch_case_list_json(n_cases: int = 512, seed: int = BATCH_SEED) -> str:
     _, table = batch_cases(n_cases, seed)
     return json.dumps(table)
+
+
+# ---------------------------------------------------------------------------
+# FP64 free-run parity cases: drops and columns placed off the lattice nodes
+# ---------------------------------------------------------------------------
+
+def offnode_parity_cases():
+    """Cases for the 1000-step FP64 free-run parity check, name -> (params, phi0, u0, steps).
+
+    Every drop centre (and the column axis) lies off the lattice nodes and off the
+    half-node mirror lines.  A centre on a node makes grad psi vanish there by symmetry,
+    so the unit normal of Eq. 32 is set by rounding and any two correct implementations
+    drift apart; off-node, the oracle run against itself with phi0 perturbed by 1e-15
+    stays within about 6e-15 on phi after 1000 steps.  Covered: the two-drop case at
+    its full 128 x 128 size, moving walls, the prescribed vortex, the classical model
+    (lambda = 0), relaxation rates off their defaults, and a D3Q19 column (24 x 24 x 96,
+    200 steps)."""
+    out = {}
+    p = CaseParams(nx=128, ny=128, W=4.0, sigma=0.01, mobility=0.1, nu=0.1, rho_heavy=1.0, rho_light=0.1,
+                   label_centres=[(40.37, 64.41, 0.0), (96.23, 63.71, 0.0)])
+    out["two_droplets_128"] = (p, drops_phi(p, [(40.37, 64.41, 0.0, 24.0), (96.23, 63.71, 0.0, 8.0)]), None, 1000)
+    p, _, u0 = shear_droplet(nx=66, ny=20, R=6.0, U=0.02, Ca=0.2, Re=0.5)
+    p = p.replace(rho_light=0.5, label_centres=[(32.31, 9.17, 0.0)])
+    out["walls_moving"] = (p, drops_phi(p, [(32.31, 9.17, 0.0, 6.0)]), u0, 1000)
+    p = CaseParams(nx=50, ny=50, mode="vortex", W=4.0, sigma=0.01, mobility=0.02, U0=0.04, T=40.0)
+    out["vortex"] = (p, drops_phi(p, [(25.3, 37.2, 0.0, 7.5)]), None, 1000)
+    p = CaseParams(nx=64, ny=64, lam=0.0, rho_light=0.2, sigma=0.02)
+    out["classical_lambda0"] = (p, drops_phi(p, [(31.77, 31.21, 0.0, 10.0)]), None, 1000)
+    p = CaseParams(nx=64, ny=20, rho_light=0.3, s_g=(0, 1.3, 1.1, 0, 0, 0, 0, 1.2, 1.1),
+                   s_f=(1.0, 1.2, 1.3, 1.1, 1.2, 1.1, 1.2, 0, 0))
+    out["mrt_rates"] = (p, drops_phi(p, [(31.63, 9.28, 0.0, 6.0)]), None, 1000)
+    p = CaseParams(nx=24, ny=24, nz=96, lattice="D3Q19", W=4.0, sigma=0.005, mobility=0.1, nu=0.05,
+                   rho_heavy=1.0, rho_light=0.1)
+    out["d3q19_column"] = (p, cylinder_phi(p, 11.63, 12.27, 6.0, 0.1, 96.0), None, 200)
+    return out
