@@ -83,15 +83,20 @@ extern "C" {
 #define VCLB_HISTORY    4096    /* per-step observations kept (ring)                */
 
 /* ---------------------------------------------------------------- parameters */
+/* Axes and faces for bc and wall_u: axis 0 = x, 1 = y, 2 = z; side 0 = the low face (below
+   the first node), 1 = the high face (above the last node). */
 typedef struct {
   int32_t lattice;          /* VCLB_D2Q9 | VCLB_D3Q19                                     */
   int32_t storage;          /* VCLB_FP64 | VCLB_FP32 | VCLB_FP16S                          */
   int32_t mode;             /* VCLB_COUPLED | VCLB_PRESCRIBED_VORTEX (D2Q9 only)           */
   int32_t nx, ny, nz;       /* nodes per axis; nz = 1 for D2Q9                             */
-  int32_t bc_y;             /* VCLB_PERIODIC | VCLB_WALL (x and z are always periodic)     */
+  int32_t bc[3][2];         /* boundary type of each face: VCLB_PERIODIC | VCLB_WALL.  Both
+                               faces of an axis must have the same type.  Supported: walls
+                               on the y faces of D2Q9 (ny >= 2); every other face periodic
+                               (VCLB_EINVAL otherwise).                                    */
   int32_t nlabels;          /* 0: one label covering the domain; else 1..VCLB_MAX_LABELS   */
-  double  wall_u_bottom[3]; /* velocity of the wall below y = 0 (VCLB_WALL)                */
-  double  wall_u_top[3];    /* velocity of the wall above y = ny - 1                       */
+  double  wall_u[3][2][3];  /* velocity of the wall on each VCLB_WALL face (ignored on
+                               periodic faces); its normal component must be 0            */
   double  W;                /* interface width (Eq. 4), > 0                                 */
   double  sigma;            /* surface tension, >= 0 (beta = 12 sigma / W, kappa = 3 sigma W / 2) */
   double  mobility;         /* M > 0; tau_g = 1/2 + M / c_s^2 (Eq. 34)                      */
@@ -100,7 +105,15 @@ typedef struct {
   double  eps_n;            /* unit normal n = grad psi / sqrt(|grad psi|^2 + eps_n^2), >= 0 */
   double  rho_heavy;        /* density at phi = 1, > 0                                      */
   double  rho_light;        /* density at phi = 0, > 0                                      */
-  double  nu;               /* kinematic viscosity > 0; tau_f = 1/2 + nu / c_s^2 (Eq. 27)   */
+  double  nu_heavy;         /* kinematic viscosity of the heavy phase (phi = 1), > 0        */
+  double  nu_light;         /* kinematic viscosity of the light phase (phi = 0), > 0.  The
+                               dynamic viscosity mu = rho nu is interpolated linearly in phi
+                               between rho_light nu_light and rho_heavy nu_heavy, and each
+                               node relaxes the stress moments of f at 1 / tau_f with
+                               tau_f = 1/2 + mu(phi) / (rho(phi) c_s^2) (Eq. 27).  Equal
+                               viscosities give one uniform tau_f.  Unequal ones are
+                               supported by the single-case steps (not by batches or the
+                               adjoint) and need the stress rates of s_f left at 0.       */
   double  s_g[19];          /* MRT rates of g in (0, 2); 0 selects the default              */
   double  s_f[19];          /* MRT rates of f in (0, 2); 0 selects the default              */
   double  U0;               /* vortex amplitude (Eqs. 43-44)                                 */
@@ -212,9 +225,28 @@ int vclb_case_time(vclb_case* c, int64_t* t, void* stream);
 /* Macroscopic fields of the current state, in FP64, in VCLB_FIELD_* bit order. */
 int vclb_observe(vclb_case* c, uint32_t field_mask, double* out, int ptr_kind, void* stream);
 
-/* Volume reductions of the current state into out[nlabels] (host memory).
-   Returns VCLB_ENONFINITE (after filling out) if any label saw a NaN/Inf. */
-int vclb_reduce(vclb_case* c, vclb_obs* out, void* stream);
+/* Volume reductions of the current state (observables of the order parameter, Eq. 35:
+   the correction term of Eq. 32 is local and takes no global quantity), accumulated in
+   FP64, one vclb_obs per label into out[] (host memory, caller-owned).
+
+   labels == NULL: the case's built-in labels (nearest label centre by minimum image, or
+   one label covering the domain); nlabels is 0 or that label count; d in vclb_obs is the
+   displacement from the label's centre.
+
+   labels != NULL: caller labels, labels[n] for node n (device memory, N int32, row-major
+   with x fastest, read only), 1 <= nlabels <= 2^20 and out[nlabels].  A node with a
+   negative label belongs to no label.  d is the node's position (x, y, z) (no wrap), so
+   sum_phi_d and sum_phi_dd are moments about the origin.  out[l].label = l.  The
+   reductions are deterministic (fixed-order sums); a workgroup's cost grows with the
+   number of distinct labels in its chunk of nodes, so labels should be spatially
+   coherent (for example connected regions).  The library allocates device scratch for
+   the partial sums on the first call that needs more than the case holds (kept until
+   vclb_case_destroy).  Returns VCLB_EINVAL (after filling out) if some node's label is
+   >= nlabels.
+
+   Returns VCLB_ENONFINITE (after filling out) if any label saw a NaN/Inf.  Synchronises
+   the stream. */
+int vclb_reduce(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* out, void* stream);
 
 /* Copy the recorded per-step reductions of steps [t_first, t_first + count) into
    out[count * nlabels] (host).  Steps older than VCLB_HISTORY or never recorded give

@@ -12,7 +12,7 @@ least one closed form, invariant, special case or brute-force check, except wher
 docstring says "parity unpinned".
 """
 from .lattice import D2Q9, D3Q19, Lattice, lattice_for
-from .model import Model, observables_from_phi, derived_observables
+from .model import Model, observables_from_phi, observables_by_labels, derived_observables
 
 __all__ = ["D2Q9", "D3Q19", "Lattice", "lattice_for", "Model", "observables_from_phi",
-           "derived_observables"]
+           "derived_observables", "observables_by_labels"]

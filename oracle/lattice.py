@@ -104,6 +104,12 @@ def lattice_for(name: str) -> Lattice:
     return {"D2Q9": D2Q9, "D3Q19": D3Q19}[name]
 
 
+def stress_rows(lat: Lattice):
+    """The moment rows of f that carry the traceless stress (they relax at 1/tau_f,
+    Eq. 27): p_xx and p_xy of Eq. 24 in D2Q9; 3p_xx, p_ww, p_xy, p_yz, p_xz in D3Q19."""
+    return (7, 8) if lat.name == "D2Q9" else (9, 11, 13, 14, 15)
+
+
 def default_rates(lat: Lattice, tau: float, which: str):
     """Diagonal relaxation rates.
 
@@ -114,10 +120,10 @@ def default_rates(lat: Lattice, tau: float, which: str):
     Eq. 30; for f the shear-stress moments relax at 1/tau_f; every other rate is 1.
     """
     s = [1.0 + 0.0 * tau] * lat.Q
-    if lat.name == "D2Q9":
-        rows = (3, 4, 5, 6) if which == "g" else (7, 8)
+    if which == "f":
+        rows = stress_rows(lat)
     else:
-        rows = (3, 4, 5, 6, 7, 8) if which == "g" else (9, 11, 13, 14, 15)
+        rows = (3, 4, 5, 6) if lat.name == "D2Q9" else (3, 4, 5, 6, 7, 8)
     for r in rows:
         s[r] = 1.0 / tau
     return s

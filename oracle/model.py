@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .lattice import default_rates, lattice_for
+from .lattice import default_rates, lattice_for, stress_rows
 
 
 def _clip01(phi):
@@ -66,6 +66,12 @@ class Model:
         # Eq. 34: M = cs^2 (tau_g - 1/2);  Eq. 27 with mu = rho nu: nu = cs^2 (tau_f - 1/2).
         self.tau_g = 0.5 + mob / self.cs2
         self.tau_f = 0.5 + p.nu / self.cs2
+        # Unequal viscosities of the two phases (Sect. 4.1 names the dynamic viscosity
+        # ratio mu_l / mu_g): tau_f follows Eq. 27 node by node (see tau_f_of).
+        nu_l = getattr(p, "nu_light", None)
+        self.visc = nu_l is not None and nu_l != p.nu
+        self.mu_heavy = p.rho_heavy * p.nu
+        self.mu_light = p.rho_light * (p.nu if nu_l is None else nu_l)
         sg = default_rates(lat, self.tau_g, "g")
         sf = default_rates(lat, self.tau_f, "f")
         if p.s_g:
@@ -127,6 +133,14 @@ class Model:
         rho_heavy at phi = 1 (a reading: the paper gives only the density ratio)."""
         p = self.p
         return p.rho_light + phi * (p.rho_heavy - p.rho_light)
+
+    def tau_f_of(self, phi, rho):
+        """Per-node relaxation time of f, Eq. 27: mu = rho c_s^2 (tau_f - 1/2), with the
+        dynamic viscosity interpolated linearly in the (unclipped) order parameter
+        between the light (phi = 0) and heavy (phi = 1) phases, as the density is (a
+        reading: the paper names the viscosity ratio but not the interpolation)."""
+        mu = self.mu_light + phi * (self.mu_heavy - self.mu_light)
+        return 0.5 + mu / (rho * self.cs2)
 
     def psi_of(self, phi):
         """Regularised signed distance, Eq. 37, evaluated on the clipped phi."""
@@ -236,14 +250,32 @@ class Model:
 
     def mrt(self, pop, eq, src, S):
         """Moment-space collision, Eqs. 25/33: m* = m - S (m - m_eq) + (I - S/2) src_bar,
-        back to velocity space with M^{-1}."""
+        back to velocity space with M^{-1}.  S is the diagonal rate matrix, or an array of
+        rates per moment row and node, shape (Q, ...) like pop."""
         Q = self.lat.Q
         shp = pop.shape
         m = self.M @ pop.reshape(Q, -1)
         meq = self.M @ eq.reshape(Q, -1)
         sb = self.M @ src.reshape(Q, -1)
-        mstar = m - S @ (m - meq) + (self.I - 0.5 * S) @ sb
+        if S.shape == (Q, Q):
+            mstar = m - S @ (m - meq) + (self.I - 0.5 * S) @ sb
+        else:
+            s = S.reshape(Q, -1)
+            mstar = m - s * (m - meq) + (1.0 - 0.5 * s) * sb
         return (self.Minv @ mstar).reshape(shp)
+
+    def f_rates(self, phi, rho):
+        """Rates of the f collision: the constant S^f, or with unequal viscosities the
+        same rates per node with the stress rows at 1 / tau_f(phi) (Eq. 27)."""
+        if not self.visc:
+            return self.Sf
+        Q = self.lat.Q
+        s = np.broadcast_to(np.diag(self.Sf).reshape((Q,) + (1,) * phi.ndim), (Q,) + phi.shape).copy()
+        s = s.astype(np.result_type(phi, s))
+        tau = self.tau_f_of(phi, rho)
+        for k in stress_rows(self.lat):
+            s[k] = 1.0 / tau
+        return s
 
     # ------------------------------------------------------------------ streaming
     def stream(self, post, rho=None, moving=False):
@@ -310,7 +342,7 @@ class Model:
             if p.mode == "coupled":
                 feq = self.f_equilibrium(F["p"], F["rho"], u)     # Eqs. 22, 23
                 Fi = self.f_forcing(u, F["grho"], F["Fs"])        # Eq. 21
-                fstar = self.mrt(self.f, feq, Fi, self.Sf)        # Eq. 25
+                fstar = self.mrt(self.f, feq, Fi, self.f_rates(phi, F["rho"]))   # Eq. 25
                 self.f = self.stream(fstar, rho=F["rho"], moving=True)
             self.g = self.stream(gstar)
             self.t += 1
@@ -386,3 +418,27 @@ def derived_observables(obs, cents=None):
     with np.errstate(invalid="ignore"):
         D = (np.sqrt(lp) - np.sqrt(lm)) / (np.sqrt(lp) + np.sqrt(lm))
     return dict(volume=V, centroid=c, D=D, count_half=obs["count_half"])
+
+
+def observables_by_labels(phi, labels, nlabels):
+    """Volume reductions of a phase field over caller-given labels: for each label l the
+    sums over the nodes with labels == l of phi, of #(phi >= 1/2), of phi x and of
+    phi x x^T (x = the node's position (i, j, k), moments about the origin), and whether
+    phi is non-finite somewhere; nodes with a negative label belong to no label.  Second
+    moments are ordered xx, yy, zz, xy, xz, yz."""
+    phi = np.asarray(phi)
+    labels = np.asarray(labels).reshape(phi.shape)
+    nz, ny, nx = phi.shape
+    Z, Y, X = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    res = {k: [] for k in ("sum_phi", "count_half", "sum_phi_d", "sum_phi_dd", "nonfinite")}
+    for k in range(nlabels):
+        m = labels == k
+        ph, x, y, z = phi[m], X[m], Y[m], Z[m]
+        res["sum_phi"].append(ph.sum())
+        res["count_half"].append(int((np.real(ph) >= 0.5).sum()))
+        res["sum_phi_d"].append([(ph * x).sum(), (ph * y).sum(), (ph * z).sum()])
+        res["sum_phi_dd"].append([(ph * x * x).sum(), (ph * y * y).sum(), (ph * z * z).sum(),
+                                  (ph * x * y).sum(), (ph * x * z).sum(), (ph * y * z).sum()])
+        res["nonfinite"].append(int(not np.all(np.isfinite(ph))))
+    return {k: np.array(v) for k, v in res.items()}

@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libvclb.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "kernels3d.hip", "batch.hip", "adjoint.hip", "probe.hip", "abi.cpp"]
+SOURCES = ["kernels.hip", "kernels3d.hip", "batch.hip", "adjoint.hip", "probe.hip", "reduce.hip", "abi.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-mcode-object-version=5",

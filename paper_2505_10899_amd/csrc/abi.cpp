@@ -17,6 +17,7 @@
 #include "adjoint.hpp"
 #include "launch.hpp"
 #include "probe.hpp"
+#include "reduce.hpp"
 
 namespace {
 
@@ -47,11 +48,16 @@ int lattice_d(int lattice) { return lattice == VCLB_D2Q9 ? 2 : 3; }
 size_t storage_bytes(int storage) { return storage == VCLB_FP64 ? 8 : (storage == VCLB_FP32 ? 4 : 2); }
 size_t arith_bytes(int storage) { return storage == VCLB_FP64 ? 8 : 4; }
 
-// relaxation rates with defaults filled in (see lattice.hpp)
+bool wall_y(const vclb_params& p) { return p.bc[1][0] == VCLB_WALL; }
+// unequal viscosities of the two phases: tau_f differs from node to node (Eq. 27)
+bool visc_ratio(const vclb_params& p) { return p.nu_heavy != p.nu_light; }
+
+// relaxation rates with defaults filled in (see lattice.hpp).  With unequal viscosities
+// the f stress rows get the heavy phase's rate here; the kernels replace it per node.
 void fill_rates(const vclb_params& p, double* sg, double* sf) {
   const int Q = lattice_q(p.lattice);
   const double tau_g = 0.5 + p.mobility * 3.0;   // Eq. 34, c_s^2 = 1/3
-  const double tau_f = 0.5 + p.nu * 3.0;         // Eq. 27 with mu = rho nu
+  const double tau_f = 0.5 + p.nu_heavy * 3.0;   // Eq. 27 with mu = rho nu
   for (int k = 0; k < Q; ++k) {
     bool gflux, fstress;
     if (p.lattice == VCLB_D2Q9) {
@@ -77,9 +83,15 @@ int validate(const vclb_params* p) {
   if (p->lattice == VCLB_D2Q9 && p->nz != 1) return fail(VCLB_EINVAL, "D2Q9 needs nz = 1");
   const double nn = double(p->nx) * p->ny * p->nz;
   if (nn > double(INT32_MAX)) return fail(VCLB_EINVAL, "more than 2^31 - 1 nodes");
-  if (p->bc_y != VCLB_PERIODIC && p->bc_y != VCLB_WALL) return fail(VCLB_EINVAL, "unknown bc_y");
-  if (p->bc_y == VCLB_WALL && p->lattice != VCLB_D2Q9) return fail(VCLB_EINVAL, "walls are D2Q9-only");
-  if (p->bc_y == VCLB_WALL && p->ny < 2) return fail(VCLB_EINVAL, "walls need ny >= 2");
+  for (int a = 0; a < 3; ++a) {
+    for (int sd = 0; sd < 2; ++sd)
+      if (p->bc[a][sd] != VCLB_PERIODIC && p->bc[a][sd] != VCLB_WALL) return fail(VCLB_EINVAL, "unknown boundary type");
+    if (p->bc[a][0] != p->bc[a][1]) return fail(VCLB_EINVAL, "both faces of an axis must have the same boundary type");
+  }
+  if (p->bc[0][0] == VCLB_WALL) return fail(VCLB_EINVAL, "walls on the x faces are not supported (x is periodic)");
+  if (p->bc[2][0] == VCLB_WALL) return fail(VCLB_EINVAL, "walls on the z faces are not supported (z is periodic)");
+  if (p->bc[1][0] == VCLB_WALL && p->lattice != VCLB_D2Q9) return fail(VCLB_EINVAL, "walls are D2Q9-only");
+  if (p->bc[1][0] == VCLB_WALL && p->ny < 2) return fail(VCLB_EINVAL, "walls need ny >= 2");
   if (p->nlabels < 0 || p->nlabels > VCLB_MAX_LABELS) return fail(VCLB_EINVAL, "nlabels out of range");
   if (!(finite(p->W) && p->W > 0)) return fail(VCLB_EINVAL, "W must be > 0");
   if (!(finite(p->sigma) && p->sigma >= 0)) return fail(VCLB_EINVAL, "sigma must be >= 0");
@@ -89,7 +101,8 @@ int validate(const vclb_params* p) {
   if (!(finite(p->eps_n) && p->eps_n >= 0)) return fail(VCLB_EINVAL, "eps_n must be >= 0");
   if (!(finite(p->rho_heavy) && p->rho_heavy > 0)) return fail(VCLB_EINVAL, "rho_heavy must be > 0");
   if (!(finite(p->rho_light) && p->rho_light > 0)) return fail(VCLB_EINVAL, "rho_light must be > 0");
-  if (!(finite(p->nu) && p->nu > 0)) return fail(VCLB_EINVAL, "nu must be > 0");
+  if (!(finite(p->nu_heavy) && p->nu_heavy > 0)) return fail(VCLB_EINVAL, "nu_heavy must be > 0");
+  if (!(finite(p->nu_light) && p->nu_light > 0)) return fail(VCLB_EINVAL, "nu_light must be > 0");
   const int Q = lattice_q(p->lattice);
   for (int k = 0; k < 19; ++k) {
     const bool used = k < Q;
@@ -99,13 +112,26 @@ int validate(const vclb_params* p) {
         return fail(VCLB_EINVAL, "relaxation rates must lie in (0, 2)");
     }
   }
+  if (visc_ratio(*p)) {
+    if (p->mode != VCLB_COUPLED) return fail(VCLB_EINVAL, "a viscosity ratio needs the coupled mode");
+    for (int k = 0; k < Q; ++k) {
+      const bool stress = p->lattice == VCLB_D2Q9 ? vclb::D2Q9::f_stress_row[k] : vclb::D3Q19::f_stress_row[k];
+      if (stress && p->s_f[k] != 0.0)
+        return fail(VCLB_EINVAL, "with unequal viscosities the stress rates of f follow Eq. 27 per node: leave them 0");
+    }
+  }
   double sg[19], sf[19];
   fill_rates(*p, sg, sf);
   for (int k = 0; k < Q; ++k)
     if (!(sg[k] > 0 && sg[k] < 2 && sf[k] > 0 && sf[k] < 2))
       return fail(VCLB_EINVAL, "derived relaxation rate outside (0, 2)");
   for (int a = 0; a < 3; ++a)
-    if (!finite(p->wall_u_bottom[a]) || !finite(p->wall_u_top[a])) return fail(VCLB_EINVAL, "wall velocity");
+    for (int sd = 0; sd < 2; ++sd)
+      for (int d = 0; d < 3; ++d) {
+        if (!finite(p->wall_u[a][sd][d])) return fail(VCLB_EINVAL, "wall velocity not finite");
+        if (p->bc[a][sd] == VCLB_WALL && d == a && p->wall_u[a][sd][d] != 0.0)
+          return fail(VCLB_EINVAL, "a wall's velocity must be tangential (zero normal component)");
+      }
   if (p->mode == VCLB_PRESCRIBED_VORTEX && !(finite(p->T) && p->T > 0 && finite(p->U0)))
     return fail(VCLB_EINVAL, "vortex needs T > 0 and a finite U0");
   for (int k = 0; k < p->nlabels; ++k)
@@ -178,6 +204,8 @@ struct vclb_case {
   int pend_nb = 0, pend_buf = 0;
   int64_t pend_step = 0;
   struct AdjStore* adj = nullptr;   // recorded forward pass of the adjoint (FP64 D2Q9 only)
+  void* lab_scratch = nullptr;       // scratch of the caller-label reductions (grown on demand)
+  size_t lab_scratch_bytes = 0;
 };
 
 namespace {
@@ -196,7 +224,8 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   d.ny = p.ny;
   d.nz = p.nz;
   d.n = long(p.nx) * p.ny * p.nz;
-  d.wall = p.bc_y == VCLB_WALL;
+  d.wall = wall_y(p);
+  d.visc = visc_ratio(p) ? 1 : 0;
   d.nl = std::max(1, p.nlabels);
   d.unit_rates = 1;
   for (int k = 0; k < L::Q; ++k)
@@ -209,7 +238,7 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
       // periodic axes: the minimum-image displacement is periodic in the centre, so the
       // centre is moved into [0, n) (the kernels rely on it to wrap without a division)
       const int na = a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
-      const bool periodic = !(a == 1 && p.bc_y == VCLB_WALL);
+      const bool periodic = p.bc[a][0] == VCLB_PERIODIC;
       if (periodic) v = v - na * std::floor(v / na);
       d.cen[k][a] = v;
     }
@@ -248,6 +277,8 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   np.eps2 = R(p.eps_n * p.eps_n);
   np.rho_l = R(p.rho_light);
   np.drho = R(p.rho_heavy - p.rho_light);
+  np.mu_l = R(p.rho_light * p.nu_light);
+  np.dmu = R(p.rho_heavy * p.nu_heavy - p.rho_light * p.nu_light);
   for (int k = 0; k < L::Q; ++k) {
     np.sg[k] = R(c.sg[k] / vclb::row_norm<L>(k));
     np.sf[k] = R(c.sf[k] / vclb::row_norm<L>(k));
@@ -257,8 +288,10 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
     // moving-wall term 2 w_i rho (c_i . u_wall) / cs^2 of the incoming direction i = opp(k),
     // stored on the outgoing direction k at the first (bottom) / last (top) y row
     const int i = L::opp[k];
-    const double cub = L::cx[i] * p.wall_u_bottom[0] + L::cy[i] * p.wall_u_bottom[1] + L::cz[i] * p.wall_u_bottom[2];
-    const double cut = L::cx[i] * p.wall_u_top[0] + L::cy[i] * p.wall_u_top[1] + L::cz[i] * p.wall_u_top[2];
+    const double* ub = p.wall_u[1][0];
+    const double* ut = p.wall_u[1][1];
+    const double cub = L::cx[i] * ub[0] + L::cy[i] * ub[1] + L::cz[i] * ub[2];
+    const double cut = L::cx[i] * ut[0] + L::cy[i] * ut[1] + L::cz[i] * ut[2];
     np.wb[k] = R(L::cy[k] < 0 ? 2.0 * L::w[i] * cub * 3.0 : 0.0);
     np.wt[k] = R(L::cy[k] > 0 ? 2.0 * L::w[i] * cut * 3.0 : 0.0);
   }
@@ -476,6 +509,7 @@ int vclb_case_create(const vclb_params* p, void* workspace, size_t workspace_byt
 void vclb_case_destroy(vclb_case* c) {
   if (!c) return;
   adj_release(c);
+  if (c->lab_scratch) (void)hipFree(c->lab_scratch);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   delete c;
 }
@@ -674,7 +708,7 @@ int vclb_case_autotune(vclb_case* c, const char* cache_path, int32_t steps, void
   const vclb_params& p = c->p;
   const std::string desc = "case:" + std::to_string(p.lattice) + ":" + std::to_string(p.storage) + ":" +
                            std::to_string(p.mode) + ":" + std::to_string(p.nx) + "x" + std::to_string(p.ny) + "x" +
-                           std::to_string(p.nz) + (p.bc_y == VCLB_WALL ? "w" : "p") + std::to_string(std::max(1, p.nlabels));
+                           std::to_string(p.nz) + (wall_y(p) ? "w" : "p") + std::to_string(std::max(1, p.nlabels));
   char key[32];
   std::snprintf(key, sizeof(key), "%016llx", static_cast<unsigned long long>(fnv1a(desc.data(), desc.size())));
   if (cache_path) {
@@ -838,8 +872,70 @@ static void unpack_obs(const double* v, int nl, vclb_obs* out) {
   (void)bad;
 }
 
-int vclb_reduce(vclb_case* c, vclb_obs* out, void* stream) {
+}  // extern "C"
+
+namespace {
+constexpr int32_t kMaxCallerLabels = 1 << 20;
+
+// checks shared by the caller-label reductions
+int label_args(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* out) {
+  if (!c || !out || !labels) return fail(VCLB_EINVAL, "NULL argument");
+  if (nlabels < 1 || nlabels > kMaxCallerLabels) return fail(VCLB_EINVAL, "nlabels must lie in 1..2^20");
+  if (!c->inited) return fail(VCLB_ESTATE, "reduce before init");
+  return VCLB_OK;
+}
+
+// phi of the current state into the case's scratch, then the label reductions into
+// `scratch` (label_scratch_bytes), results copied to out; synchronises the stream
+int label_reduce_into(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* out, void* scratch,
+                      hipStream_t s) {
+  if (int rc0 = flush_pending(c, s)) return rc0;
+  const long n = long(c->p.nx) * c->p.ny * c->p.nz;
+  int rc = dispatch(*c, [&](auto dc, auto) {
+    using DC = decltype(dc);
+    using L = typename DevTraits<DC>::L;
+    using St = typename DevTraits<DC>::St;
+    int r = vclb::launch_phi_psi<L, St>(dc, s);
+    if (r) return r;
+    return vclb::launch_label_reduce(dc.tmp_phi, labels, n, c->p.nx, c->p.ny, nlabels, long(c->t_host), scratch, s);
+  });
+  if (rc) return fail(VCLB_EHIP, "label reduction launch failed");
+  const char* res = static_cast<const char*>(scratch) + vclb::label_result_offset(n, nlabels);
+  double bad = 0.0;
+  HIP_TRY(hipMemcpyAsync(out, res, size_t(nlabels) * sizeof(vclb_obs), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&bad, res + size_t(nlabels) * sizeof(vclb_obs), sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (bad > 0.0) return fail(VCLB_EINVAL, std::to_string(int64_t(bad)) + " node label(s) >= nlabels");
+  for (int k = 0; k < nlabels; ++k)
+    if (out[k].nonfinite) return fail(VCLB_ENONFINITE, "phi has a NaN/Inf");
+  return VCLB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int vclb_reduce(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* out, void* stream) {
+  if (labels) {
+    if (int rc = label_args(c, labels, nlabels, out)) return rc;
+    const long n = long(c->p.nx) * c->p.ny * c->p.nz;
+    const size_t need = vclb::label_scratch_bytes(n, nlabels);
+    hipStream_t s = as_stream(stream);
+    if (c->lab_scratch_bytes < need) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if (c->lab_scratch) (void)hipFree(c->lab_scratch);
+      c->lab_scratch = nullptr;
+      c->lab_scratch_bytes = 0;
+      if (hipMalloc(&c->lab_scratch, need) != hipSuccess) {
+        c->lab_scratch = nullptr;
+        return fail(VCLB_ENOMEM, "label reduction scratch");
+      }
+      c->lab_scratch_bytes = need;
+    }
+    return label_reduce_into(c, labels, nlabels, out, c->lab_scratch, s);
+  }
   if (!c || !out) return fail(VCLB_EINVAL, "NULL argument");
+  if (nlabels != 0 && nlabels != std::max(1, c->p.nlabels))
+    return fail(VCLB_EINVAL, "with the built-in labels nlabels is 0 or the case's label count");
   if (!c->inited) return fail(VCLB_ESTATE, "reduce before init");
   hipStream_t s = as_stream(stream);
   if (int rc0 = flush_pending(c, s)) return rc0;
@@ -1278,6 +1374,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
       return fail(VCLB_EINVAL, "batches hold coupled D2Q9 cases");
     if (cases[k].storage != cases[0].storage) return fail(VCLB_EINVAL, "every case of a batch has one storage");
     if (cases[k].nlabels > 1) return fail(VCLB_EINVAL, "batched cases have one observation label");
+    if (visc_ratio(cases[k])) return fail(VCLB_EINVAL, "batched cases have one viscosity (nu_heavy = nu_light)");
     if (double(cases[k].nx + 2) * (cases[k].ny + 2) >= double(1 << 24))
       return fail(VCLB_EINVAL, "batched cases hold fewer than 2^24 padded nodes");
   }
@@ -1698,7 +1795,7 @@ int vclb_batch_autotune(vclb_batch* b, const char* cache_path, int32_t steps, vo
   // key: storage and every case's shape and boundary
   std::string desc = "s" + std::to_string(b->storage);
   for (vclb_case* c : b->cases)
-    desc += ":" + std::to_string(c->p.nx) + "x" + std::to_string(c->p.ny) + (c->p.bc_y == VCLB_WALL ? "w" : "p");
+    desc += ":" + std::to_string(c->p.nx) + "x" + std::to_string(c->p.ny) + (wall_y(c->p) ? "w" : "p");
   char key[32];
   std::snprintf(key, sizeof(key), "%016llx", static_cast<unsigned long long>(fnv1a(desc.data(), desc.size())));
   if (cache_path) {
@@ -1877,6 +1974,7 @@ AdjStore adj_layout(const vclb_params& p, int64_t nsteps, int32_t every) {
 int adj_check_case(const vclb_case* c) {
   if (c->p.lattice != VCLB_D2Q9 || c->p.storage != VCLB_FP64 || c->p.mode != VCLB_COUPLED)
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
+  if (visc_ratio(c->p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
   return VCLB_OK;
 }
 
@@ -1947,6 +2045,7 @@ int vclb_adjoint_bytes(const vclb_params* p, int64_t nsteps, int32_t every, size
   if (!bytes || nsteps < 0 || every < 0) return fail(VCLB_EINVAL, "bad argument");
   if (p->lattice != VCLB_D2Q9 || p->storage != VCLB_FP64 || p->mode != VCLB_COUPLED)
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
+  if (visc_ratio(*p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
   if (every == 0) every = adj_default_every(nsteps);
   *bytes = adj_layout(*p, nsteps, every).total;
   return VCLB_OK;

@@ -22,6 +22,7 @@ struct DevCase {
   int wall;                     // bounce-back walls bound y
   int nl;                       // labels (1..kMaxLabels)
   int unit_rates;               // every rate outside the g flux and f stress rows is 1
+  int visc;                     // the phases have different viscosities (per-node tau_f)
   double cen[kMaxLabels][3];    // label centres
   S* pop[2][2];                 // [g = 0, f = 1][buffer]; f is null in vortex mode
   R* J;                         // previous phi u, D * n

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) k_collide_plain(DevCase<L, St> c, int red
 #pragma unroll
     for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
     NodeOut<L, R> out;
-    node_update<L, R, COUPLED, St::shifted>(c.np, in, g, f, J, out);
+    node_update_any<L, R, COUPLED, St::shifted>(c.np, c.visc != 0, in, g, f, J, out);
     store_node<L, St, COUPLED>(c, par, n, y, in.nphi[0], out.rho, g, f, J);
     if (reduce) accumulate(c, acc, double(in.nphi[0]), x, y, z);
   }
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_fields(DevCase<L, St> c, unsigned mask,
 #pragma unroll
   for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
   NodeOut<L, R> o;
-  node_update<L, R, COUPLED, St::shifted>(c.np, in, g, f, J, o);
+  node_update_any<L, R, COUPLED, St::shifted>(c.np, c.visc != 0, in, g, f, J, o);
   long off = 0;
   if (mask & 0x01u) { out[off + n] = double(in.nphi[0]); off += c.n; }
   if (mask & 0x02u) { out[off + n] = double(o.rho); off += c.n; }
@@ -263,7 +263,7 @@ constexpr int step2d_min_blocks() {
   return waves / (BS / 256) > 0 ? waves / (BS / 256) : 1;
 }
 
-template <class St, bool COUPLED, class IX, bool UNIT, int BS>
+template <class St, bool COUPLED, class IX, bool UNIT, int BS, bool VISC>
 __global__ void __launch_bounds__(BS, (step2d_min_blocks<St, UNIT, BS>()))
     k_step2d(DevCase<D2Q9, St> c, int TY, int nseg, int reduce) {
   extern __shared__ unsigned char smem_raw[];
@@ -274,8 +274,8 @@ __global__ void __launch_bounds__(BS, (step2d_min_blocks<St, UNIT, BS>()))
   const int nstrips = gridDim.x / nseg;
   const int seg = tile / nstrips, strip = tile - seg * nstrips;
   const int y0 = seg * TY;
-  step2d_tile<St, COUPLED, IX, UNIT>(c, c.t, strip * int(blockDim.x), y0, min(y0 + TY, c.ny), reduce != 0,
-                                     c.part_w, gridDim.x, blockIdx.x, smem_raw);
+  step2d_tile<St, COUPLED, IX, UNIT, VISC>(c, c.t, strip * int(blockDim.x), y0, min(y0 + TY, c.ny), reduce != 0,
+                                           c.part_w, gridDim.x, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------- second reduction pass
@@ -333,20 +333,31 @@ int launch_step_fused(const DevCase<L, St>& c, const Tile& tile, int reduce, hip
     // strips wider than 256 lanes (512 or 1024) take the 1024-lane instantiation, which
     // exists for 4-byte arithmetic only
     bool bad_shape = false;
-    auto go = [&](auto ix, auto unit) {
+    auto go = [&](auto ix, auto unit, auto visc) {
+      constexpr bool U = decltype(unit)::value, V = decltype(visc)::value;
       if (tile.bx <= 256) {
-        hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), decltype(unit)::value, 256>), grid, block, lds, s, c,
-                           tile.ty, nseg, reduce);
+        hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), U, 256, V>), grid, block, lds, s, c, tile.ty, nseg,
+                           reduce);
       } else if constexpr (sizeof(typename St::R) == 4) {
-        hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), decltype(unit)::value, 1024>), grid, block, lds, s, c,
-                           tile.ty, nseg, reduce);
+        hipLaunchKernelGGL((k_step2d<St, COUPLED, decltype(ix), U, 1024, V>), grid, block, lds, s, c, tile.ty, nseg,
+                           reduce);
       } else {
         bad_shape = true;
       }
     };
+    // per-node tau_f only where the phases' viscosities differ (coupled cases)
+    auto pick_visc = [&](auto ix, auto unit) {
+      if constexpr (COUPLED) {
+        if (c.visc) {
+          go(ix, unit, std::true_type{});
+          return;
+        }
+      }
+      go(ix, unit, std::false_type{});
+    };
     auto pick = [&](auto ix) {
-      if (c.unit_rates) go(ix, std::true_type{});
-      else go(ix, std::false_type{});
+      if (c.unit_rates) pick_visc(ix, std::true_type{});
+      else pick_visc(ix, std::false_type{});
     };
     if constexpr (std::is_same<St, StoreF16S>::value) {
       if (c.n < (1L << 29)) pick(0u);
@@ -422,6 +433,11 @@ VCLB_INSTANTIATE(D3Q19, StoreF32, true)
 VCLB_INSTANTIATE(D3Q19, StoreF16S, true)
 template int launch_reduce_state<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
 template int launch_phi_psi<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
+template int launch_phi_psi<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
+template int launch_phi_psi<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);
+template int launch_phi_psi<D3Q19, StoreF64>(const DevCase<D3Q19, StoreF64>&, hipStream_t);
+template int launch_phi_psi<D3Q19, StoreF32>(const DevCase<D3Q19, StoreF32>&, hipStream_t);
+template int launch_phi_psi<D3Q19, StoreF16S>(const DevCase<D3Q19, StoreF16S>&, hipStream_t);
 template int launch_finalize<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
 template int launch_finalize<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
 template int launch_finalize<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);

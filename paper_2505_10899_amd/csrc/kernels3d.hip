@@ -75,7 +75,8 @@ constexpr int step3d_min_blocks() {
 
 // NL: labels of the volume reductions (1 or 2), fixed per case; UNIT: the case's rates
 // outside the g flux and f stress rows are all 1
-template <class St, int NL, bool UNIT, class IX, int BS>
+// VISC: the phases have different viscosities (per-node tau_f of the stress rows)
+template <class St, int NL, bool UNIT, class IX, int BS, bool VISC>
 __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(DevCase<D3Q19, St> c, int BX, int BY,
                                                                             int nby, int nbz, int reduce) {
   using L = D3Q19;
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
         if (L::cz[i] != 0) { st.gphi[2] += R(3.0 * L::w[i] * L::cz[i]) * ph; st.gpsi[2] += R(3.0 * L::w[i] * L::cz[i]) * ps; }
       }
       NodeOut<L, R> out;
-      node_update_mom_s<L, R, true, St::shifted, UNIT>(c.np, st, gcur, f, J, out);
+      node_update_mom_s<L, R, true, St::shifted, UNIT, VISC>(c.np, st, gcur, f, J, out);
       const int dst = par ^ 1;
       R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
 #pragma unroll
@@ -296,15 +297,16 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   const size_t lds = step3d_lds_bytes<St>(tile.bx, tile.by3);
   const dim3 grid(nbx * nby * nbz), block(lanes);
   int rc = 0;
-  auto go = [&](auto nl, auto unit, auto ix) {
+  auto go = [&](auto nl, auto unit, auto ix, auto visc) {
+    constexpr bool V = decltype(visc)::value;
     if (lanes <= 256) {
-      hipLaunchKernelGGL((k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 256>), grid, block,
+      hipLaunchKernelGGL((k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 256, V>), grid, block,
                          lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
     } else if constexpr (stage3d<St>()) {
       // wide sections stage more than the default 64 KiB of dynamic LDS: raise this
       // instantiation's limit to the device maximum once per device (the tile check has
       // compared the section with that maximum)
-      auto kern = k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 768>;
+      auto kern = k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 768, V>;
       static int raised[64] = {};   // per instantiation and device; a repeated raise is harmless
       int dev = 0, max_lds = 0;
       if (hipGetDevice(&dev) != hipSuccess) {
@@ -327,7 +329,10 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   using Two = std::integral_constant<int, 2>;
   // 64-bit indexing: the 32-bit byte-offset form (unsigned IX) measured 0.5% slower in
   // FP32 and 5.6% slower in FP16S on this kernel (and equal in FP64)
-  auto pick_ix = [&](auto nl, auto unit) { go(nl, unit, 0L); };
+  auto pick_ix = [&](auto nl, auto unit) {
+    if (c.visc) go(nl, unit, 0L, std::true_type{});
+    else go(nl, unit, 0L, std::false_type{});
+  };
   auto pick_unit = [&](auto nl) {
     if (c.unit_rates) pick_ix(nl, std::true_type{});
     else pick_ix(nl, std::false_type{});

@@ -117,6 +117,8 @@ struct NodeParams {
   R eps2;        // eps_n^2
   R rho_l;       // rho at phi = 0
   R drho;        // rho_heavy - rho_light
+  R mu_l;        // dynamic viscosity at phi = 0, rho_light nu_light
+  R dmu;         // rho_heavy nu_heavy - rho_light nu_light
   R sg[L::Q];    // s_k^g / |M_k|^2
   R sf[L::Q];    // s_k^f / |M_k|^2
   R wb[L::Q];    // moving-wall term for outgoing direction o at the first y row (times rho)
@@ -198,6 +200,14 @@ struct NodeOut {
   R u[L::D];
 };
 
+// Relaxation rate of the f stress moments at a node whose phases have different
+// viscosities: 1 / tau_f with tau_f = 1/2 + mu / (rho c_s^2) (Eq. 27), where the dynamic
+// viscosity mu is linear in phi between the light and heavy phases, like rho.
+template <class L, class R>
+__device__ __forceinline__ R stress_rate(const NodeParams<L, R>& p, R phi, R irho) {
+  return recip(R(0.5) + R(3) * (p.mu_l + phi * p.dmu) * irho);
+}
+
 // ---------------------------------------------------------------- D2Q9 in closed form
 // m = M g with the shared partial sums of the rows of Eq. 24
 template <class R>
@@ -248,7 +258,9 @@ __device__ __forceinline__ void d2q9_from_moments(const R (&m)[9], R (&v)[9]) {
 // UNIT: every rate outside the g flux rows (3-6) and the f stress rows (7-8) is exactly 1
 // (the defaults); those rows then relax straight to m_eq + src / 2 and their m is never
 // formed.
-template <class R, bool COUPLED, bool SH, bool UNIT = false>
+// VISC: the two phases have different viscosities; the stress rows relax at the node's
+// own 1 / tau_f (Eq. 27), see stress_rate.
+template <class R, bool COUPLED, bool SH, bool UNIT = false, bool VISC = false>
 __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, const NodeIn<D2Q9, R>& in,
                                                  R (&g)[9], R (&f)[9], R (&J)[2], NodeOut<D2Q9, R>& out) {
   const R* q = in.nphi;
@@ -271,9 +283,11 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
   const R grx = p.drho * gpx, gry = p.drho * gpy;
   R ux, uy, press = R(0);
   R fm[9];
+  R s_stress = R(0);
   if constexpr (COUPLED) {
     d2q9_moments<R>(f, fm);
     const R irho = recip(rho);
+    if constexpr (VISC) s_stress = stress_rate(p, phi, irho);
     ux = (fm[3] + R(0.5) * Fx) * irho;                                           // Eq. 28
     uy = (fm[5] + R(0.5) * Fy) * irho;
     const R P = fm[0] - f[0];
@@ -341,8 +355,9 @@ __device__ __forceinline__ void node_update_d2q9(const NodeParams<D2Q9, R>& p, c
                       R(1.0 / 3.0) * (ux * gry + uy * grx)};
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
+      const R sk = (VISC && D2Q9::f_stress_row[k]) ? s_stress : p.sfr[k];
       if (UNIT && !D2Q9::f_stress_row[k]) fm[k] = eq[k] + R(0.5) * src[k];
-      else fm[k] = fm[k] - p.sfr[k] * (fm[k] - eq[k]) + (R(1) - R(0.5) * p.sfr[k]) * src[k];
+      else fm[k] = fm[k] - sk * (fm[k] - eq[k]) + (R(1) - R(0.5) * sk) * src[k];
     }
     d2q9_from_moments<R>(fm, f);
   }
@@ -499,7 +514,8 @@ struct StencilOut {
 
 // UNIT: every rate outside the g flux rows and the f stress rows is exactly 1 (the
 // defaults); those rows then relax straight to m_eq + src / 2 without forming m.
-template <class L, class R, bool COUPLED, bool SH, bool UNIT = false>
+// VISC: the stress rows relax at the node's own rate (stress_rate).
+template <class L, class R, bool COUPLED, bool SH, bool UNIT = false, bool VISC = false>
 __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, const StencilOut<L, R>& st,
                                                   R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
   constexpr int Q = L::Q, D = L::D;
@@ -520,6 +536,7 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
     grho[d] = p.drho * gphi[d];
   }
   R press = R(0);
+  R s_stress = R(0);
   if constexpr (COUPLED) {
     // momentum and the sum of the moving populations; the full moments of f are formed
     // only at its collision, so that they are not live across the g collision
@@ -533,6 +550,7 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
     }
     R uu = R(0), ug = R(0);
     const R irho = recip(rho);
+    if constexpr (VISC) s_stress = stress_rate(p, phi, irho);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       u[d] = (jj[d] + R(0.5) * Fs[d]) * irho;                                       // Eq. 28
@@ -600,7 +618,7 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
       if constexpr (UNIT && !FRateRows<L>::need(k)) {
         fm[k] = eq + R(0.5) * src;
       } else {
-        const R s = p.sfr[k];
+        const R s = (VISC && L::f_stress_row[k]) ? s_stress : p.sfr[k];
         fm[k] = fm[k] - s * (fm[k] - eq) + (R(1) - R(0.5) * s) * src;
       }
     });
@@ -613,7 +631,7 @@ __device__ __forceinline__ void node_update_mom_s(const NodeParams<L, R>& p, con
   for (int d = 0; d < D; ++d) out.u[d] = u[d];
 }
 
-template <class L, class R, bool COUPLED, bool SH>
+template <class L, class R, bool COUPLED, bool SH, bool VISC = false>
 __device__ __forceinline__ void node_update_mom(const NodeParams<L, R>& p, const NodeIn<L, R>& in,
                                                 R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
   StencilOut<L, R> st;
@@ -623,14 +641,21 @@ __device__ __forceinline__ void node_update_mom(const NodeParams<L, R>& p, const
   stencil_grad<L, R>(in.npsi, st.gpsi);
 #pragma unroll
   for (int d = 0; d < L::D; ++d) st.u[d] = in.u[d];
-  node_update_mom_s<L, R, COUPLED, SH>(p, st, g, f, J, out);
+  node_update_mom_s<L, R, COUPLED, SH, false, VISC>(p, st, g, f, J, out);
 }
 
-template <class L, class R, bool COUPLED, bool SH = false>
+template <class L, class R, bool COUPLED, bool SH = false, bool VISC = false>
 __device__ __forceinline__ void node_update(const NodeParams<L, R>& p, const NodeIn<L, R>& in, R (&g)[L::Q],
                                             R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
-  if constexpr (L::Q == 9) node_update_d2q9<R, COUPLED, SH>(p, in, g, f, J, out);
-  else node_update_mom<L, R, COUPLED, SH>(p, in, g, f, J, out);
+  if constexpr (L::Q == 9) node_update_d2q9<R, COUPLED, SH, false, VISC>(p, in, g, f, J, out);
+  else node_update_mom<L, R, COUPLED, SH, VISC>(p, in, g, f, J, out);
+}
+// the same with the viscosity choice made at run time (plain path and observe)
+template <class L, class R, bool COUPLED, bool SH = false>
+__device__ __forceinline__ void node_update_any(const NodeParams<L, R>& p, bool visc, const NodeIn<L, R>& in,
+                                                R (&g)[L::Q], R (&f)[L::Q], R (&J)[L::D], NodeOut<L, R>& out) {
+  if (COUPLED && visc) node_update<L, R, COUPLED, SH, COUPLED>(p, in, g, f, J, out);
+  else node_update<L, R, COUPLED, SH, false>(p, in, g, f, J, out);
 }
 // Velocity of the prescribed single vortex, Eqs. 43-44, at node (x, y) and step t.
 template <class R>

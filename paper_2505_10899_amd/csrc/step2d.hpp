@@ -56,7 +56,7 @@ struct Acc2 {
 // stencils from LDS and updates the current row: every population is read from HBM
 // once, except the two halo columns and the two halo rows of the tile.
 // UNIT: the case's rates outside the g flux and f stress rows are all 1
-template <class St, bool COUPLED, class IX, bool UNIT>
+template <class St, bool COUPLED, class IX, bool UNIT, bool VISC = false>
 __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, int x0, int y0, int y1, bool reduce,
                                             double* __restrict__ part, long part_stride, long part_index,
                                             unsigned char* smem_raw) {
@@ -158,7 +158,7 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
         in.u[1] = uy;
       }
       NodeOut<L, R> out;
-      node_update_d2q9<R, COUPLED, St::shifted, UNIT>(c.np, in, gcur, f, J, out);
+      node_update_d2q9<R, COUPLED, St::shifted, UNIT, VISC>(c.np, in, gcur, f, J, out);
       R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
 #pragma unroll
       for (int i = 0; i < Q; ++i) {

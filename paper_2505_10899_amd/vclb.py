@@ -39,11 +39,12 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("bc_y", ctypes.c_int32), ("nlabels", ctypes.c_int32),
-        ("wall_u_bottom", ctypes.c_double * 3), ("wall_u_top", ctypes.c_double * 3),
+        ("bc", (ctypes.c_int32 * 2) * 3), ("nlabels", ctypes.c_int32),
+        ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
         ("W", ctypes.c_double), ("sigma", ctypes.c_double), ("mobility", ctypes.c_double),
         ("lam", ctypes.c_double), ("xi", ctypes.c_double), ("eps_n", ctypes.c_double),
-        ("rho_heavy", ctypes.c_double), ("rho_light", ctypes.c_double), ("nu", ctypes.c_double),
+        ("rho_heavy", ctypes.c_double), ("rho_light", ctypes.c_double),
+        ("nu_heavy", ctypes.c_double), ("nu_light", ctypes.c_double),
         ("s_g", ctypes.c_double * 19), ("s_f", ctypes.c_double * 19),
         ("U0", ctypes.c_double), ("T", ctypes.c_double),
         ("label_centre", (ctypes.c_double * 3) * MAX_LABELS),
@@ -82,7 +83,7 @@ _SIGS = [
     ("vclb_case_set_reduce_every", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("vclb_case_time", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64), ctypes.c_void_p]),
     ("vclb_observe", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
-    ("vclb_reduce", ctypes.c_int, [ctypes.c_void_p, _P(Obs), ctypes.c_void_p]),
+    ("vclb_reduce", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
     ("vclb_history", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
     ("vclb_state_bytes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_size_t)]),
     ("vclb_batch_create", ctypes.c_int, [_P(Params), ctypes.c_int32, _P(ctypes.c_void_p)]),
@@ -156,14 +157,18 @@ def to_cparams(p) -> Params:
     c.storage = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}[p.storage]
     c.mode = {"coupled": COUPLED, "vortex": PRESCRIBED_VORTEX}[p.mode]
     c.nx, c.ny, c.nz = int(p.nx), int(p.ny), int(p.nz)
-    c.bc_y = WALL if p.wall_y else PERIODIC
+    # walls bound y (both faces) or nothing: x and z are periodic
+    c.bc[1][0] = c.bc[1][1] = WALL if p.wall_y else PERIODIC
     c.nlabels = len(p.label_centres)
     for a in range(3):
-        c.wall_u_bottom[a] = float(p.wall_u_bottom[a])
-        c.wall_u_top[a] = float(p.wall_u_top[a])
+        c.wall_u[1][0][a] = float(p.wall_u_bottom[a])
+        c.wall_u[1][1][a] = float(p.wall_u_top[a])
     c.W, c.sigma, c.mobility = float(p.W), float(p.sigma), float(p.mobility)
     c.lam, c.xi, c.eps_n = float(p.lam), float(p.xi), float(p.eps_n)
-    c.rho_heavy, c.rho_light, c.nu = float(p.rho_heavy), float(p.rho_light), float(p.nu)
+    c.rho_heavy, c.rho_light = float(p.rho_heavy), float(p.rho_light)
+    nu_l = getattr(p, "nu_light", None)
+    c.nu_heavy = float(p.nu)
+    c.nu_light = float(p.nu if nu_l is None else nu_l)
     for k, v in enumerate(p.s_g or ()):
         c.s_g[k] = float(v)
     for k, v in enumerate(p.s_f or ()):
@@ -334,7 +339,7 @@ class Case:
     def reduce_raw(self, stream=None):
         """Moments of the current state as the C array of vclb_obs (one per label)."""
         arr = (Obs * self.nlabels)()
-        rc = lib().vclb_reduce(self.h, arr, _stream_handle(stream))
+        rc = lib().vclb_reduce(self.h, None, 0, arr, _stream_handle(stream))
         if rc not in (VCLB_OK, VCLB_ENONFINITE):
             check(rc)
         return arr
@@ -371,10 +376,26 @@ class Case:
 
     def reduce(self, stream=None) -> dict:
         arr = (Obs * self.nlabels)()
-        rc = lib().vclb_reduce(self.h, arr, _stream_handle(stream))
+        rc = lib().vclb_reduce(self.h, None, 0, arr, _stream_handle(stream))
         if rc not in (VCLB_OK, VCLB_ENONFINITE):
             check(rc)
         out = _obs_to_dict(arr, self.nlabels)
+        out["rc"] = rc
+        return out
+
+    def reduce_labels(self, labels, nlabels: int = 0, stream=None) -> dict:
+        """Volume reductions over caller labels: labels[n] (int32, shape (nz, ny, nx) or
+        flat; numpy or torch; negative = no label), nlabels labels (0: max label + 1).
+        Moments are about the origin (d = the node's position)."""
+        lab = torch.as_tensor(labels).reshape(-1).to(device=self.device, dtype=torch.int32).contiguous()
+        if lab.numel() != self.n:
+            raise VclbError(VCLB_EINVAL, "one label per node")
+        nl = int(nlabels) if nlabels else int(lab.max().item()) + 1
+        arr = (Obs * max(1, nl))()
+        rc = lib().vclb_reduce(self.h, ctypes.c_void_p(lab.data_ptr()), nl, arr, _stream_handle(stream))
+        if rc not in (VCLB_OK, VCLB_ENONFINITE):
+            check(rc)
+        out = _obs_to_dict(arr, max(1, nl))
         out["rc"] = rc
         return out
 
@@ -482,6 +503,7 @@ def _obs_to_dict(arr, n) -> dict:
         "sum_phi_dd": np.array([list(arr[k].sum_phi_dd) for k in range(n)]),
         "nonfinite": np.array([arr[k].nonfinite for k in range(n)]),
         "step": np.array([arr[k].step for k in range(n)]),
+        "label": np.array([arr[k].label for k in range(n)]),
     }
 
 

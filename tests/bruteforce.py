@@ -26,7 +26,7 @@ def d2q9_tables():
 class Dense2D:
     def __init__(self, nx, ny, *, W, sigma, mobility, nu, lam, xi, eps_n, rho_h, rho_l,
                  wall_y=False, ub=(0.0, 0.0), ut=(0.0, 0.0), mode="coupled", U0=0.0, T=1.0,
-                 s_g=None, s_f=None):
+                 s_g=None, s_f=None, nu_l=None):
         self.nx, self.ny, self.N = nx, ny, nx * ny
         self.c, self.w, self.M = d2q9_tables()
         self.W, self.lam, self.xi, self.eps = W, lam, xi, eps_n
@@ -42,6 +42,11 @@ class Dense2D:
         self.Bg = Minv @ (np.eye(9) - 0.5 * np.diag(sg)) @ self.M
         self.Af = Minv @ np.diag(sf) @ self.M
         self.Bf = Minv @ (np.eye(9) - 0.5 * np.diag(sf)) @ self.M
+        # unequal viscosities: at each node the stress rows relax at 1 / tau_f with
+        # tau_f = 1/2 + mu / (rho cs^2), mu linear in phi between the two phases (Eq. 27)
+        self.Minv, self.sf = Minv, list(sf)
+        self.mu_h, self.mu_l = rho_h * nu, rho_l * (nu if nu_l is None else nu_l)
+        self.visc = nu_l is not None and nu_l != nu
         self.opp = [int(np.where((self.c == -ci).all(axis=1))[0][0]) for ci in self.c]
         self._build_stencils()
 
@@ -123,7 +128,13 @@ class Dense2D:
                 Fi = np.array([w[i] * (uk @ grho[k] + (c[i] @ Fs[k]) / CS2
                                        + (np.outer(uk, grho[k]) * (np.outer(c[i], c[i]) - CS2 * np.eye(2))).sum() / CS2)
                                for i in range(9)])
-                fs[k] = f[k] - self.Af @ (f[k] - feq) + self.Bf @ Fi
+                Af, Bf = self.Af, self.Bf
+                if self.visc:
+                    tau = 0.5 + (self.mu_l + phi[k] * (self.mu_h - self.mu_l)) / (rho[k] * CS2)
+                    sk = np.diag(self.sf[:7] + [1 / tau, 1 / tau])
+                    Af = self.Minv @ sk @ self.M
+                    Bf = self.Minv @ (np.eye(9) - 0.5 * sk) @ self.M
+                fs[k] = f[k] - Af @ (f[k] - feq) + Bf @ Fi
             else:
                 fs[k] = f[k]
         # streaming as a dense permutation (plus bounce-back), Q N x Q N

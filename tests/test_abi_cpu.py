@@ -195,3 +195,63 @@ def test_bandwidth_probe_validates_before_any_hip_call():
     assert L.vclb_bandwidth_probe(1, p, None, 64, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL
     odd = ctypes.c_void_p(p.value + 4)
     assert L.vclb_bandwidth_probe(0, odd, p, 48, 1, 0, ctypes.byref(g), None) == v.VCLB_EINVAL  # alignment
+
+
+# --------------------------------------------------------------------------- boundary types per face
+def _raw(p, edit):
+    v = _vclb()
+    c = v.to_cparams(p)
+    edit(c)
+    return c
+
+
+def _rc_validate(c):
+    return _vclb().lib().vclb_params_validate(ctypes.byref(c))
+
+
+def test_boundary_faces_validated_per_axis():
+    v = _vclb()
+    WALL, PER = v.WALL, v.PERIODIC
+    p = _valid()
+    assert _rc_validate(_raw(p, lambda c: None)) == v.VCLB_OK
+    # walls on both y faces of D2Q9: supported
+    def ywalls(c):
+        c.bc[1][0] = c.bc[1][1] = WALL
+        c.wall_u[1][0][0], c.wall_u[1][1][0] = -0.01, 0.02
+    assert _rc_validate(_raw(p, ywalls)) == v.VCLB_OK
+    bad = {
+        "x walls": lambda c: (c.bc[0].__setitem__(0, WALL), c.bc[0].__setitem__(1, WALL)),
+        "z walls": lambda c: (c.bc[2].__setitem__(0, WALL), c.bc[2].__setitem__(1, WALL)),
+        "one-sided y wall": lambda c: c.bc[1].__setitem__(0, WALL),
+        "unknown type": lambda c: (c.bc[1].__setitem__(0, 7), c.bc[1].__setitem__(1, 7)),
+        "normal wall velocity": lambda c: (ywalls(c), c.wall_u[1][0].__setitem__(1, 0.01)),
+        "non-finite wall velocity": lambda c: c.wall_u[0][1].__setitem__(2, float("nan")),
+    }
+    for name, edit in bad.items():
+        assert _rc_validate(_raw(p, edit)) == v.VCLB_EINVAL, name
+    # D3Q19 supports no walls at all
+    q = W.rayleigh_plateau()[0]
+    assert _rc_validate(_raw(q, lambda c: None)) == v.VCLB_OK
+    assert _rc_validate(_raw(q, lambda c: (c.bc[1].__setitem__(0, WALL), c.bc[1].__setitem__(1, WALL)))) == v.VCLB_EINVAL
+
+
+def test_viscosity_ratio_validation():
+    v = _vclb()
+    p = _valid().replace(nu=0.3, nu_light=0.05)
+    v.validate(p)
+    assert v.to_cparams(p).nu_heavy == 0.3 and v.to_cparams(p).nu_light == 0.05
+    v.validate(W.rayleigh_plateau()[0].replace(nu_light=0.2))
+    for change in (dict(nu_light=-0.1), dict(nu_light=float("nan")),
+                   dict(s_f=(0, 0, 0, 0, 0, 0, 0, 1.2, 0)),       # a stress rate fixed by hand
+                   dict(mode="vortex", T=100.0)):
+        with pytest.raises(v.VclbError) as e:
+            v.validate(p.replace(**change))
+        assert e.value.code == v.VCLB_EINVAL, change
+    # rates outside the stress rows stay free
+    v.validate(p.replace(s_f=(0, 1.3, 0, 0, 0, 0, 0, 0, 0)))
+    # batches and the adjoint hold one viscosity; both refuse before touching HIP
+    arr = (v.Params * 2)(v.to_cparams(_valid()), v.to_cparams(p))
+    h = ctypes.c_void_p()
+    assert v.lib().vclb_batch_create(arr, 2, ctypes.byref(h)) == v.VCLB_EINVAL and not h.value
+    nb = ctypes.c_size_t()
+    assert v.lib().vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p)), 10, 2, ctypes.byref(nb)) == v.VCLB_EINVAL

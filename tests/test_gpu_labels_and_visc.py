@@ -1,0 +1,187 @@
+"""GPU checks of two parts of the boundary:
+
+- vclb_reduce with caller labels: the FP64 device reductions over a label array equal
+  the oracle's observables_by_labels on the same phase field (every storage, both
+  lattices, labels that are negative, unused or numerous), are deterministic, and report
+  labels >= nlabels;
+- unequal viscosities of the two phases (per-node tau_f, Eq. 27): one step from the
+  oracle's exact state matches the oracle node by node (fused and plain paths, D2Q9 and
+  D3Q19), and 1000 free FP64 steps of an off-node drop match it to 1e-12 on phi, rho, u;
+  the FP32 and FP16S storages keep the volume.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Model
+from oracle.model import observables_by_labels
+
+pytestmark = pytest.mark.gpu
+
+
+def _v():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_10899_amd import vclb
+    return vclb
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    p2 = W.CaseParams(nx=70, ny=45, W=4.0, sigma=0.01, rho_light=0.1, label_centres=[(20.3, 22.1, 0.0)])
+    phi2 = W.drops_phi(p2, [(20.3, 22.1, 0, 9.0), (52.7, 20.4, 0, 6.0)])
+    p3 = W.CaseParams(nx=20, ny=18, nz=24, lattice="D3Q19", sigma=0.005, nu=0.05, rho_light=0.1)
+    phi3 = W.cylinder_phi(p3, 9.3, 8.6, 4.0, 0.1, 24.0)
+    return {"d2q9": (p2, phi2), "d3q19": (p3, phi3)}
+
+
+def _labels(shape, kind, rng):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    if kind == "halves":            # two regions, a strip with no label, label 2 unused
+        lab = np.where(x < nx // 2, 0, 1)
+        lab[:, :, nx // 2 - 2:nx // 2 + 1] = -1
+        return lab.astype(np.int32), 3
+    if kind == "blocks":            # many small blocks, numbered in a shuffled order
+        b = (x // 3) + ((nx + 2) // 3) * ((y // 3) + ((ny + 2) // 3) * (z // 3))
+        nb = int(b.max()) + 1
+        perm = rng.permutation(nb)
+        return perm[b].astype(np.int32), nb
+    raise ValueError(kind)
+
+
+def _compare(got, ref, nl):
+    for k in ("sum_phi", "sum_phi_d", "sum_phi_dd"):
+        g, r = np.asarray(got[k])[:nl], np.asarray(ref[k])
+        scale = np.maximum(np.abs(r), 1.0)
+        assert np.all(np.abs(g - r) <= 1e-12 * scale), (k, float(np.max(np.abs(g - r) / scale)))
+    assert np.array_equal(np.asarray(got["count_half"])[:nl].astype(int), ref["count_half"])
+    assert not np.any(np.asarray(got["nonfinite"])[:nl])
+
+
+@pytest.mark.parametrize("kind", ["halves", "blocks"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19"])
+def test_caller_label_reductions_match_the_oracle(lattice, storage, kind):
+    """The device reductions of the GPU's own phase field against the oracle's sums of that
+    same field (in FP64) over the same labels."""
+    v = _v()
+    p, phi0 = _cases()[lattice]
+    p = p.replace(storage=storage)
+    rng = np.random.default_rng(7)
+    lab, nl = _labels(phi0.shape, kind, rng)
+    say(f"case: caller labels, {lattice} {storage} {kind}: {nl} labels")
+    c = v.Case(p).init(phi0)
+    c.step(7)
+    phi = c.observe(v.FIELD_PHI)["phi"].reshape(phi0.shape)
+    got = c.reduce_labels(lab, nl)
+    assert got["rc"] == v.VCLB_OK
+    ref = observables_by_labels(phi, lab, nl)
+    _compare(got, ref, nl)
+    assert np.array_equal(np.asarray(got["label"])[:nl], np.arange(nl))
+    # deterministic, and the built-in reduction is untouched by it
+    again = c.reduce_labels(lab, nl)
+    for k in ("sum_phi", "sum_phi_d", "sum_phi_dd"):
+        assert np.array_equal(np.asarray(again[k]), np.asarray(got[k]))
+    b = c.reduce()
+    assert abs(b["sum_phi"].sum() - phi.sum()) <= 1e-12 * phi.sum()
+
+
+def test_caller_labels_against_the_oracle_state_fp64():
+    """FP64: after 20 steps the GPU and the oracle agree on phi to ~1e-15, so the label
+    reductions agree with the oracle run itself."""
+    v = _v()
+    p, phi0 = _cases()["d2q9"]
+    lab, nl = _labels(phi0.shape, "halves", np.random.default_rng(1))
+    c = v.Case(p).init(phi0)
+    c.step(20)
+    m = Model(p).init(phi0)
+    m.step(20)
+    _compare(c.reduce_labels(lab, nl), observables_by_labels(m.phi(), lab, nl), nl)
+
+
+def test_label_out_of_range_is_reported():
+    v = _v()
+    p, phi0 = _cases()["d2q9"]
+    lab, _ = _labels(phi0.shape, "halves", np.random.default_rng(1))
+    c = v.Case(p).init(phi0)
+    with pytest.raises(v.VclbError) as e:
+        c.reduce_labels(lab, 1)          # label 1 >= nlabels
+    assert e.value.code == v.VCLB_EINVAL
+
+
+# --------------------------------------------------------------------------- unequal viscosities
+def _visc_case(lattice, storage="fp64"):
+    if lattice == "d2q9":
+        p, _, u0 = W.shear_droplet(nx=66, ny=24, R=7.0, U=0.02, Ca=0.2, Re=0.5)
+        p = p.replace(rho_light=0.3, nu=0.15, nu_light=0.04, storage=storage,
+                      label_centres=[(32.31, 11.17, 0.0)])
+        return p, W.drops_phi(p, [(32.31, 11.17, 0.0, 7.0)]), u0
+    p = W.CaseParams(nx=16, ny=12, nz=20, lattice="D3Q19", sigma=0.005, nu=0.12, nu_light=0.03, rho_light=0.2,
+                     storage=storage)
+    return p, W.cylinder_phi(p, 7.3, 5.6, 4.0, 0.1, 20.0), None
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19"])
+def test_viscosity_ratio_one_step_parity(lattice, plain):
+    v = _v()
+    from test_gpu_parity import one_step_parity
+    p, phi0, u0 = _visc_case(lattice)
+    say(f"case: viscosity ratio {p.nu / p.nu_light:.2f}, {lattice}, {'plain' if plain else 'fused'}")
+    m = Model(p).init(phi0, u0)
+    for t in (0, 5, 30):
+        while m.t < t:
+            m.step(1)
+        ref = Model(p)
+        ref.g, ref.f, ref.Jprev, ref.t = m.g.copy(), m.f.copy(), m.Jprev.copy(), m.t
+        ratio, ferr, raw = one_step_parity(p, ref, plain=plain)
+        say(f"  t={t}: populations {raw:.2e} (error / bound {ratio:.2f}), fields {ferr:.2e}")
+        assert ratio <= 1.0 and ferr <= 1e-13, t
+
+
+@pytest.mark.parametrize("plain", [False, True], ids=["fused", "plain"])
+def test_viscosity_ratio_fp64_free_run_1e12(plain):
+    v = _v()
+    p, phi0, u0 = _visc_case("d2q9")
+    steps = 1000
+    m = Model(p).init(phi0, u0)
+    m.step(steps)
+    F0 = m.fields()
+    c = v.Case(p).init(phi0, u0)
+    (c.step_plain if plain else c.step)(steps)
+    F = c.observe(v.FIELD_PHI | v.FIELD_RHO | v.FIELD_U)
+    errs = {k: float(np.max(np.abs(F[k] - F0[k]))) for k in ("phi", "rho", "u")}
+    say(f"case: viscosity ratio, 1000 FP64 steps, {'plain' if plain else 'fused'}: max-abs {errs}")
+    for k, e in errs.items():
+        assert e <= 1e-12, (k, e)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+@pytest.mark.parametrize("lattice", ["d2q9", "d3q19"])
+def test_viscosity_ratio_reduced_precision(lattice, storage):
+    """Reduced storage with unequal viscosities: phi and u stay close to the FP64 oracle
+    over 100 steps and the total of phi is kept."""
+    v = _v()
+    p, phi0, u0 = _visc_case(lattice, storage)
+    steps = 100
+    m = Model(p.replace(storage="fp64")).init(phi0, u0)
+    m.step(steps)
+    F0 = m.fields()
+    c = v.Case(p).init(phi0, u0)
+    v0 = c.reduce()["sum_phi"].sum()
+    c.step(steps)
+    F = c.observe(v.FIELD_PHI | v.FIELD_U)
+    dphi = float(np.max(np.abs(F["phi"] - F0["phi"])))
+    du = float(np.max(np.abs(F["u"] - F0["u"])))
+    drift = abs(c.reduce()["sum_phi"].sum() - v0) / v0
+    say(f"case: viscosity ratio {lattice} {storage}, {steps} steps: |dphi| {dphi:.2e}, |du| {du:.2e}, drift {drift:.2e}")
+    tol = {"fp32": (1e-5, 1e-6, 1e-6), "fp16s": (2e-3, 1e-4, 1e-4)}[storage]
+    assert dphi <= tol[0] and du <= tol[1] and drift <= tol[2]

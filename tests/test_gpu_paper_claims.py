@@ -87,9 +87,11 @@ def test_single_vortex_returns_closer_with_the_correction():
     assert err[0.5] <= 0.6 * err[0.0]                # measured: 0.70 against 1.47
 
 
-def _drops(phi):
-    """Volumes #(phi >= 1/2) of the connected regions of a (nz, ny, nx) field, periodic in
-    z (the column's axis), largest first."""
+def _drop_labels(phi):
+    """Host labels of the drops of a (nz, ny, nx) field: the connected regions of
+    phi >= 1/2, joined across the periodic z faces (the column's axis), numbered largest
+    first; every other node takes the label of the nearest region node (so that each
+    drop's diffuse interface counts with it).  Returns (labels int32, count)."""
     from scipy import ndimage
     lab, n = ndimage.label(phi >= 0.5)
     parent = list(range(n + 1))
@@ -104,11 +106,28 @@ def _drops(phi):
     both = (lo > 0) & (hi > 0)
     for a, b in zip(lo[both], hi[both]):
         parent[root(int(a))] = root(int(b))
+    roots = np.array([root(k) for k in range(n + 1)])
+    lab = roots[lab]
     size = np.bincount(lab.ravel(), minlength=n + 1)
-    vol = {}
-    for k in range(1, n + 1):
-        vol[root(k)] = vol.get(root(k), 0) + int(size[k])
-    return sorted(vol.values(), reverse=True)
+    size[0] = 0
+    order = [k for k in np.argsort(-size, kind="stable") if size[k] > 0]
+    renum = np.full(n + 1, -1)
+    renum[order] = np.arange(len(order))
+    lab = renum[lab]
+    # nearest region node for the rest, on three copies stacked along the periodic z axis
+    nz = phi.shape[0]
+    tiled = np.concatenate([lab, lab, lab], axis=0)
+    _, idx = ndimage.distance_transform_edt(tiled < 0, return_indices=True)
+    near = tiled[tuple(idx)][nz:2 * nz]
+    return near.astype(np.int32), len(order)
+
+
+def _drops(v, c, phi):
+    """Per drop, largest first: #(phi >= 1/2) and the FP64 volume sum(phi), both from the
+    library's device reductions over the host's drop labels."""
+    lab, n = _drop_labels(phi)
+    r = c.reduce_labels(lab, n)
+    return [int(x) for x in r["count_half"]], [float(x) for x in r["sum_phi"]]
 
 
 def test_rayleigh_plateau_column_keeps_its_drops_only_with_the_correction():
@@ -121,12 +140,16 @@ def test_rayleigh_plateau_column_keeps_its_drops_only_with_the_correction():
         c = v.Case(p.replace(lam=lam)).init(phi0, u0)
         c.set_reduce_every(0)
         vol0 = int((phi0 >= 0.5).sum())
+        total0 = c.reduce()["sum_phi"].sum()
         c.step(30000)
-        d30 = _drops(c.observe(v.FIELD_PHI)["phi"])
+        d30, s30 = _drops(v, c, c.observe(v.FIELD_PHI)["phi"])
         c.step(10000)
-        d40 = _drops(c.observe(v.FIELD_PHI)["phi"])
+        d40, s40 = _drops(v, c, c.observe(v.FIELD_PHI)["phi"])
         out[lam] = (vol0, d30, d40)
-        say(f"column, lam = {lam}: drops at 30k {d30}, at 40k {d40}; volume at 40k / initial {sum(d40) / vol0:.4f}")
+        say(f"column, lam = {lam}: drops #(phi >= 1/2) at 30k {d30}, at 40k {d40}; volume at 40k / initial "
+            f"{sum(d40) / vol0:.4f}; sum(phi) per drop at 30k {np.round(s30, 2).tolist()}, at 40k {np.round(s40, 2).tolist()}")
+        # every node belongs to a drop: the drops' sum(phi) add up to the total, which is conserved
+        assert abs(sum(s40) - total0) <= 1e-6 * total0
     for lam in (0.5, 0.0):
         vol0, d30, d40 = out[lam]
         assert len(d30) == 2 and len(d40) == 2, lam                      # one drop and one satellite

@@ -206,11 +206,12 @@ def test_stencil_wall_mirror():
 def _dense_from(p):
     return Dense2D(p.nx, p.ny, W=p.W, sigma=p.sigma, mobility=p.mobility, nu=p.nu, lam=p.lam, xi=p.xi,
                    eps_n=p.eps_n, rho_h=p.rho_heavy, rho_l=p.rho_light, wall_y=p.wall_y,
-                   ub=p.wall_u_bottom[:2], ut=p.wall_u_top[:2], mode=p.mode, U0=p.U0, T=p.T)
+                   ub=p.wall_u_bottom[:2], ut=p.wall_u_top[:2], mode=p.mode, U0=p.U0, T=p.T,
+                   nu_l=p.nu_light)
 
 
 @pytest.mark.parametrize("shape", [(4, 4), (5, 3)])
-@pytest.mark.parametrize("variant", ["periodic", "walls", "vortex"])
+@pytest.mark.parametrize("variant", ["periodic", "walls", "vortex", "viscosity_ratio"])
 def test_oracle_equals_dense_bruteforce(shape, variant):
     nx, ny = shape
     kw = dict(nx=nx, ny=ny, W=2.0, sigma=0.02, mobility=0.07, nu=0.13, rho_heavy=1.0, rho_light=0.2)
@@ -218,6 +219,8 @@ def test_oracle_equals_dense_bruteforce(shape, variant):
         kw.update(wall_y=True, wall_u_bottom=(-0.03, 0.0, 0.0), wall_u_top=(0.05, 0.0, 0.0))
     if variant == "vortex":
         kw.update(mode="vortex", U0=0.04, T=7.0)
+    if variant == "viscosity_ratio":
+        kw.update(nu_light=0.41, wall_y=True, wall_u_bottom=(-0.03, 0.0, 0.0), wall_u_top=(0.05, 0.0, 0.0))
     p = W.CaseParams(**kw)
     rng = np.random.default_rng(nx * 10 + ny)
     phi0 = rng.uniform(-0.05, 1.05, (1, ny, nx))
@@ -513,3 +516,71 @@ def test_single_vortex_reverses():
         assert e_half > 5.0 and e_end < 0.4, (lam, e_half, e_end)
         errs[lam] = e_end
     assert errs[0.5] < errs[0.0]
+
+
+# --------------------------------------------------------------------------- unequal viscosities (Eq. 27)
+@pytest.mark.parametrize("nu_h,nu_l,rho_l", [(0.5, 0.1, 1.0), (0.1, 0.5, 0.25)])
+def test_two_layer_couette_flow(nu_h, nu_l, rho_l):
+    """Heavy fluid below, light fluid above, a flat interface half-way between walls moving
+    at -U and +U.  At steady state the shear stress tau = mu du/dy is the same at every
+    height, so du/dy = tau / mu(y), and the wall speeds fix tau through
+    2U = tau sum_y 1 / mu(y) (midpoint rule over the nodes between the half-way walls).
+    In each bulk layer the profile is linear with slope tau / mu of that phase: their
+    ratio is mu_light / mu_heavy."""
+    ny, U = 32, 0.01
+    p = W.CaseParams(nx=3, ny=ny, wall_y=True, wall_u_bottom=(-U, 0, 0), wall_u_top=(U, 0, 0),
+                     nu=nu_h, nu_light=nu_l, rho_heavy=1.0, rho_light=rho_l, sigma=0.001, W=4.0)
+    y = np.arange(ny)
+    prof = 0.5 * (1 + np.tanh(2 * ((ny / 2 - 0.5) - y) / p.W))
+    m = Model(p).init(np.broadcast_to(prof[None, :, None], (1, ny, 3)).copy())
+    m.step(5000)
+    F = m.fields()
+    phi, u = F["phi"][0, :, 1], F["u"][0, 0, :, 1]
+    mu_h, mu_l = 1.0 * nu_h, rho_l * nu_l
+    mu = mu_l + phi * (mu_h - mu_l)
+    tau = 2 * U / np.sum(1.0 / mu)
+    lo, hi = slice(2, 9), slice(ny - 9, ny - 2)
+    s_lo = np.polyfit(y[lo], u[lo], 1)[0]
+    s_hi = np.polyfit(y[hi], u[hi], 1)[0]
+    assert abs((s_hi / s_lo) / (mu_h / mu_l) - 1) < 1e-3
+    assert abs(s_lo / (tau / mu_h) - 1) < 1e-2
+    assert abs(s_hi / (tau / mu_l) - 1) < 1e-2
+    # one kinematic viscosity: the dynamic viscosities differ by the density ratio only
+    q = Model(p.replace(nu=max(nu_h, nu_l), nu_light=None)).init(np.broadcast_to(prof[None, :, None], (1, ny, 3)).copy())
+    q.step(5000)
+    uq = q.fields()["u"][0, 0, :, 1]
+    ratio = np.polyfit(y[hi], uq[hi], 1)[0] / np.polyfit(y[lo], uq[lo], 1)[0]
+    assert abs(ratio / (1.0 / rho_l) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("phase", [0.0, 1.0])
+def test_viscosity_of_each_pure_phase(phase):
+    """A shear wave in a pure phase decays at nu k^2 with that phase's own viscosity."""
+    n, steps = 64, 500
+    p = W.CaseParams(nx=4, ny=n, rho_heavy=1.0, rho_light=0.5, nu=0.12, nu_light=0.05)
+    y = np.arange(n)
+    u0 = np.zeros((2, 1, n, 4))
+    u0[0] = (0.01 * np.sin(2 * np.pi * y / n))[None, :, None]
+    m = Model(p).init(np.full((1, n, 4), phase), u0)
+    c0 = _fourier1(m.fields()["u"][0, 0, :, 0])
+    m.step(steps)
+    c1 = _fourier1(m.fields()["u"][0, 0, :, 0])
+    k = 2 * np.pi / n
+    nu = p.nu if phase == 1.0 else p.nu_light
+    assert abs(-np.log(abs(c1) / abs(c0)) / steps / (nu * k * k) - 1) < 5e-3
+
+
+def test_observables_by_labels_on_known_field():
+    from oracle.model import observables_by_labels
+    phi = np.zeros((2, 3, 4))
+    lab = -np.ones((2, 3, 4), dtype=int)
+    phi[0, 1, 2], lab[0, 1, 2] = 1.0, 0          # label 0 at (x, y, z) = (2, 1, 0)
+    phi[1, 2, 3], lab[1, 2, 3] = 0.25, 0         # label 0 at (3, 2, 1)
+    phi[1, 0, 0], lab[1, 0, 0] = 0.5, 2          # label 2 at (0, 0, 1)
+    phi[0, 0, 1] = 0.9                           # no label: not counted
+    o = observables_by_labels(phi, lab, 3)
+    assert np.allclose(o["sum_phi"], [1.25, 0.0, 0.5])
+    assert list(o["count_half"]) == [1, 0, 1]
+    assert np.allclose(o["sum_phi_d"][0], [2 + 0.75, 1 + 0.5, 0.25])
+    assert np.allclose(o["sum_phi_dd"][0], [4 + 2.25, 1 + 1.0, 0.25, 2 + 1.5, 0 + 0.75, 0 + 0.5])
+    assert np.allclose(o["sum_phi_d"][2], [0, 0, 0.5]) and np.allclose(o["sum_phi_dd"][2], [0, 0, 0.5, 0, 0, 0])

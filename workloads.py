@@ -55,7 +55,9 @@ class CaseParams:
     eps_n: float = 1e-12                       # |grad psi| regulariser of the unit normal
     rho_heavy: float = 1.0                     # density where phi = 1
     rho_light: float = 1.0                     # density where phi = 0
-    nu: float = 0.1                            # kinematic viscosity (tau_f = 1/2 + nu / cs^2)
+    nu: float = 0.1                            # kinematic viscosity (tau_f = 1/2 + nu / cs^2); of the
+                                               # heavy phase when nu_light is given
+    nu_light: Optional[float] = None           # kinematic viscosity of the light phase (None: nu)
     s_g: Optional[Tuple[float, ...]] = None    # None: default MRT rates for g
     s_f: Optional[Tuple[float, ...]] = None    # None: default MRT rates for f
     U0: float = 0.0                            # prescribed single-vortex amplitude (Eqs. 43-44)
