@@ -248,6 +248,18 @@ int vclb_observe(vclb_case* c, uint32_t field_mask, double* out, int ptr_kind, v
    the stream. */
 int vclb_reduce(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): vclb_reduce with caller labels (labels must not
+   be NULL; same arguments, results and errors), whose partial sums live in a fixed device
+   scratch array of 4 MiB that the library holds on each device it runs on until the
+   process ends, so that the call allocates nothing.  Returns VCLB_EINVAL, before any
+   launch, when the reduction needs more scratch than that: about
+   (13 nlabels + 1) * 8 * min(512, ceil(N / 2048)) bytes for the partials plus 104 bytes per
+   label (for example at most 78 labels on a grid of 10^6 nodes or more).  Every call on one
+   device shares that device's array: calls that overlap on one device (different streams
+   or threads) race and must be serialised by the caller.  Synchronises the stream. */
+int vclb_reduce_static(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* out, void* stream);
+
 /* Copy the recorded per-step reductions of steps [t_first, t_first + count) into
    out[count * nlabels] (host).  Steps older than VCLB_HISTORY or never recorded give
    VCLB_ESTATE. */

@@ -957,6 +957,20 @@ int vclb_reduce(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* 
   return VCLB_OK;
 }
 
+int vclb_reduce_static(vclb_case* c, const int32_t* labels, int32_t nlabels, vclb_obs* out, void* stream) {
+  if (int rc = label_args(c, labels, nlabels, out)) return rc;
+  const long n = long(c->p.nx) * c->p.ny * c->p.nz;
+  const size_t need = vclb::label_scratch_bytes(n, nlabels);
+  if (need > vclb::kStaticScratchBytes)
+    return fail(VCLB_EINVAL, "the label reduction needs " + std::to_string(need) + " bytes of scratch; the fixed scratch holds " +
+                                 std::to_string(vclb::kStaticScratchBytes) + " (use fewer labels or vclb_reduce)");
+  void* scratch = nullptr;
+  const int rs = vclb::static_scratch(&scratch);
+  if (rs == -1) return fail(VCLB_EINVAL, "device index beyond the fixed scratch table");
+  if (rs) return fail(VCLB_EHIP, "hipGetSymbolAddress of the fixed scratch failed");
+  return label_reduce_into(c, labels, nlabels, out, scratch, as_stream(stream));
+}
+
 int vclb_history(vclb_case* c, int64_t t_first, int32_t count, vclb_obs* out, void* stream) {
   if (!c || !out || count < 0 || t_first < 0) return fail(VCLB_EINVAL, "bad argument");
   if (count == 0) return VCLB_OK;

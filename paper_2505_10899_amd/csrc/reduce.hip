@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <mutex>
 
 #include "devcase.hpp"
 #include "reduce.hpp"
@@ -177,5 +178,27 @@ int launch_label_reduce(const R* phi, const int* labels, long n, int nx, int ny,
 
 template int launch_label_reduce<double>(const double*, const int*, long, int, int, int, long, void*, hipStream_t);
 template int launch_label_reduce<float>(const float*, const int*, long, int, int, int, long, void*, hipStream_t);
+
+// ---------------------------------------------------------------- fixed device scratch
+// Scratch of the label reductions for callers that cannot allocate (kStaticScratchBytes per
+// device, held until the process ends).  Its host-side name is only a handle: the device
+// address comes from hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+int static_scratch(void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -3;
+  if (dev < 0 || dev >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -3;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return 0;
+}
 
 }  // namespace vclb

@@ -33,4 +33,12 @@ inline size_t label_result_offset(long n, int nlabels) {
   return ((part + 255) / 256) * 256;
 }
 
+// Fixed device scratch for callers that cannot allocate (vclb_reduce_static): one array
+// of kStaticScratchBytes per device, its device address looked up once per device.
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+// the scratch array's device address on the current device (0) or a HIP error (-3) / a
+// device index beyond kMaxDevices (-1)
+int static_scratch(void** ptr);
+
 }  // namespace vclb

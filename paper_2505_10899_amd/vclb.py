@@ -84,6 +84,8 @@ _SIGS = [
     ("vclb_case_time", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64), ctypes.c_void_p]),
     ("vclb_observe", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     ("vclb_reduce", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
+    ("vclb_reduce_static", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, _P(Obs),
+                                          ctypes.c_void_p]),
     ("vclb_history", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _P(Obs), ctypes.c_void_p]),
     ("vclb_state_bytes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_size_t)]),
     ("vclb_batch_create", ctypes.c_int, [_P(Params), ctypes.c_int32, _P(ctypes.c_void_p)]),
@@ -383,16 +385,18 @@ class Case:
         out["rc"] = rc
         return out
 
-    def reduce_labels(self, labels, nlabels: int = 0, stream=None) -> dict:
+    def reduce_labels(self, labels, nlabels: int = 0, static: bool = False, stream=None) -> dict:
         """Volume reductions over caller labels: labels[n] (int32, shape (nz, ny, nx) or
         flat; numpy or torch; negative = no label), nlabels labels (0: max label + 1).
-        Moments are about the origin (d = the node's position)."""
+        Moments are about the origin (d = the node's position).  static: use the entry
+        point that allocates nothing (vclb_reduce_static, fixed device scratch)."""
         lab = torch.as_tensor(labels).reshape(-1).to(device=self.device, dtype=torch.int32).contiguous()
         if lab.numel() != self.n:
             raise VclbError(VCLB_EINVAL, "one label per node")
         nl = int(nlabels) if nlabels else int(lab.max().item()) + 1
         arr = (Obs * max(1, nl))()
-        rc = lib().vclb_reduce(self.h, ctypes.c_void_p(lab.data_ptr()), nl, arr, _stream_handle(stream))
+        fn = lib().vclb_reduce_static if static else lib().vclb_reduce
+        rc = fn(self.h, ctypes.c_void_p(lab.data_ptr()), nl, arr, _stream_handle(stream))
         if rc not in (VCLB_OK, VCLB_ENONFINITE):
             check(rc)
         out = _obs_to_dict(arr, max(1, nl))
