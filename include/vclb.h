@@ -101,6 +101,18 @@ typedef struct {
   double  sigma;            /* surface tension, >= 0 (beta = 12 sigma / W, kappa = 3 sigma W / 2) */
   double  mobility;         /* M > 0; tau_g = 1/2 + M / c_s^2 (Eq. 34)                      */
   double  lambda;           /* penalty constant (0.5 in the paper); 0 gives the classical model */
+  double  mass_fix;         /* rate r in [0, 1] of a global volume correction, the kind of
+                               correction the paper's introduction describes and argues
+                               against (0, the default, is the paper's model).  With r > 0,
+                               each step measures the volume V = sum H(phi_c), H(p) =
+                               p^2 (3 - 2 p), of the time-t field and adds to every g_i the
+                               source w_i kappa delta(phi_c), delta(p) = 4 p (1 - p) (the
+                               interface indicator of Eq. 5), with kappa = r (V_ref - V) /
+                               sum delta: the total of phi changes by r (V_ref - V).  V_ref is
+                               V of the state given to vclb_case_init or vclb_case_set_state
+                               (checkpoints keep it).  Steps then run the plain two-kernel
+                               path plus the reduction; not supported by batches or the
+                               adjoint.                                                    */
   double  xi;               /* regulariser of Eq. 37 (1e-10 in the paper), > 0              */
   double  eps_n;            /* unit normal n = grad psi / sqrt(|grad psi|^2 + eps_n^2), >= 0 */
   double  rho_heavy;        /* density at phi = 1, > 0                                      */

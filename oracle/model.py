@@ -72,6 +72,9 @@ class Model:
         self.visc = nu_l is not None and nu_l != p.nu
         self.mu_heavy = p.rho_heavy * p.nu
         self.mu_light = p.rho_light * (p.nu if nu_l is None else nu_l)
+        # global volume correction (an ablation, not the paper's model: see global_source)
+        self.mass_fix = float(getattr(p, "mass_fix", 0.0))
+        self.V_ref = None
         sg = default_rates(lat, self.tau_g, "g")
         sf = default_rates(lat, self.tau_f, "f")
         if p.s_g:
@@ -141,6 +144,32 @@ class Model:
         reading: the paper names the viscosity ratio but not the interpolation)."""
         mu = self.mu_light + phi * (self.mu_heavy - self.mu_light)
         return 0.5 + mu / (rho * self.cs2)
+
+    @staticmethod
+    def smooth_volume_terms(phi):
+        """H(phi_c) = phi_c^2 (3 - 2 phi_c), a smooth step that counts the volume enclosed by
+        the phi = 1/2 level (it is flat at 0 and 1, so small bulk shifts of phi do not
+        count), and the interface indicator delta(phi_c) = 4 phi_c (1 - phi_c), which is
+        W |grad phi| of the equilibrium profile (Eq. 5)."""
+        pc = _clip01(phi)
+        return pc * pc * (3.0 - 2.0 * pc), 4.0 * pc * (1.0 - pc)
+
+    def volume(self, phi=None):
+        """V = sum_x H(phi_c): the volume the global correction holds."""
+        return self.smooth_volume_terms(self.phi() if phi is None else phi)[0].sum()
+
+    def global_source(self, phi):
+        """The correction of the kind the paper's introduction describes (Wang et al.): a
+        source added at every interface node, in proportion to the interface indicator,
+        whose total makes up a rate r of the volume lost since the reference state:
+        S(x) = kappa delta(x), kappa = r (V_ref - V(t)) / sum delta.  The paper states no
+        formula; this form is a reading.  Returns S (zero without the correction)."""
+        if self.mass_fix == 0.0:
+            return None
+        H, delta = self.smooth_volume_terms(phi)
+        sd = delta.sum()
+        kappa = self.mass_fix * (self.V_ref - H.sum()) / sd if np.real(sd) > 0 else 0.0 * sd
+        return kappa * delta
 
     def psi_of(self, phi):
         """Regularised signed distance, Eq. 37, evaluated on the clipped phi."""
@@ -325,6 +354,12 @@ class Model:
             self.f = np.zeros_like(self.g)
         self.Jprev = phi0 * u0
         self.t = 0
+        self.set_reference_volume()
+        return self
+
+    def set_reference_volume(self):
+        """V_ref of the global correction: the volume of the current state."""
+        self.V_ref = self.volume() if self.mass_fix != 0.0 else None
         return self
 
     def step(self, n=1):
@@ -339,6 +374,9 @@ class Model:
             G = self.g_source(V)                                  # Eq. 32
             geq = self.g_equilibrium(phi, F["mu"], u)             # Eq. 31
             gstar = self.mrt(self.g, geq, G, self.Sg)             # Eq. 33
+            S = self.global_source(phi)
+            if S is not None:                                     # g_i += w_i S
+                gstar = gstar + self.lat.w.reshape((-1,) + (1,) * phi.ndim) * S
             if p.mode == "coupled":
                 feq = self.f_equilibrium(F["p"], F["rho"], u)     # Eqs. 22, 23
                 Fi = self.f_forcing(u, F["grho"], F["Fs"])        # Eq. 21

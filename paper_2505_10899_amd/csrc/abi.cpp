@@ -97,6 +97,8 @@ int validate(const vclb_params* p) {
   if (!(finite(p->sigma) && p->sigma >= 0)) return fail(VCLB_EINVAL, "sigma must be >= 0");
   if (!(finite(p->mobility) && p->mobility > 0)) return fail(VCLB_EINVAL, "mobility must be > 0");
   if (!(finite(p->lambda) && p->lambda >= 0)) return fail(VCLB_EINVAL, "lambda must be >= 0");
+  if (!(finite(p->mass_fix) && p->mass_fix >= 0 && p->mass_fix <= 1))
+    return fail(VCLB_EINVAL, "mass_fix must lie in [0, 1]");
   if (!(finite(p->xi) && p->xi > 0)) return fail(VCLB_EINVAL, "xi must be > 0");
   if (!(finite(p->eps_n) && p->eps_n >= 0)) return fail(VCLB_EINVAL, "eps_n must be >= 0");
   if (!(finite(p->rho_heavy) && p->rho_heavy > 0)) return fail(VCLB_EINVAL, "rho_heavy must be > 0");
@@ -141,7 +143,7 @@ int validate(const vclb_params* p) {
 }
 
 struct Layout {
-  size_t pop[2][2], J, phis[2], partials[2], hist, cur, tmp_phi, tmp_psi, total;
+  size_t pop[2][2], J, phis[2], partials[2], hist, cur, tmp_phi, tmp_psi, mass, mass_part, total;
   long partial_blocks;
 };
 
@@ -172,6 +174,9 @@ Layout layout_for(const vclb_params& p) {
   L.cur = take(size_t(nl) * vclb::kObsFields * sizeof(double));
   L.tmp_phi = take(n * rb);
   L.tmp_psi = take(n * rb);
+  // the global volume correction: [V_ref, kappa, V, sum delta] and per-workgroup partials
+  L.mass = take(4 * sizeof(double));
+  L.mass_part = p.mass_fix > 0 ? take(2 * ((n + 255) / 256) * sizeof(double)) : SIZE_MAX;
   L.total = off;
   return L;
 }
@@ -265,6 +270,9 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   d.cur = reinterpret_cast<double*>(c.ws + c.lay.cur);
   d.tmp_phi = reinterpret_cast<R*>(c.ws + c.lay.tmp_phi);
   d.tmp_psi = reinterpret_cast<R*>(c.ws + c.lay.tmp_psi);
+  d.mfix = p.mass_fix > 0 ? 1 : 0;
+  d.mass = reinterpret_cast<double*>(c.ws + c.lay.mass);
+  d.mass_part = c.lay.mass_part == SIZE_MAX ? nullptr : reinterpret_cast<double*>(c.ws + c.lay.mass_part);
   auto& np = d.np;
   const double sigma = p.sigma, W = p.W;
   np.W4 = R(W / 4.0);
@@ -296,6 +304,7 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
     np.wt[k] = R(L::cy[k] > 0 ? 2.0 * L::w[i] * cut * 3.0 : 0.0);
   }
   np.U0 = R(p.U0);
+  np.mass_fix = p.mass_fix;
   np.T = p.T;
   return d;
 }
@@ -542,6 +551,22 @@ int vclb_case_set_reduce_every(vclb_case* c, int32_t every) {
   return VCLB_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// the global volume correction's reference volume V_ref from the case's current state
+int mass_reference(vclb_case* c, hipStream_t s) {
+  if (!(c->p.mass_fix > 0)) return VCLB_OK;
+  int rc = dispatch(*c, [&](auto dc, auto) {
+    using DC = decltype(dc);
+    return vclb::launch_mass_ref<typename DevTraits<DC>::L, typename DevTraits<DC>::St>(dc, s);
+  });
+  return rc ? fail(VCLB_EHIP, "reference volume launch failed") : VCLB_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int vclb_case_init(vclb_case* c, const double* phi0, const double* u0, int ptr_kind, void* stream) {
   if (!c || !phi0) return fail(VCLB_EINVAL, "case or phi0 is NULL");
   if (ptr_kind != VCLB_HOST && ptr_kind != VCLB_DEVICE) return fail(VCLB_EINVAL, "bad ptr_kind");
@@ -578,6 +603,7 @@ int vclb_case_init(vclb_case* c, const double* phi0, const double* u0, int ptr_k
     if (e != hipSuccess) return hip_fail(e, "init");
   }
   if (rc) return fail(VCLB_EHIP, "init kernel launch failed");
+  if (int rm = mass_reference(c, s)) return rm;
   c->t_host = 0;
   std::fill(c->recorded.begin(), c->recorded.end(), -1);
   c->pending = false;
@@ -622,6 +648,7 @@ int vclb_case_set_state(vclb_case* c, const double* g, const double* f, const do
   if (rc) return fail(VCLB_EHIP, "set_state launch failed");
   if (e != hipSuccess) return hip_fail(e, "set_state");
   c->t_host = t;
+  if (int rm = mass_reference(c, s)) return rm;
   std::fill(c->recorded.begin(), c->recorded.end(), -1);
   c->pending = false;
   c->inited = true;
@@ -667,6 +694,7 @@ int vclb_case_get_state(vclb_case* c, double* g, double* f, double* J, int ptr_k
 
 static int do_steps(vclb_case* c, int64_t nsteps, void* stream, bool fused) {
   if (!c) return fail(VCLB_EINVAL, "case is NULL");
+  if (c->p.mass_fix > 0) fused = false;   // the global correction runs on the plain path
   if (nsteps < 0) return fail(VCLB_EINVAL, "nsteps < 0");
   if (!c->inited) return fail(VCLB_ESTATE, "step before init");
   const long blocks = fused ? vclb::fused_blocks(lattice_d(c->p.lattice), c->p.nx, c->p.ny, c->p.nz, c->tile)
@@ -1019,6 +1047,7 @@ std::vector<Span> state_spans(const vclb_case* c, int par) {
   if (c->p.mode == VCLB_COUPLED) v.push_back({c->lay.pop[1][par], size_t(Q) * n * storage_bytes(c->p.storage)});
   v.push_back({c->lay.J, size_t(D) * n * arith_bytes(c->p.storage)});
   if (c->p.storage != VCLB_FP64) v.push_back({c->lay.phis[par], n * 4});
+  v.push_back({c->lay.mass, sizeof(double)});   // V_ref of the global volume correction
   return v;
 }
 
@@ -1389,6 +1418,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
     if (cases[k].storage != cases[0].storage) return fail(VCLB_EINVAL, "every case of a batch has one storage");
     if (cases[k].nlabels > 1) return fail(VCLB_EINVAL, "batched cases have one observation label");
     if (visc_ratio(cases[k])) return fail(VCLB_EINVAL, "batched cases have one viscosity (nu_heavy = nu_light)");
+    if (cases[k].mass_fix > 0) return fail(VCLB_EINVAL, "batched cases take no global volume correction");
     if (double(cases[k].nx + 2) * (cases[k].ny + 2) >= double(1 << 24))
       return fail(VCLB_EINVAL, "batched cases hold fewer than 2^24 padded nodes");
   }
@@ -1989,6 +2019,7 @@ int adj_check_case(const vclb_case* c) {
   if (c->p.lattice != VCLB_D2Q9 || c->p.storage != VCLB_FP64 || c->p.mode != VCLB_COUPLED)
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
   if (visc_ratio(c->p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
+  if (c->p.mass_fix > 0) return fail(VCLB_EINVAL, "the adjoint covers cases without the global volume correction");
   return VCLB_OK;
 }
 
@@ -2060,6 +2091,7 @@ int vclb_adjoint_bytes(const vclb_params* p, int64_t nsteps, int32_t every, size
   if (p->lattice != VCLB_D2Q9 || p->storage != VCLB_FP64 || p->mode != VCLB_COUPLED)
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
   if (visc_ratio(*p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
+  if (p->mass_fix > 0) return fail(VCLB_EINVAL, "the adjoint covers cases without the global volume correction");
   if (every == 0) every = adj_default_every(nsteps);
   *bytes = adj_layout(*p, nsteps, every).total;
   return VCLB_OK;

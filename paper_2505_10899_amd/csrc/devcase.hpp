@@ -37,6 +37,9 @@ struct DevCase {
   double* cur;                  // [label][kObsFields] reductions of the current state
   R* tmp_phi;                   // scratch N: phi (plain path and observe)
   R* tmp_psi;                   // scratch N: psi
+  int mfix;                     // the global volume correction is on (rate np.mass_fix)
+  double* mass;                 // [V_ref, kappa, V, sum delta] of the global correction
+  double* mass_part;            // its workgroup partials, [2][workgroup]
   NodeParams<L, R> np;
 };
 

@@ -165,6 +165,58 @@ __global__ void __launch_bounds__(256) k_phi_psi(DevCase<L, St> c) {
   c.tmp_psi[n] = psi_of<R>(phi, c.np.W4, c.np.xi);
 }
 
+// ---------------------------------------------------------------- global volume correction
+// (an ablation of the kind of correction the paper argues against; off by default)
+// Per workgroup: sum H(phi_c) and sum delta(phi_c) of the scratch phi, H(p) = p^2 (3 - 2p),
+// delta(p) = 4 p (1 - p).
+template <class L, class St>
+__global__ void __launch_bounds__(256) k_mass_partials(DevCase<L, St> c) {
+  __shared__ double red[4 * 2];
+  const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (n < c.n) {
+    const double pc = double(clamp01(c.tmp_phi[n]));
+    v[0] = pc * pc * (3.0 - 2.0 * pc);
+    v[1] = 4.0 * pc * (1.0 - pc);
+  }
+  const double s = block_sum_fields<2>(v, 2, red);
+  if (threadIdx.x < 2) c.mass_part[long(threadIdx.x) * gridDim.x + blockIdx.x] = s;
+}
+
+// Sum the partials in workgroup order.  set_ref: the volume becomes the reference V_ref
+// (kappa 0); else kappa = r (V_ref - V) / sum delta.
+template <class L, class St>
+__global__ void __launch_bounds__(256) k_mass_fold(DevCase<L, St> c, int nb, int set_ref) {
+  __shared__ double red[4 * 2];
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    v[0] += c.mass_part[b];
+    v[1] += c.mass_part[nb + b];
+  }
+  const double s = block_sum_fields<2>(v, 2, red);
+  __shared__ double tot[2];
+  if (threadIdx.x < 2) tot[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double V = tot[0], sd = tot[1];
+    if (set_ref) {
+      c.mass[0] = V;
+      c.mass[1] = 0.0;
+    } else {
+      c.mass[1] = sd > 0.0 ? c.np.mass_fix * (c.mass[0] - V) / sd : 0.0;
+    }
+    c.mass[2] = V;
+    c.mass[3] = sd;
+  }
+}
+
+template <class L, class St>
+static void launch_mass(const DevCase<L, St>& c, int set_ref, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_mass_partials<L, St>), dim3(nb), dim3(256), 0, s, c);
+  hipLaunchKernelGGL((k_mass_fold<L, St>), dim3(1), dim3(256), 0, s, c, int(nb), set_ref);
+}
+
 // gather a scratch field at x + c_i with periodic wrap / wall mirror
 template <class L, class St>
 __device__ __forceinline__ void gather(const DevCase<L, St>& c, const typename St::R* __restrict__ a, int x,
@@ -200,6 +252,12 @@ __global__ void __launch_bounds__(256) k_collide_plain(DevCase<L, St> c, int red
     for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
     NodeOut<L, R> out;
     node_update_any<L, R, COUPLED, St::shifted>(c.np, c.visc != 0, in, g, f, J, out);
+    if (c.mfix) {   // g_i += w_i kappa delta(phi_c): the global correction's source
+      const R pc = clamp01(in.nphi[0]);
+      const R src = R(c.mass[1]) * (R(4) * pc * (R(1) - pc));
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) g[i] += R(L::w[i]) * src;
+    }
     store_node<L, St, COUPLED>(c, par, n, y, in.nphi[0], out.rho, g, f, J);
     if (reduce) accumulate(c, acc, double(in.nphi[0]), x, y, z);
   }
@@ -314,6 +372,7 @@ template <class L, class St, bool COUPLED>
 int launch_step_plain(const DevCase<L, St>& c, int reduce, hipStream_t s) {
   const unsigned nb = unsigned((c.n + 255) / 256);
   hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
+  if (c.mfix) launch_mass(c, 0, s);
   hipLaunchKernelGGL((k_collide_plain<L, St, COUPLED>), dim3(nb), dim3(256), 0, s, c, reduce);
   if (reduce) launch_finalize(self_pending(c, int(nb), c.hist + (c.t % kHistory) * c.nl * kObsFields), s);
   return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -388,6 +447,14 @@ int launch_phi_psi(const DevCase<L, St>& c, hipStream_t s) {
 }
 
 template <class L, class St>
+int launch_mass_ref(const DevCase<L, St>& c, hipStream_t s) {
+  const unsigned nb = unsigned((c.n + 255) / 256);
+  hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
+  launch_mass(c, 1, s);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class L, class St>
 int launch_reduce_state(const DevCase<L, St>& c, hipStream_t s) {
   const unsigned nb = unsigned((c.n + 255) / 256);
   hipLaunchKernelGGL((k_phi_psi<L, St>), dim3(nb), dim3(256), 0, s, c);
@@ -432,6 +499,12 @@ VCLB_INSTANTIATE(D3Q19, StoreF64, true)
 VCLB_INSTANTIATE(D3Q19, StoreF32, true)
 VCLB_INSTANTIATE(D3Q19, StoreF16S, true)
 template int launch_reduce_state<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
+template int launch_mass_ref<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
+template int launch_mass_ref<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
+template int launch_mass_ref<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);
+template int launch_mass_ref<D3Q19, StoreF64>(const DevCase<D3Q19, StoreF64>&, hipStream_t);
+template int launch_mass_ref<D3Q19, StoreF32>(const DevCase<D3Q19, StoreF32>&, hipStream_t);
+template int launch_mass_ref<D3Q19, StoreF16S>(const DevCase<D3Q19, StoreF16S>&, hipStream_t);
 template int launch_phi_psi<D2Q9, StoreF64>(const DevCase<D2Q9, StoreF64>&, hipStream_t);
 template int launch_phi_psi<D2Q9, StoreF32>(const DevCase<D2Q9, StoreF32>&, hipStream_t);
 template int launch_phi_psi<D2Q9, StoreF16S>(const DevCase<D2Q9, StoreF16S>&, hipStream_t);

@@ -26,6 +26,9 @@ template <class L, class St>
 int launch_phi_psi(const DevCase<L, St>& c, hipStream_t s);
 template <class L, class St>
 int launch_reduce_state(const DevCase<L, St>& c, hipStream_t s);
+// the global volume correction's reference volume, from the current state
+template <class L, class St>
+int launch_mass_ref(const DevCase<L, St>& c, hipStream_t s);
 template <class L, class St, bool COUPLED>
 int launch_set_state(const DevCase<L, St>& c, const double* g, const double* f, const double* J, long t,
                      hipStream_t s);

@@ -128,6 +128,7 @@ struct NodeParams {
   R sfr[L::Q];   // s_k^f (unscaled)
   R U0;          // vortex amplitude
   double T;      // vortex period (steps)
+  double mass_fix;   // rate of the global volume correction (0: off)
 };
 
 template <class R>

@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
         ("bc", (ctypes.c_int32 * 2) * 3), ("nlabels", ctypes.c_int32),
         ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
         ("W", ctypes.c_double), ("sigma", ctypes.c_double), ("mobility", ctypes.c_double),
-        ("lam", ctypes.c_double), ("xi", ctypes.c_double), ("eps_n", ctypes.c_double),
+        ("lam", ctypes.c_double), ("mass_fix", ctypes.c_double), ("xi", ctypes.c_double),
+        ("eps_n", ctypes.c_double),
         ("rho_heavy", ctypes.c_double), ("rho_light", ctypes.c_double),
         ("nu_heavy", ctypes.c_double), ("nu_light", ctypes.c_double),
         ("s_g", ctypes.c_double * 19), ("s_f", ctypes.c_double * 19),
@@ -167,6 +168,7 @@ def to_cparams(p) -> Params:
         c.wall_u[1][1][a] = float(p.wall_u_top[a])
     c.W, c.sigma, c.mobility = float(p.W), float(p.sigma), float(p.mobility)
     c.lam, c.xi, c.eps_n = float(p.lam), float(p.xi), float(p.eps_n)
+    c.mass_fix = float(getattr(p, "mass_fix", 0.0))
     c.rho_heavy, c.rho_light = float(p.rho_heavy), float(p.rho_light)
     nu_l = getattr(p, "nu_light", None)
     c.nu_heavy = float(p.nu)

@@ -255,3 +255,17 @@ def test_viscosity_ratio_validation():
     assert v.lib().vclb_batch_create(arr, 2, ctypes.byref(h)) == v.VCLB_EINVAL and not h.value
     nb = ctypes.c_size_t()
     assert v.lib().vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p)), 10, 2, ctypes.byref(nb)) == v.VCLB_EINVAL
+
+
+def test_global_correction_validation():
+    v = _vclb()
+    p = _valid().replace(mass_fix=0.5)
+    v.validate(p)
+    for r in (-0.1, 1.5, float("nan")):
+        with pytest.raises(v.VclbError):
+            v.validate(p.replace(mass_fix=r))
+    arr = (v.Params * 1)(v.to_cparams(p))
+    h = ctypes.c_void_p()
+    assert v.lib().vclb_batch_create(arr, 1, ctypes.byref(h)) == v.VCLB_EINVAL and not h.value
+    nb = ctypes.c_size_t()
+    assert v.lib().vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p)), 10, 2, ctypes.byref(nb)) == v.VCLB_EINVAL

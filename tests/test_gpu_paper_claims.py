@@ -87,6 +87,48 @@ def test_single_vortex_returns_closer_with_the_correction():
     assert err[0.5] <= 0.6 * err[0.0]                # measured: 0.70 against 1.47
 
 
+def _regions_periodic_x(mask):
+    """Number of connected regions of a (ny, nx) mask, periodic along x."""
+    from scipy import ndimage
+    lab, n = ndimage.label(mask)
+    parent = list(range(n + 1))
+
+    def root(k):
+        while parent[k] != k:
+            parent[k] = parent[parent[k]]
+            k = parent[k]
+        return k
+
+    for a, b in zip(lab[:, 0], lab[:, -1]):
+        if a > 0 and b > 0:
+            parent[root(int(a))] = root(int(b))
+    return len({root(k) for k in range(1, n + 1)})
+
+
+def test_rayleigh_plateau_layer_2d_stays_one_layer():
+    """Sect. 4.3 at the paper's own size: the layer of Eq. 45 on 256 x 128 nodes (readings in
+    workloads.paper_rayleigh_plateau_2d), 100 000 steps, with the correction and without
+    it.  A planar layer has no azimuthal curvature to drive a Rayleigh-Plateau break-up:
+    under both models it stays one connected layer along the periodic x axis, and its
+    area #(phi >= 1/2) stays within 1% of its start."""
+    v = _v()
+    for lam in (0.5, 0.0):
+        p, phi0, u0 = W.paper_rayleigh_plateau_2d(lam)
+        c = v.Case(p).init(phi0, u0)
+        c.set_reduce_every(0)
+        a0 = int((phi0 >= 0.5).sum())
+        areas, parts = [], []
+        for _ in range(10):
+            c.step(10000)
+            phi = c.observe(v.FIELD_PHI)["phi"][0]
+            parts.append(_regions_periodic_x(phi >= 0.5))
+            areas.append(int((phi >= 0.5).sum()))
+        say(f"2D layer, lam = {lam}: area / initial every 10k steps {np.round(np.array(areas) / a0, 4).tolist()}, "
+            f"connected regions {parts}")
+        assert all(k == 1 for k in parts), lam
+        assert np.all(np.abs(np.array(areas) / a0 - 1.0) <= 0.01), lam     # measured: within 0.8% (lam 0.5)
+
+
 def _drop_labels(phi):
     """Host labels of the drops of a (nz, ny, nx) field: the connected regions of
     phi >= 1/2, joined across the periodic z faces (the column's axis), numbered largest

@@ -584,3 +584,38 @@ def test_observables_by_labels_on_known_field():
     assert np.allclose(o["sum_phi_d"][0], [2 + 0.75, 1 + 0.5, 0.25])
     assert np.allclose(o["sum_phi_dd"][0], [4 + 2.25, 1 + 1.0, 0.25, 2 + 1.5, 0 + 0.75, 0 + 0.5])
     assert np.allclose(o["sum_phi_d"][2], [0, 0, 0.5]) and np.allclose(o["sum_phi_dd"][2], [0, 0, 0.5, 0, 0, 0])
+
+
+# --------------------------------------------------------------------------- global volume correction (ablation)
+def _two_drops_48(lam, r):
+    p = W.CaseParams(nx=48, ny=48, W=4.0, sigma=0.01, mobility=0.1, rho_light=1.0, lam=lam, mass_fix=r,
+                     label_centres=[(15.3, 24.2, 0.0), (36.7, 23.9, 0.0)])
+    return p, W.drops_phi(p, [(15.3, 24.2, 0, 10.0), (36.7, 23.9, 0, 4.5)])
+
+
+def test_global_correction_changes_the_total_by_its_own_amount_only():
+    """Every other part of the step keeps sum(phi) (streaming permutes, collisions keep
+    the zeroth moment), so each step the total must change by exactly what the source adds,
+    r (V_ref - V(t)); and V_ref is the smooth volume of the initial state."""
+    r = 0.7
+    p, phi0 = _two_drops_48(0.0, r)
+    m = Model(p).init(phi0)
+    pc = np.clip(phi0, 0, 1)
+    assert abs(m.V_ref - (pc * pc * (3 - 2 * pc)).sum()) < 1e-9
+    m.step(300)                       # let the volume drift a little first
+    for _ in range(30):
+        before, V = m.phi().sum(), m.volume()
+        m.step(1)
+        assert abs((m.phi().sum() - before) - r * (m.V_ref - V)) < 1e-12 * before
+
+
+def test_global_correction_holds_the_volume_the_classical_model_loses():
+    out = {}
+    for r in (0.0, 1.0):
+        p, phi0 = _two_drops_48(0.0, r)
+        m = Model(p).init(phi0)
+        V0, S0 = m.volume(), m.phi().sum()
+        m.step(2000)
+        out[r] = (m.volume() / V0, m.phi().sum() / S0)
+    assert out[0.0][0] < 0.99 and abs(out[0.0][1] - 1) < 1e-12      # classical: V falls, sum(phi) kept
+    assert abs(out[1.0][0] - 1) < 1e-4 and out[1.0][1] > 1.01        # corrected: V kept, sum(phi) grows

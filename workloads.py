@@ -51,6 +51,7 @@ class CaseParams:
     sigma: float = 0.01
     mobility: float = 0.1
     lam: float = 0.5                           # penalty constant (Sect. 2, after Eq. 6)
+    mass_fix: float = 0.0                      # rate of a global volume correction (0: none)
     xi: float = 1e-10                          # regulariser in Eq. 37
     eps_n: float = 1e-12                       # |grad psi| regulariser of the unit normal
     rho_heavy: float = 1.0                     # density where phi = 1
@@ -230,6 +231,24 @@ def paper_shear_drop(lam: float = 0.5, storage: str = "fp64", r: float = 8.0,
                    wall_y=True, wall_u_bottom=(-U, 0.0, 0.0), wall_u_top=(U, 0.0, 0.0), storage=storage,
                    label_centres=[(63.5, 31.5, 0.0)])
     return p, drops_phi(p, [(63.5, 31.5, 0.0, r)]), couette_u(p)
+
+
+def paper_rayleigh_plateau_2d(lam: float = 0.5, storage: str = "fp64") -> Tuple[CaseParams, np.ndarray, None]:
+    """Sect. 4.3: the layer of Eq. 45, phi = 1/2 [1 + tanh(2 (a - y + 0.05 cos x) / W)], on
+    (0, 2 pi) x (0, pi) with 256 x 128 nodes and a = 0.15, fluid at rest.  Readings: a and
+    the 0.05 amplitude are in the box's units, so 128 / pi nodes per unit (a = 6.1 nodes,
+    amplitude 2.0 nodes); W = 3 lattice units (Sect. 4.1's common value); half-way walls at
+    y = 0 and y = pi (node rows 0 and 127 lie half a node inside them), x periodic; node
+    (i, j) sits at (x, y) = ((i + 1/2) h, (j + 1/2) h) with h = pi / 128."""
+    nx, ny = 256, 128
+    h = np.pi / ny
+    p = CaseParams(nx=nx, ny=ny, W=3.0, sigma=0.01, mobility=0.1, nu=0.1, rho_heavy=1.0, rho_light=1.0, lam=lam,
+                   wall_y=True, storage=storage)
+    x = (np.arange(nx, dtype=np.float64) + 0.5) * h
+    y = (np.arange(ny, dtype=np.float64) + 0.5) * h
+    s = (0.15 - y[:, None] + 0.05 * np.cos(x)[None, :]) / h          # signed distance in nodes
+    phi0 = (0.5 * (1.0 + np.tanh(2.0 * s / p.W)))[None]
+    return p, phi0, None
 
 
 BATCH_SEED = 10899
