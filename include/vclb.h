@@ -166,6 +166,13 @@ int vclb_version(void);
    owned by the caller.  blocks: workgroups of 256 lanes (0: 4 per compute unit). */
 int vclb_bandwidth_probe(int32_t mode, void* dst, const void* src, size_t bytes, int32_t reps, int32_t blocks,
                          double* gbs, void* stream);
+/* The same with the kernel's shape chosen: each lane keeps `unroll` (1, 2, 4 or 8) 16-byte
+   vectors in flight (a workgroup's tile is unroll * 256 consecutive vectors; all loads are
+   issued before the first store or use), with non-temporal loads and stores if
+   nontemporal = 1.  vclb_bandwidth_probe is unroll 1, nontemporal 0.  Sweeping unroll,
+   nontemporal and blocks and keeping the fastest gives the device's achievable rate. */
+int vclb_bandwidth_probe_ex(int32_t mode, int32_t unroll, int32_t nontemporal, void* dst, const void* src,
+                            size_t bytes, int32_t reps, int32_t blocks, double* gbs, void* stream);
 
 /* Check parameters without any HIP call.  Fills the defaults of zero rates. */
 int vclb_params_validate(const vclb_params* p);

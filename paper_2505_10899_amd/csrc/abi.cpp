@@ -434,7 +434,14 @@ int vclb_version(void) { return 10000; }
 
 int vclb_bandwidth_probe(int32_t mode, void* dst, const void* src, size_t bytes, int32_t reps, int32_t blocks,
                          double* gbs, void* stream) {
+  return vclb_bandwidth_probe_ex(mode, 1, 0, dst, src, bytes, reps, blocks, gbs, stream);
+}
+
+int vclb_bandwidth_probe_ex(int32_t mode, int32_t unroll, int32_t nontemporal, void* dst, const void* src,
+                            size_t bytes, int32_t reps, int32_t blocks, double* gbs, void* stream) {
   if (mode < 0 || mode > 2) return fail(VCLB_EINVAL, "mode is 0 (copy), 1 (read) or 2 (write)");
+  if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) return fail(VCLB_EINVAL, "unroll is 1, 2, 4 or 8");
+  if (nontemporal != 0 && nontemporal != 1) return fail(VCLB_EINVAL, "nontemporal is 0 or 1");
   if (!gbs || reps < 1 || reps > 1000 || blocks < 0) return fail(VCLB_EINVAL, "bad probe arguments");
   if (bytes == 0 || bytes % 16 != 0) return fail(VCLB_EINVAL, "bytes must be a positive multiple of 16");
   if (!dst || (mode != 2 && !src)) return fail(VCLB_EINVAL, "NULL buffer");
@@ -448,13 +455,15 @@ int vclb_bandwidth_probe(int32_t mode, void* dst, const void* src, size_t bytes,
     blocks = 4 * ncu;
   }
   const long n16 = long(bytes / 16);
-  if (vclb::launch_probe(mode, dst, src, n16, blocks, s)) return fail(VCLB_EHIP, "probe launch failed");   // warm-up
+  if (vclb::launch_probe(mode, unroll, nontemporal, dst, src, n16, blocks, s))
+    return fail(VCLB_EHIP, "probe launch failed");   // warm-up
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int rc = VCLB_OK;
   hipError_t e = hipEventRecord(e0, s);
-  for (int r = 0; e == hipSuccess && rc == VCLB_OK && r < reps; ++r) rc = vclb::launch_probe(mode, dst, src, n16, blocks, s);
+  for (int r = 0; e == hipSuccess && rc == VCLB_OK && r < reps; ++r)
+    rc = vclb::launch_probe(mode, unroll, nontemporal, dst, src, n16, blocks, s);
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.0f;

@@ -53,10 +53,27 @@ __device__ __forceinline__ double min_image(double d, int n, bool periodic) {
   return d < -h ? d + double(n) : (d >= h ? d - double(n) : d);
 }
 
+// Shifted storage keeps each stored g as a deviation from the rest state of the node that
+// will read it: d_i = g*_i - r_i phi_r, with phi_r the reader's phi at the writer's time
+// level, which the reader finds in its own entry of phis.  A node then decodes all its
+// pulls with one load of its own phis entry.  The writer knows phi_r: it is the stencil
+// value of phi at x + c_i, or its own phi when c_i leaves through a wall (the value
+// bounces back to the writer).  With e*_i = g*_i - r_i phi (the collision's deviation from
+// the writer's own rest state) the stored value is e*_i + r_i (phi - phi_r).
+template <class R>
+__device__ __forceinline__ R encode_dev(R e, R rest_i, R phi_self, R phi_reader) {
+  return e + rest_i * (phi_self - phi_reader);
+}
+// whether direction i of a node in row y leaves through a wall (and comes back to it)
+template <class L>
+__device__ __forceinline__ bool leaves_through_wall(int i, int y, int ny, bool wall) {
+  return wall && ((y == 0 && L::cy[i] < 0) || (y == ny - 1 && L::cy[i] > 0));
+}
+
 // Pull the Q populations of one set arriving at node (x, y, z):
 // pop_i(x) = post_i(x - c_i), or the node's own opposite post-collision value when
 // x - c_i lies behind a wall.  For shifted storage (g set) `out` receives the stored
-// deviations d_i and `ps` the phi of the node that wrote them (see phi_of_pulled).
+// deviations d_i and `ps` the phi they are relative to: the node's own phis entry.
 template <class L, class St, class Case>
 __device__ __forceinline__ void pull(const Case& c, const typename St::S* __restrict__ src,
                                      const float* __restrict__ phis, int x, int y, int z,
@@ -80,15 +97,20 @@ __device__ __forceinline__ void pull(const Case& c, const typename St::S* __rest
     if (L::cz[i] != 0) zs = wrapi(zs, c.nz);
     const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
     out[i] = St::load(src, long(pi) * c.n + s);
-    if constexpr (St::shifted) {
-      if (ps) ps[i] = R(ldg(phis, s));
+  }
+  if constexpr (St::shifted) {
+    if (ps) {
+      const R own = R(ldg(phis, x + long(c.nx) * (y + long(c.ny) * z)));
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) ps[i] = own;
     }
   }
 }
 
-// phi = sum_i g_i (Eq. 35) of a pulled g set.  For shifted storage g_i = d_i + r_i phi_s,
-// and on return v holds e_i = g_i - r_i phi = d_i + r_i (phi_s - phi): the deviation
-// from this node's own rest state, formed without rounding at the magnitude of g.
+// phi = sum_i g_i (Eq. 35) of a pulled g set.  For shifted storage g_i = d_i + r_i phi_s
+// (phi_s: the phi the stored deviations refer to), and on return v holds
+// e_i = g_i - r_i phi = d_i + r_i (phi_s - phi): the deviation from this node's own rest
+// state, formed without rounding at the magnitude of g.
 template <class L, class St>
 __device__ __forceinline__ typename St::R phi_of_pulled(typename St::R (&v)[L::Q], const typename St::R (&ps)[L::Q],
                                                         const typename St::R (&rest)[L::Q]) {
@@ -218,18 +240,23 @@ __device__ __forceinline__ void finish_block(const Case& c, const Acc& a, bool r
 
 // store one node's post-collision state (with the moving-wall term on f for the
 // directions that leave through a wall, read back by the bounce-back pull)
+// nphi: phi at x + c_i (the readers of the shifted g, see encode_dev)
 template <class L, class St, bool COUPLED>
 __device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, long n, int y,
-                                           typename St::R phi, typename St::R rho,
+                                           const typename St::R (&nphi)[L::Q], typename St::R rho,
                                            const typename St::R (&g)[L::Q], typename St::R (&f)[L::Q],
                                            const typename St::R (&J)[L::D]) {
   using R = typename St::R;
   const int dst = par ^ 1;
-  R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
+  const R phi = nphi[0];
+  R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    St::store(c.pop[0][dst], long(i) * c.n + n, g[i]);
-    if constexpr (St::fold) res += St::rounding(g[i]);
+    R d = g[i];
+    if constexpr (St::shifted)
+      d = encode_dev(g[i], c.np.rest[i], phi, leaves_through_wall<L>(i, y, c.ny, c.wall != 0) ? phi : nphi[i]);
+    St::store(c.pop[0][dst], long(i) * c.n + n, d);
+    if constexpr (St::fold) res += St::rounding(d);
   }
   if constexpr (COUPLED) {
     if (c.wall) {

@@ -47,8 +47,8 @@ __device__ __forceinline__ void divmod_pitch(int v, int P, float rcpP, int& q, i
 // uniform base, so each address is one shift-add with no sign extension: directions
 // 2, 5, 6 index from their own planes (a bounce from the bottom wall reads plane
 // opp(i) = i + 2 at s0 + 2n), directions 4, 7, 8 from the plane of opp(i) = i - 2 (their
-// own entry lies 2n further on; a bounce from the top wall reads s0 there).  ps: phi of
-// the writer (shifted storage).
+// own entry lies 2n further on; a bounce from the top wall reads s0 there).  ps (shifted
+// storage): the phi the stored deviations refer to, this node's own phis entry.
 template <class St>
 __device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9], const float* __restrict__ phis,
                                            int x, int y, int nx, int ny, int n, bool wall,
@@ -73,10 +73,12 @@ __device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9]
   }
   const typename St::S* base[9] = {src[0], src[1], src[2], src[3], src[2], src[5], src[6], src[5], src[6]};
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    v[i] = St::load(base[i], off[i]);
-    if constexpr (St::shifted) {
-      if (ps) ps[i] = R(ldg(phis, nd[i]));
+  for (int i = 0; i < 9; ++i) v[i] = St::load(base[i], off[i]);
+  if constexpr (St::shifted) {   // every deviation refers to this node's own phis entry
+    if (ps) {
+      const R own = R(ldg(phis, s0));
+#pragma unroll
+      for (int i = 0; i < 9; ++i) ps[i] = own;
     }
   }
 }
@@ -178,11 +180,15 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
       }
       NodeOut<L, R> out;
       node_update_d2q9<R, true, St::shifted, UNIT>(c.np, in, e[SU], f, J, out);
-      R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
+      R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        St::store(c.pop[0][dst] + long(j) * n, nn, e[SU][j]);
-        if constexpr (St::fold) res += St::rounding(e[SU][j]);
+        R d = e[SU][j];
+        if constexpr (St::shifted)   // relative to the reader's phi (encode_dev)
+          d = encode_dev(e[SU][j], c.np.rest[j], in.nphi[0],
+                         leaves_through_wall<L>(j, y, ny, wall) ? in.nphi[0] : in.nphi[j]);
+        St::store(c.pop[0][dst] + long(j) * n, nn, d);
+        if constexpr (St::fold) res += St::rounding(d);
       }
       if (wall && y == 0) {
 #pragma unroll

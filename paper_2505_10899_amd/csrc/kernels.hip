@@ -75,7 +75,8 @@ __global__ void __launch_bounds__(256) k_init(DevCase<L, St> c, const double* __
     zs = wrapi(zs, c.nz);
     const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
     R gv = geq;
-    if constexpr (St::shifted) gv -= R(float(phi0[s])) * c.np.rest[pi];
+    // shifted storage: relative to the reader's phis entry, phi0 at this node n
+    if constexpr (St::shifted) gv -= R(float(phi0[n])) * c.np.rest[pi];
     St::store(c.pop[0][0], long(pi) * c.n + s, gv);
     if constexpr (COUPLED) St::store(c.pop[1][0], long(pi) * c.n + s, feq);
   }
@@ -106,9 +107,9 @@ __global__ void __launch_bounds__(256) k_set_state(DevCase<L, St> c, const doubl
     zs = wrapi(zs, c.nz);
     const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
     R gv = R(g[long(i) * c.n + n]);
-    if constexpr (St::shifted) {
+    if constexpr (St::shifted) {   // relative to the reader's (this node n's) phis entry
       double ps = 0.0;
-      for (int k = 0; k < L::Q; ++k) ps += g[long(k) * c.n + s];
+      for (int k = 0; k < L::Q; ++k) ps += g[long(k) * c.n + n];
       gv -= R(float(ps)) * c.np.rest[pi];
     }
     St::store(c.pop[0][par], long(pi) * c.n + s, gv);
@@ -258,7 +259,7 @@ __global__ void __launch_bounds__(256) k_collide_plain(DevCase<L, St> c, int red
 #pragma unroll
       for (int i = 0; i < L::Q; ++i) g[i] += R(L::w[i]) * src;
     }
-    store_node<L, St, COUPLED>(c, par, n, y, in.nphi[0], out.rho, g, f, J);
+    store_node<L, St, COUPLED>(c, par, n, y, in.nphi, out.rho, g, f, J);
     if (reduce) accumulate(c, acc, double(in.nphi[0]), x, y, z);
   }
   finish_block(c, acc, reduce != 0);
@@ -332,8 +333,11 @@ __global__ void __launch_bounds__(BS, (step2d_min_blocks<St, UNIT, BS>()))
   const int nstrips = gridDim.x / nseg;
   const int seg = tile / nstrips, strip = tile - seg * nstrips;
   const int y0 = seg * TY;
-  step2d_tile<St, COUPLED, IX, UNIT, VISC>(c, c.t, strip * int(blockDim.x), y0, min(y0 + TY, c.ny), reduce != 0,
-                                           c.part_w, gridDim.x, blockIdx.x, smem_raw);
+  // non-temporal population accesses for 4- and 8-byte storage (2-byte storage measured
+  // no faster with them)
+  constexpr bool NT = sizeof(typename St::S) >= 4;
+  step2d_tile<St, COUPLED, IX, UNIT, VISC, NT>(c, c.t, strip * int(blockDim.x), y0, min(y0 + TY, c.ny),
+                                               reduce != 0, c.part_w, gridDim.x, blockIdx.x, smem_raw);
 }
 
 // ---------------------------------------------------------------- second reduction pass

@@ -36,8 +36,8 @@ __device__ __forceinline__ Nbr3 nbr3(int x, int y, int z, int nx, int ny, int nz
 
 // The 19 pulls at one node: 32-bit node offsets from the uniform base of each
 // direction's plane (the case has fewer than 2^31 nodes), accessed with index type IX
-// (unsigned: 32-bit byte offsets, when n times the element size fits them).  ps: phi of
-// the writer.
+// (unsigned: 32-bit byte offsets, when n times the element size fits them).  ps (shifted
+// storage): the phi the stored deviations refer to, this node's own phis entry.
 template <class St, class IX>
 __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, const float* __restrict__ phis,
                                        long n, const Nbr3& o, typename St::R (&out)[19], typename St::R* ps) {
@@ -53,10 +53,14 @@ __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, c
     if constexpr (L::cz[i] > 0) s += o.zm;
     if constexpr (L::cz[i] < 0) s += o.zp;
     out[i] = St::load(src + i * n, IX(s));
-    if constexpr (St::shifted) {
-      if (ps) ps[i] = R(ldg(phis, IX(s)));
-    }
   });
+  if constexpr (St::shifted) {   // every deviation refers to this node's own phis entry
+    if (ps) {
+      const R own = R(ldg(phis, IX(o.s0)));
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) ps[i] = own;
+    }
+  }
 }
 
 // Workgroups per CU the register budget is sized for (256 lanes each): with 4-byte
@@ -209,11 +213,16 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
       NodeOut<L, R> out;
       node_update_mom_s<L, R, true, St::shifted, UNIT, VISC>(c.np, st, gcur, f, J, out);
       const int dst = par ^ 1;
-      R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
+      R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        St::store(c.pop[0][dst] + i * c.n, IX(nn), gcur[i]);
-        if constexpr (St::fold) res += St::rounding(gcur[i]);
+        R d = gcur[i];
+        if constexpr (St::shifted) {   // relative to the reader's phi, read back from the ring
+          const int sr = slot(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
+          d = encode_dev(gcur[i], c.np.rest[i], st.phi, sring[sr].phi);
+        }
+        St::store(c.pop[0][dst] + i * c.n, IX(nn), d);
+        if constexpr (St::fold) res += St::rounding(d);
       }
 #pragma unroll
       for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, IX(nn), f[i]);

@@ -50,7 +50,29 @@ __device__ __forceinline__ void stg(T* p, unsigned i, T v) {
   *(T VCLB_GLOBAL*)((char VCLB_GLOBAL*)p + b) = v;
 }
 
+// Non-temporal forms: the access carries the streaming hint, so that the line is not
+// kept for reuse (a population is read once and written once per step).
+template <class T, class I>
+__device__ __forceinline__ T ldg_nt(const T* p, I i) {
+  return __builtin_nontemporal_load((const T VCLB_GLOBAL*)p + i);
+}
+template <class T, class I>
+__device__ __forceinline__ void stg_nt(T* p, I i, T v) {
+  __builtin_nontemporal_store(v, (T VCLB_GLOBAL*)p + i);
+}
+template <class T>
+__device__ __forceinline__ T ldg_nt(const T* p, unsigned i) {
+  const unsigned b = i * unsigned(sizeof(T));
+  return __builtin_nontemporal_load((const T VCLB_GLOBAL*)((const char VCLB_GLOBAL*)p + b));
+}
+template <class T>
+__device__ __forceinline__ void stg_nt(T* p, unsigned i, T v) {
+  const unsigned b = i * unsigned(sizeof(T));
+  __builtin_nontemporal_store(v, (T VCLB_GLOBAL*)((char VCLB_GLOBAL*)p + b));
+}
+
 // ---------------------------------------------------------------- storage codecs
+// load / store: plain accesses; load_nt / store_nt: with the non-temporal hint
 // fold: the storage rounds coarsely enough that the writer phi stored beside a node's g
 // absorbs the sum of their rounding errors (rounding(v): stored value minus v)
 struct StoreF64 {
@@ -63,6 +85,10 @@ struct StoreF64 {
   __device__ static R load(const S* p, I i) { return ldg(p, i); }
   template <class I>
   __device__ static void store(S* p, I i, R v) { stg(p, i, v); }
+  template <class I>
+  __device__ static R load_nt(const S* p, I i) { return ldg_nt(p, i); }
+  template <class I>
+  __device__ static void store_nt(S* p, I i, R v) { stg_nt(p, i, v); }
 };
 // FP32 storage uses the same deviation representation as FP16S (see below): the g
 // arithmetic then never rounds at the magnitude of the rest populations (~0.7), which
@@ -77,21 +103,26 @@ struct StoreF32 {
   __device__ static R load(const S* p, I i) { return ldg(p, i); }
   template <class I>
   __device__ static void store(S* p, I i, R v) { stg(p, i, v); }
+  template <class I>
+  __device__ static R load_nt(const S* p, I i) { return ldg_nt(p, i); }
+  template <class I>
+  __device__ static void store_nt(S* p, I i, R v) { stg_nt(p, i, v); }
 };
 // FP16 storage of deviations from the rest equilibrium: g_i - phi r_i with
-// r_0 = 1 + (w_0 - 1) lambda, r_i = w_i lambda (g_eq at u = 0, mu = 0); f is stored
-// as is (its rest equilibrium, f_eq at p = 0 and u = 0, vanishes).  phi of the node
-// that wrote the value travels beside it in FP32.  Shifted storage also switches the
-// g collision to deviation variables e_i = g_i - r_i phi (node_update, SH = true).
+// r_0 = 1 + (w_0 - 1) lambda, r_i = w_i lambda (g_eq at u = 0, mu = 0), where phi is that
+// of the node that will read the value, kept in FP32 in the reader's own entry of a phi
+// array (encode_dev); f is stored as is (its rest equilibrium, f_eq at p = 0 and u = 0,
+// vanishes).  Shifted storage also switches the g collision to deviation variables
+// e_i = g_i - r_i phi (node_update, SH = true).
 struct StoreF16S {
   using S = __half;
   using R = float;
   static constexpr bool shifted = true;
-  // A node's stored deviations, rounded to 2 bytes, change the sum of its nine g by the
-  // sum of their rounding errors; at a node in a steady state that error is the same
-  // every step, so the total of phi would drift steadily.  The writer phi stored beside
-  // them (FP32) takes that sum off, so the populations its neighbours decode add up to
-  // the node's phi again.
+  // A node's stored deviations, rounded to 2 bytes, change the total of g by the sum of
+  // their rounding errors; at a node in a steady state that error is the same every step,
+  // so the total of phi would drift steadily.  The node's own phi entry (FP32), which its
+  // next pull adds back to every population it reads, is stored less that sum, so that the
+  // total of the decoded populations stays the total of phi.
   static constexpr bool fold = true;
   __device__ static R rounding(R v) { return __half2float(__float2half_rn(v)) - v; }
   template <class I>
@@ -101,6 +132,14 @@ struct StoreF16S {
   template <class I>
   __device__ static void store(S* p, I i, R v) {
     stg(reinterpret_cast<unsigned short*>(p), i, __half_as_ushort(__float2half_rn(v)));
+  }
+  template <class I>
+  __device__ static R load_nt(const S* p, I i) {
+    return __half2float(__ushort_as_half(ldg_nt(reinterpret_cast<const unsigned short*>(p), i)));
+  }
+  template <class I>
+  __device__ static void store_nt(S* p, I i, R v) {
+    stg_nt(reinterpret_cast<unsigned short*>(p), i, __half_as_ushort(__float2half_rn(v)));
   }
 };
 

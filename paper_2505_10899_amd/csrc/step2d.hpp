@@ -14,8 +14,9 @@ struct Col3 { int c, m, p; };
 struct Row3 { int c, m, p; bool lo, hi; };
 
 // IX: index type of the accesses; unsigned when every node index times the element size
-// fits 32 bits (32-bit byte offsets from uniform bases), else long.
-template <class St, class IX>
+// fits 32 bits (32-bit byte offsets from uniform bases), else long.  NT: population loads
+// with the non-temporal hint.
+template <class St, class IX, bool NT = false>
 __device__ __forceinline__ void pull9(const typename St::S* const (&src)[9], const float* __restrict__ phis,
                                       const Col3& x, const Row3& y, typename St::R (&v)[9],
                                       typename St::R* ps) {
@@ -34,10 +35,12 @@ __device__ __forceinline__ void pull9(const typename St::S* const (&src)[9], con
     off[8] = s0; base[8] = src[6];
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    v[i] = St::load(base[i], IX(off[i]));
-    if constexpr (St::shifted) {
-      if (ps) ps[i] = R(ldg(phis, IX(off[i])));
+  for (int i = 0; i < 9; ++i) v[i] = NT ? St::load_nt(base[i], IX(off[i])) : St::load(base[i], IX(off[i]));
+  if constexpr (St::shifted) {   // every deviation refers to this node's own phis entry
+    if (ps) {
+      const R own = R(ldg(phis, IX(s0)));
+#pragma unroll
+      for (int i = 0; i < 9; ++i) ps[i] = own;
     }
   }
 }
@@ -55,8 +58,10 @@ struct Acc2 {
 // (plus one halo column on each side, computed by lanes 0 and 1), then applies the
 // stencils from LDS and updates the current row: every population is read from HBM
 // once, except the two halo columns and the two halo rows of the tile.
-// UNIT: the case's rates outside the g flux and f stress rows are all 1
-template <class St, bool COUPLED, class IX, bool UNIT, bool VISC = false>
+// UNIT: the case's rates outside the g flux and f stress rows are all 1.  NT: population
+// loads and stores with the non-temporal hint (measured faster for the single-case
+// strips of 4-byte and 8-byte storage, slower in the batched march).
+template <class St, bool COUPLED, class IX, bool UNIT, bool VISC = false, bool NT = false>
 __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, int x0, int y0, int y1, bool reduce,
                                             double* __restrict__ part, long part_stride, long part_index,
                                             unsigned char* smem_raw) {
@@ -109,12 +114,12 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
   auto phi_row = [&](int r, R (&g)[Q]) {
     const Row3 rw = row3(r);
     R ps[Q];
-    pull9<St, IX>(gsrc, phis, col, rw, g, ps);
+    pull9<St, IX, NT>(gsrc, phis, col, rw, g, ps);
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     sring[slot(r) * W + lane + 1] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
     if (halo_lane) {
       R gh[Q], hps[Q];
-      pull9<St, IX>(gsrc, phis, hcol, rw, gh, hps);
+      pull9<St, IX, NT>(gsrc, phis, hcol, rw, gh, hps);
       const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       sring[slot(r) * W + hidx] = PhiPsi{hp, psi_of<R>(hp, c.np.W4, c.np.xi)};
     }
@@ -137,7 +142,7 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
     // so that one memory round trip per row covers both
     const int nn = xw + nx * y;
     R f[Q], J[2];
-    if constexpr (COUPLED) pull9<St, IX>(fsrc, phis, col, row3(y), f, nullptr);
+    if constexpr (COUPLED) pull9<St, IX, NT>(fsrc, phis, col, row3(y), f, nullptr);
     J[0] = ldg(c.J, IX(nn));
     J[1] = ldg(c.J + n, IX(nn));
     phi_row(y + 1, gnext);
@@ -159,11 +164,16 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
       }
       NodeOut<L, R> out;
       node_update_d2q9<R, COUPLED, St::shifted, UNIT, VISC>(c.np, in, gcur, f, J, out);
-      R res = R(0);   // rounding of the stored g deviations, taken off the writer phi
+      R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        St::store(c.pop[0][dst] + long(i) * n, IX(nn), gcur[i]);
-        if constexpr (St::fold) res += St::rounding(gcur[i]);
+        R d = gcur[i];
+        if constexpr (St::shifted)   // relative to the reader's phi (encode_dev)
+          d = encode_dev(gcur[i], c.np.rest[i], in.nphi[0],
+                         leaves_through_wall<L>(i, y, ny, wall) ? in.nphi[0] : in.nphi[i]);
+        if constexpr (NT) St::store_nt(c.pop[0][dst] + long(i) * n, IX(nn), d);
+        else St::store(c.pop[0][dst] + long(i) * n, IX(nn), d);
+        if constexpr (St::fold) res += St::rounding(d);
       }
       if constexpr (COUPLED) {
         if (wall && y == 0) {
@@ -177,7 +187,10 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
             if (L::cy[i] > 0) f[i] += c.np.wt[i] * out.rho;
         }
 #pragma unroll
-        for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + long(i) * n, IX(nn), f[i]);
+        for (int i = 0; i < Q; ++i) {
+          if constexpr (NT) St::store_nt(c.pop[1][dst] + long(i) * n, IX(nn), f[i]);
+          else St::store(c.pop[1][dst] + long(i) * n, IX(nn), f[i]);
+        }
       }
       stg(c.J, IX(nn), J[0]);
       stg(c.J + n, IX(nn), J[1]);

@@ -95,6 +95,9 @@ _SIGS = [
     ("vclb_batch_nodes", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_int64)]),
     ("vclb_bandwidth_probe", ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                              ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_double), ctypes.c_void_p]),
+    ("vclb_bandwidth_probe_ex", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                                _P(ctypes.c_double), ctypes.c_void_p]),
     ("vclb_batch_init", ctypes.c_int, [ctypes.c_void_p, _P(ctypes.c_void_p), _P(ctypes.c_void_p), ctypes.c_int,
                                         ctypes.c_void_p]),
     ("vclb_batch_set_tile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
@@ -451,6 +454,30 @@ def bandwidth_probe(mode: str = "copy", nbytes: int = 2 << 30, reps: int = 10, b
                                      ctypes.c_size_t(n * 4), int(reps), int(blocks), ctypes.byref(g),
                                      _stream_handle(stream)))
     return g.value
+
+
+def bandwidth_probe_best(mode: str = "copy", nbytes: int = 2 << 30, reps: int = 5, device="cuda", stream=None):
+    """Fastest rate (GB/s) of the probe over its kernel shapes (vclb_bandwidth_probe_ex):
+    vectors in flight per lane {1, 2, 4, 8} x plain / non-temporal accesses x {2, 4, 8, 16}
+    workgroups per compute unit.  Returns (GB/s, {"unroll", "nontemporal",
+    "blocks_per_cu"})."""
+    m = {"copy": 0, "read": 1, "write": 2}[mode]
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device=device) if m != 2 else None
+    dst = torch.empty(n if m != 1 else 4, dtype=torch.float32, device=device)
+    ncu = torch.cuda.get_device_properties(torch.device(device)).multi_processor_count
+    best, cfg = 0.0, None
+    for unroll in (1, 2, 4, 8):
+        for nt in (0, 1):
+            for per_cu in (2, 4, 8, 16):
+                g = ctypes.c_double(0.0)
+                check(lib().vclb_bandwidth_probe_ex(m, unroll, nt, ctypes.c_void_p(dst.data_ptr()),
+                                                    ctypes.c_void_p(src.data_ptr() if src is not None else 0),
+                                                    ctypes.c_size_t(n * 4), int(reps), int(per_cu * ncu),
+                                                    ctypes.byref(g), _stream_handle(stream)))
+                if g.value > best:
+                    best, cfg = g.value, {"unroll": unroll, "nontemporal": nt, "blocks_per_cu": per_cu}
+    return best, cfg
 
 
 def obs_derived(arr, nlabels: int) -> np.ndarray:

@@ -340,14 +340,13 @@ def _sample(cases):
     return sorted(idx)
 
 
-# launch configurations the benchmark's autotuner has picked on this batch: 512-lane
+# every launch shape the benchmark may time the batch in (bench.BATCH_SHAPES): 512-lane
 # workgroups with whole-case items (ty 1024) or items of about 16k nodes (ty 64), with
 # bands for the cases that fit the two-slot FIFO and strips for the wider ones
 # (flat_pct 100) or bands for every case (101, the four-slot FIFO kernel); and 1024-lane
-# workgroups (FP32, FP16S), which fit every case's padded row in one chunk, with whole
-# cases or 16k-node items.  The autotuner may pick any shape of its search; the benchmark
-# therefore also checks its timed state bit for bit against the first shape here.
-FULL_SHAPES = [(512, 1024, 100), (512, 1024, 101), (512, 64, 100), (1024, 1024, 101), (1024, 64, 100)]
+# workgroups (FP32, FP16S), which fit every case's padded row in one chunk.
+import bench  # noqa: E402
+FULL_SHAPES = list(bench.BATCH_SHAPES)
 
 
 def _full_batch(v, storage, bx, ty, flat_pct):

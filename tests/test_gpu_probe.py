@@ -44,3 +44,26 @@ def test_probe_moves_what_it_claims_and_reports_a_sane_rate():
     assert 100.0 < g.value < 8000.0, g.value
     for mode in ("copy", "read", "write"):
         assert 100.0 < v.bandwidth_probe(mode, nbytes=512 << 20, reps=3) < 8000.0
+
+
+@pytest.mark.parametrize("unroll,nt", [(2, 0), (8, 1), (4, 1)])
+def test_probe_shapes_move_what_they_claim(unroll, nt):
+    """Every kernel shape of the probe sweep copies and fills the whole buffer, including a
+    ragged last tile."""
+    import torch
+    v = _v()
+    n = (64 << 20) // 4 + 12                                 # not a multiple of any tile
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.zeros(n, dtype=torch.float32, device="cuda")
+    g = ctypes.c_double(0.0)
+    s = torch.cuda.current_stream().cuda_stream
+    print(f"case: probe shape unroll {unroll}, non-temporal {nt}", flush=True)
+    rc = v.lib().vclb_bandwidth_probe_ex(0, unroll, nt, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                         ctypes.c_size_t(n * 4), 2, 97, ctypes.byref(g), ctypes.c_void_p(s))
+    assert rc == 0 and torch.equal(dst, src) and 100.0 < g.value < 8000.0
+    rc = v.lib().vclb_bandwidth_probe_ex(2, unroll, nt, ctypes.c_void_p(dst.data_ptr()), None, ctypes.c_size_t(n * 4),
+                                         2, 0, ctypes.byref(g), ctypes.c_void_p(s))
+    pattern = torch.tensor([1.0, 2.0, 3.0, 4.0], device="cuda").repeat(n // 4)
+    assert rc == 0 and torch.equal(dst, pattern)
+    assert v.lib().vclb_bandwidth_probe_ex(0, 3, 0, ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                           ctypes.c_size_t(n * 4), 2, 0, ctypes.byref(g), ctypes.c_void_p(s)) == -1
