@@ -34,6 +34,21 @@ __device__ __forceinline__ Nbr3 nbr3(int x, int y, int z, int nx, int ny, int nz
   return o;
 }
 
+// Offset of the writer of direction i from the uniform base of its plane: the node's own
+// index s0 moved by one of xm / xp, ym / yp, zm / zp per axis.
+template <int i>
+__device__ __forceinline__ int pull_index(const Nbr3& o) {
+  using L = D3Q19;
+  int s = o.s0;
+  if constexpr (L::cx[i] > 0) s += o.xm;
+  if constexpr (L::cx[i] < 0) s += o.xp;
+  if constexpr (L::cy[i] > 0) s += o.ym;
+  if constexpr (L::cy[i] < 0) s += o.yp;
+  if constexpr (L::cz[i] > 0) s += o.zm;
+  if constexpr (L::cz[i] < 0) s += o.zp;
+  return s;
+}
+
 // The 19 pulls at one node: 32-bit node offsets from the uniform base of each
 // direction's plane (the case has fewer than 2^31 nodes), accessed with index type IX
 // (unsigned: 32-bit byte offsets, when n times the element size fits them).  ps (shifted
@@ -45,14 +60,7 @@ __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, c
   using R = typename St::R;
   static_for<0, L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    int s = o.s0;
-    if constexpr (L::cx[i] > 0) s += o.xm;
-    if constexpr (L::cx[i] < 0) s += o.xp;
-    if constexpr (L::cy[i] > 0) s += o.ym;
-    if constexpr (L::cy[i] < 0) s += o.yp;
-    if constexpr (L::cz[i] > 0) s += o.zm;
-    if constexpr (L::cz[i] < 0) s += o.zp;
-    out[i] = St::load(src + i * n, IX(s));
+    out[i] = St::load(src + i * n, IX(pull_index<i>(o)));
   });
   if constexpr (St::shifted) {   // every deviation refers to this node's own phis entry
     if (ps) {
@@ -77,6 +85,121 @@ constexpr int step3d_min_blocks() {
   return BS > 256 ? 1 : (stage3d<St>() ? 3 : 2);
 }
 
+// phi and psi of a node side by side: one 2-word LDS access per stencil point
+template <class R>
+struct alignas(2 * sizeof(R)) PhiPsi3 {
+  R phi, psi;
+};
+
+// slot of plane z in the 4-plane ring (z >= -1)
+__device__ __forceinline__ int ring_slot3d(int z) { return (z + 4) & 3; }
+
+// Update of the node (xw, yw, z) held by lane (tx, ty) of its section: g (pulled, as
+// deviations from the node's own rest state for shifted storage), f and the previous
+// phi u in registers, phi and psi of the 18 neighbours in the ring of PS = PW x (BY + 2)
+// nodes per plane.  Stores the post-collision state and accumulates the reductions.
+template <class St, int NL, bool UNIT, bool VISC, class IX>
+__device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const PhiPsi3<typename St::R>* sring,
+                                              int PS, int PW, int tx, int ty, int xw, int yw, int z, int nn, int par,
+                                              typename St::R (&gcur)[19], typename St::R (&f)[19],
+                                              typename St::R (&J)[3], bool reduce, double (&s0)[NL], double (&s1)[NL],
+                                              double (&s2)[NL], int (&cnt)[NL], int (&bad)[NL]) {
+  using L = D3Q19;
+  using R = typename St::R;
+  constexpr int Q = L::Q;
+  // stencils of Eqs. 39-40 accumulated straight from the LDS ring
+  StencilOut<L, R> st;
+  const int s0i = ring_slot3d(z) * PS + (ty + 1) * PW + tx + 1;
+  st.phi = sring[s0i].phi;
+  st.lap = R(0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) st.gphi[d] = st.gpsi[d] = R(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int s = ring_slot3d(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
+    const PhiPsi3<R> v = sring[s];
+    const R ph = v.phi, ps = v.psi;
+    st.lap += R(6.0 * L::w[i]) * (ph - st.phi);
+    if (L::cx[i] != 0) { st.gphi[0] += R(3.0 * L::w[i] * L::cx[i]) * ph; st.gpsi[0] += R(3.0 * L::w[i] * L::cx[i]) * ps; }
+    if (L::cy[i] != 0) { st.gphi[1] += R(3.0 * L::w[i] * L::cy[i]) * ph; st.gpsi[1] += R(3.0 * L::w[i] * L::cy[i]) * ps; }
+    if (L::cz[i] != 0) { st.gphi[2] += R(3.0 * L::w[i] * L::cz[i]) * ph; st.gpsi[2] += R(3.0 * L::w[i] * L::cz[i]) * ps; }
+  }
+  NodeOut<L, R> out;
+  node_update_mom_s<L, R, true, St::shifted, UNIT, VISC>(c.np, st, gcur, f, J, out);
+  const int dst = par ^ 1;
+  R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R d = gcur[i];
+    if constexpr (St::shifted) {   // relative to the reader's phi, read back from the ring
+      const int sr = ring_slot3d(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
+      d = encode_dev(gcur[i], c.np.rest[i], st.phi, sring[sr].phi);
+    }
+    St::store(c.pop[0][dst] + i * c.n, IX(nn), d);
+    if constexpr (St::fold) res += St::rounding(d);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, IX(nn), f[i]);
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) stg(c.J + d * c.n, IX(nn), J[d]);
+  if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi - res));
+  if (reduce) {
+    const double ph = double(st.phi);
+    int lab = 0;
+    if constexpr (NL > 1) {
+      double r[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double dx = min_image(double(xw) - c.cen[k][0], c.nx, true);
+        const double dy = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
+        const double dz = min_image(double(z) - c.cen[k][2], c.nz, true);
+        r[k] = dx * dx + dy * dy + dz * dz;
+      }
+      lab = (r[1] < r[0]) ? 1 : 0;
+    }
+    const bool fin = isfinite(ph);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const double dz = min_image(double(z) - c.cen[k][2], c.nz, true);
+      const double w = (k == lab) ? ph : 0.0;
+      s0[k] += w;
+      s1[k] += w * dz;
+      s2[k] += w * dz * dz;
+      cnt[k] += (k == lab && ph >= 0.5) ? 1 : 0;
+      bad[k] += (k == lab && !fin) ? 1 : 0;
+    }
+  }
+}
+
+// End of a section's march: its partial reductions (the lane's x and y are fixed, so
+// only the z moments were accumulated per plane) into the workgroup's slot.
+template <class St, int NL>
+__device__ __forceinline__ void finish_section3d(const DevCase<D3Q19, St>& c, int xw, int yw, const double (&s0)[NL],
+                                                 const double (&s1)[NL], const double (&s2)[NL], const int (&cnt)[NL],
+                                                 const int (&bad)[NL], int reduce, double* red) {
+  Acc acc;
+  acc.zero();
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const double dx = min_image(double(xw) - c.cen[k][0], c.nx, true);
+    const double dy = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
+    acc.v[k][0] = s0[k];
+    acc.v[k][1] = double(cnt[k]);
+    acc.v[k][2] = dx * s0[k];
+    acc.v[k][3] = dy * s0[k];
+    acc.v[k][4] = s1[k];
+    acc.v[k][5] = dx * dx * s0[k];
+    acc.v[k][6] = dy * dy * s0[k];
+    acc.v[k][7] = s2[k];
+    acc.v[k][8] = dx * dy * s0[k];
+    acc.v[k][9] = dx * s1[k];
+    acc.v[k][10] = dy * s1[k];
+    acc.v[k][11] = double(bad[k]);
+  }
+  __syncthreads();
+  finish_block(c, acc, reduce != 0, red);
+}
+
 // NL: labels of the volume reductions (1 or 2), fixed per case; UNIT: the case's rates
 // outside the g flux and f stress rows are all 1
 // VISC: the phases have different viscosities (per-node tau_f of the stress rows)
@@ -89,10 +212,7 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
   constexpr bool STAGE = stage3d<St>();
   extern __shared__ unsigned char smem_raw[];
   const int PW = BX + 2, PH = BY + 2, PS = PW * PH;
-  // phi and psi of a node side by side: one 2-word LDS access per stencil point
-  struct alignas(2 * sizeof(R)) PhiPsi {
-    R phi, psi;
-  };
+  using PhiPsi = PhiPsi3<R>;
   PhiPsi* sring = reinterpret_cast<PhiPsi*>(smem_raw);
   R* sg = reinterpret_cast<R*>(sring + 4 * PS);   // STAGE: [2][Q][nthr], the pulled g of planes z and z + 1, per lane
   const int nthr = BX * BY;
@@ -119,11 +239,10 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
   const float* phis = c.phis[par];
   const int nx = c.nx, ny = c.ny, nz = c.nz, nxy = nx * ny;
   const int ring = 2 * PW + 2 * BY;
-  auto slot = [](int r) -> int { return (r + 4) & 3; };
   // pull plane z into g, form phi and psi into the ring (with the halo ring)
   auto plane = [&](int z, R (&g)[Q]) {
     const int zr = wrapi(z, c.nz);
-    const int s = slot(z) * PS;
+    const int s = ring_slot3d(z) * PS;
     R ps[Q];
     pull19<St, IX>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy), g, ps);
     const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
@@ -193,95 +312,15 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     __syncthreads();
     if (active) {
       if constexpr (STAGE) stage_get(z, gcur);
-      // stencils of Eqs. 39-40 accumulated straight from the LDS ring
-      StencilOut<L, R> st;
-      const int s0i = slot(z) * PS + (ty + 1) * PW + tx + 1;
-      st.phi = sring[s0i].phi;
-      st.lap = R(0);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) st.gphi[d] = st.gpsi[d] = R(0);
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const int s = slot(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
-        const PhiPsi v = sring[s];
-        const R ph = v.phi, ps = v.psi;
-        st.lap += R(6.0 * L::w[i]) * (ph - st.phi);
-        if (L::cx[i] != 0) { st.gphi[0] += R(3.0 * L::w[i] * L::cx[i]) * ph; st.gpsi[0] += R(3.0 * L::w[i] * L::cx[i]) * ps; }
-        if (L::cy[i] != 0) { st.gphi[1] += R(3.0 * L::w[i] * L::cy[i]) * ph; st.gpsi[1] += R(3.0 * L::w[i] * L::cy[i]) * ps; }
-        if (L::cz[i] != 0) { st.gphi[2] += R(3.0 * L::w[i] * L::cz[i]) * ph; st.gpsi[2] += R(3.0 * L::w[i] * L::cz[i]) * ps; }
-      }
-      NodeOut<L, R> out;
-      node_update_mom_s<L, R, true, St::shifted, UNIT, VISC>(c.np, st, gcur, f, J, out);
-      const int dst = par ^ 1;
-      R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        R d = gcur[i];
-        if constexpr (St::shifted) {   // relative to the reader's phi, read back from the ring
-          const int sr = slot(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
-          d = encode_dev(gcur[i], c.np.rest[i], st.phi, sring[sr].phi);
-        }
-        St::store(c.pop[0][dst] + i * c.n, IX(nn), d);
-        if constexpr (St::fold) res += St::rounding(d);
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, IX(nn), f[i]);
-#pragma unroll
-      for (int d = 0; d < L::D; ++d) stg(c.J + d * c.n, IX(nn), J[d]);
-      if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi - res));
-      if (reduce) {
-        const double ph = double(st.phi);
-        int lab = 0;
-        if constexpr (NL > 1) {
-          double r[2];
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const double dx = min_image(double(xw) - c.cen[k][0], c.nx, true);
-            const double dy = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
-            const double dz = min_image(double(z) - c.cen[k][2], c.nz, true);
-            r[k] = dx * dx + dy * dy + dz * dz;
-          }
-          lab = (r[1] < r[0]) ? 1 : 0;
-        }
-        const bool fin = isfinite(ph);
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-          const double dz = min_image(double(z) - c.cen[k][2], c.nz, true);
-          const double w = (k == lab) ? ph : 0.0;
-          s0[k] += w;
-          s1[k] += w * dz;
-          s2[k] += w * dz * dz;
-          cnt[k] += (k == lab && ph >= 0.5) ? 1 : 0;
-          bad[k] += (k == lab && !fin) ? 1 : 0;
-        }
-      }
+      update_node3d<St, NL, UNIT, VISC, IX>(c, sring, PS, PW, tx, ty, xw, yw, z, nn, par, gcur, f, J, reduce != 0, s0,
+                                            s1, s2, cnt, bad);
     }
     if constexpr (!STAGE) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) gcur[i] = gnext[i];
     }
   }
-  Acc acc;
-  acc.zero();
-#pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const double dx = min_image(double(xw) - c.cen[k][0], c.nx, true);
-    const double dy = min_image(double(yw) - c.cen[k][1], c.ny, !c.wall);
-    acc.v[k][0] = s0[k];
-    acc.v[k][1] = double(cnt[k]);
-    acc.v[k][2] = dx * s0[k];
-    acc.v[k][3] = dy * s0[k];
-    acc.v[k][4] = s1[k];
-    acc.v[k][5] = dx * dx * s0[k];
-    acc.v[k][6] = dy * dy * s0[k];
-    acc.v[k][7] = s2[k];
-    acc.v[k][8] = dx * dy * s0[k];
-    acc.v[k][9] = dx * s1[k];
-    acc.v[k][10] = dy * s1[k];
-    acc.v[k][11] = double(bad[k]);
-  }
-  __syncthreads();
-  finish_block(c, acc, reduce != 0, reinterpret_cast<double*>(smem_raw));
+  finish_section3d<St, NL>(c, xw, yw, s0, s1, s2, cnt, bad, reduce, reinterpret_cast<double*>(smem_raw));
 }
 
 template <class St>
@@ -308,14 +347,16 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   int rc = 0;
   auto go = [&](auto nl, auto unit, auto ix, auto visc) {
     constexpr bool V = decltype(visc)::value;
+    constexpr int NL = decltype(nl)::value;
+    constexpr bool U = decltype(unit)::value;
     if (lanes <= 256) {
-      hipLaunchKernelGGL((k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 256, V>), grid, block,
-                         lds, s, c, tile.bx, tile.by3, nby, nbz, reduce);
+      hipLaunchKernelGGL((k_step3d<St, NL, U, decltype(ix), 256, V>), grid, block, lds, s, c, tile.bx, tile.by3, nby,
+                         nbz, reduce);
     } else if constexpr (stage3d<St>()) {
       // wide sections stage more than the default 64 KiB of dynamic LDS: raise this
       // instantiation's limit to the device maximum once per device (the tile check has
       // compared the section with that maximum)
-      auto kern = k_step3d<St, decltype(nl)::value, decltype(unit)::value, decltype(ix), 768, V>;
+      auto kern = k_step3d<St, NL, U, decltype(ix), 768, V>;
       static int raised[64] = {};   // per instantiation and device; a repeated raise is harmless
       int dev = 0, max_lds = 0;
       if (hipGetDevice(&dev) != hipSuccess) {
