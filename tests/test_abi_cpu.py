@@ -61,6 +61,7 @@ def test_valid_params_pass():
     dict(mode="vortex", T=0.0), dict(lattice="D3Q19", wall_y=True, nz=4),
     dict(lattice="D3Q19", mode="vortex", nz=4), dict(wall_y=True, ny=1),
     dict(label_centres=[(0, 0, 0)] * 3),
+    dict(nx=65536, ny=32768),                    # 2^31 nodes: one more than the largest case
 ])
 def test_invalid_params_rejected_without_gpu(change):
     v = _vclb()
@@ -73,6 +74,20 @@ def test_invalid_params_rejected_without_gpu(change):
     rc = v.lib().vclb_case_create(ctypes.byref(v.to_cparams(p)), None, 0, ctypes.byref(h))
     assert rc == v.VCLB_EINVAL and not h.value
     assert len(v.lib().vclb_last_error()) > 0
+
+
+def test_largest_case_validates_with_64_bit_sizes():
+    """2^31 - 1 nodes is the largest case (node indices are 32-bit inside the kernels); its
+    workspace, far beyond 2^32 bytes, is sized without overflow (no HIP call)."""
+    v = _vclb()
+    p = _valid().replace(nx=46341, ny=46340, label_centres=[(100.0, 100.0, 0.0)])
+    assert p.nx * p.ny <= 2 ** 31 - 1
+    v.validate(p)
+    b = {s: v.workspace_bytes(p.replace(storage=s)) for s in ("fp16s", "fp32", "fp64")}
+    n = p.nx * p.ny
+    # at least the populations (2 sets, A and B) and the previous phi u of every node
+    assert b["fp64"] >= n * (2 * 2 * 9 * 8 + 2 * 8) > 2 ** 39
+    assert b["fp16s"] < b["fp32"] < b["fp64"]
 
 
 def test_workspace_grows_with_storage_precision():
