@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_batch512.txt")
 
 # Algorithmic HBM bytes per node update: every population read once and written once,
-# the previous phi u read and written, and, for the 2-byte storage only, the FP32 phi of
-# the node that wrote a set of deviations written once and read once (the 2-byte
-# deviations cannot be decoded without it).  (lattice, coupled) -> storage -> bytes
+# the previous phi u read and written, and, for the 2-byte storage only, the FP32 phi the
+# stored deviations refer to (that of the node that reads them) written once and read
+# once (the 2-byte deviations cannot be decoded without it).  (lattice, coupled) -> storage -> bytes
 BYTES_PER_NODE = {
     ("D2Q9", True): {"fp64": 2 * 9 * 8 * 2 + 2 * 8 * 2,                 # 320
                      "fp32": 2 * 9 * 4 * 2 + 2 * 4 * 2,                 # 160
@@ -52,8 +52,8 @@ BYTES_PER_NODE = {
                       "fp16s": 2 * 19 * 2 * 2 + 3 * 4 * 2 + 4 * 2},     # 184
 }
 # What the kernels of this library move per node update in their layout: FP32 storage
-# also keeps g as deviations from the writer's rest state, with the writer's phi
-# beside them (4 B written, 4 B read), to hold the total of phi to FP32 rounding.
+# also keeps g as deviations from a rest state, with the phi they refer to beside them
+# (4 B written, 4 B read), to hold the total of phi to FP32 rounding.
 LAYOUT_EXTRA = {"fp64": 0, "fp32": 8, "fp16s": 0}
 
 

@@ -97,6 +97,18 @@ typedef struct {
   int32_t nlabels;          /* 0: one label covering the domain; else 1..VCLB_MAX_LABELS   */
   double  wall_u[3][2][3];  /* velocity of the wall on each VCLB_WALL face (ignored on
                                periodic faces); its normal component must be 0            */
+  double  wall_cos[3][2];   /* wetting: cos(theta) of each VCLB_WALL face, theta the contact
+                               angle measured in the heavy phase (phi = 1), |cos| <= 1; 0 on
+                               periodic faces.  The paper states no boundary conditions;
+                               this is a reading.  The equilibrium profile (Eqs. 4-5) has
+                               |grad phi| = (4 / W) phi (1 - phi), so a wall meeting the
+                               interface at theta has a normal derivative of phi, into the
+                               fluid, of -(4 / W) cos(theta) phi (1 - phi).  The stencils
+                               (Eqs. 39-40) see, behind the half-way wall, the ghost
+                               phi_g = phi_e + (4 / W) cos(theta) phi_e (1 - phi_e) of the
+                               edge row's phi_e, and psi (Eq. 37) of phi_g.  0, the
+                               default (theta = 90 degrees), makes the ghost the edge
+                               row's mirror.  Not supported by the adjoint.              */
   double  W;                /* interface width (Eq. 4), > 0                                 */
   double  sigma;            /* surface tension, >= 0 (beta = 12 sigma / W, kappa = 3 sigma W / 2) */
   double  mobility;         /* M > 0; tau_g = 1/2 + M / c_s^2 (Eq. 34)                      */

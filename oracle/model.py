@@ -95,12 +95,31 @@ class Model:
         self.cvec = lat.c[:, :D].astype(np.float64)      # (Q, D)
 
     # ------------------------------------------------------------------ stencils
-    def _pad(self, a):
+    def wet_ghost(self, edge, side):
+        """phi of the ghost row behind a wall (side 0: bottom, 1: top) from the edge row's
+        phi_e.  The equilibrium profile (Eqs. 4-5) has |grad phi| = (4 / W) phi (1 - phi);
+        where the interface meets the wall at the contact angle theta (measured in the
+        heavy phase), the normal derivative of phi into the fluid is then
+        -(4 / W) cos(theta) phi (1 - phi).  Taken as the one-sided difference across the
+        half-way wall with phi at the edge node: phi_g = phi_e + (4 / W) cos(theta)
+        phi_e (1 - phi_e).  theta = 90 degrees (cos = 0) gives the mirror phi_g = phi_e.
+        (A reading: the paper states no boundary conditions.)"""
+        p = self.p
+        cw = getattr(p, "wall_cos_bottom" if side == 0 else "wall_cos_top", 0.0)
+        if cw == 0.0:
+            return edge
+        return edge + 4.0 / p.W * cw * edge * (1.0 - edge)
+
+    def _pad(self, a, wet=False):
         """One ghost layer: periodic axes wrap; wall axes (y) mirror the first interior
         node across the half-way wall, i.e. zero normal gradient (a reading: the paper
-        does not state its boundary conditions)."""
+        does not state its boundary conditions).  wet: a is phi, and the ghost rows are
+        the wetting ghosts of the edge rows (wet_ghost)."""
         a = np.pad(a, ((1, 1), (0, 0), (0, 0)), mode="wrap")
         a = np.pad(a, ((0, 0), (1, 1), (0, 0)), mode="edge" if self.p.wall_y else "wrap")
+        if wet and self.p.wall_y:
+            a[:, 0, :] = self.wet_ghost(a[:, 1, :], 0)
+            a[:, -1, :] = self.wet_ghost(a[:, -2, :], 1)
         a = np.pad(a, ((0, 0), (0, 0), (1, 1)), mode="wrap")
         return a
 
@@ -109,11 +128,9 @@ class Model:
         cx, cy, cz = (int(v) for v in ci)
         return ap[1 + cz:1 + cz + nz, 1 + cy:1 + cy + ny, 1 + cx:1 + cx + nx]
 
-    def grad(self, a):
-        """Isotropic gradient, Eq. 39: sum_{i != 0} w_i c_i a(x + c_i) / cs^2."""
+    def _grad_padded(self, ap):
         lat = self.lat
-        ap = self._pad(a)
-        out = np.zeros((lat.D,) + self.shape, dtype=a.dtype)
+        out = np.zeros((lat.D,) + self.shape, dtype=ap.dtype)
         for i in range(1, lat.Q):
             nb = self._at(ap, lat.c[i])
             for d in range(lat.D):
@@ -121,10 +138,20 @@ class Model:
                     out[d] = out[d] + lat.w[i] * lat.c[i, d] * nb / self.cs2
         return out
 
-    def lap(self, a):
-        """Isotropic Laplacian, Eq. 40: sum_{i != 0} 2 w_i [a(x + c_i) - a(x)] / cs^2."""
+    def grad(self, a, wet=False):
+        """Isotropic gradient, Eq. 39: sum_{i != 0} w_i c_i a(x + c_i) / cs^2 (wet: a is phi,
+        with wetting ghosts behind walls)."""
+        return self._grad_padded(self._pad(a, wet))
+
+    def grad_psi(self, phi):
+        """Gradient (Eq. 39) of psi (Eq. 37), with psi of the wetting ghosts behind walls."""
+        return self._grad_padded(self.psi_of(self._pad(phi, wet=True)))
+
+    def lap(self, a, wet=False):
+        """Isotropic Laplacian, Eq. 40: sum_{i != 0} 2 w_i [a(x + c_i) - a(x)] / cs^2 (wet: a
+        is phi, with wetting ghosts behind walls)."""
         lat = self.lat
-        ap = self._pad(a)
+        ap = self._pad(a, wet)
         out = np.zeros(self.shape, dtype=a.dtype)
         for i in range(1, lat.Q):
             out = out + 2.0 * lat.w[i] * (self._at(ap, lat.c[i]) - a) / self.cs2
@@ -206,9 +233,9 @@ class Model:
         rho = self.rho_of(phi)
         psi = self.psi_of(phi)                                     # Eq. 37
         sech2 = 1.0 - np.tanh(2.0 * psi / p.W) ** 2                # factor in Eq. 32
-        gphi = self.grad(phi)                                      # Eq. 39
-        lphi = self.lap(phi)                                       # Eq. 40
-        gpsi = self.grad(psi)
+        gphi = self.grad(phi, wet=True)                            # Eq. 39
+        lphi = self.lap(phi, wet=True)                             # Eq. 40
+        gpsi = self.grad_psi(phi)
         mu = 4.0 * self.beta * phi * (phi - 1.0) * (phi - 0.5) - self.kappa * lphi   # Eq. 2
         Fs = mu * gphi                                             # F_s = mu grad phi (Sect. 2)
         grho = (p.rho_heavy - p.rho_light) * gphi
@@ -346,7 +373,7 @@ class Model:
             u0 = np.zeros((lat.D,) + self.shape, dtype=self.dtype)
         else:
             u0 = np.asarray(u0).reshape((lat.D,) + self.shape).astype(self.dtype)
-        mu0 = 4.0 * self.beta * phi0 * (phi0 - 1.0) * (phi0 - 0.5) - self.kappa * self.lap(phi0)
+        mu0 = 4.0 * self.beta * phi0 * (phi0 - 1.0) * (phi0 - 0.5) - self.kappa * self.lap(phi0, wet=True)
         self.g = self.g_equilibrium(phi0, mu0, u0)
         if p.mode == "coupled":
             self.f = self.f_equilibrium(np.zeros_like(phi0), self.rho_of(phi0), u0)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -134,6 +135,12 @@ int validate(const vclb_params* p) {
         if (p->bc[a][sd] == VCLB_WALL && d == a && p->wall_u[a][sd][d] != 0.0)
           return fail(VCLB_EINVAL, "a wall's velocity must be tangential (zero normal component)");
       }
+  for (int a = 0; a < 3; ++a)
+    for (int sd = 0; sd < 2; ++sd) {
+      const double cw = p->wall_cos[a][sd];
+      if (!finite(cw) || cw < -1.0 || cw > 1.0) return fail(VCLB_EINVAL, "wall_cos must lie in [-1, 1]");
+      if (cw != 0.0 && p->bc[a][sd] != VCLB_WALL) return fail(VCLB_EINVAL, "wall_cos is for wall faces only");
+    }
   if (p->mode == VCLB_PRESCRIBED_VORTEX && !(finite(p->T) && p->T > 0 && finite(p->U0)))
     return fail(VCLB_EINVAL, "vortex needs T > 0 and a finite U0");
   for (int k = 0; k < p->nlabels; ++k)
@@ -303,6 +310,9 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
     np.wb[k] = R(L::cy[k] < 0 ? 2.0 * L::w[i] * cub * 3.0 : 0.0);
     np.wt[k] = R(L::cy[k] > 0 ? 2.0 * L::w[i] * cut * 3.0 : 0.0);
   }
+  // wetting ghosts behind the bottom / top wall: phi_g = phi_e + c phi_e (1 - phi_e)
+  np.wet_lo = R(4.0 / W * (wall_y(p) ? p.wall_cos[1][0] : 0.0));
+  np.wet_hi = R(4.0 / W * (wall_y(p) ? p.wall_cos[1][1] : 0.0));
   np.U0 = R(p.U0);
   np.mass_fix = p.mass_fix;
   np.T = p.T;
@@ -1060,7 +1070,14 @@ std::vector<Span> state_spans(const vclb_case* c, int par) {
   return v;
 }
 
-uint64_t params_hash(const vclb_params& p) { return fnv1a(&p, sizeof(p)); }
+// fingerprint of the parameter values: the bytes of the struct up to nlabels and from
+// wall_u on, skipping the alignment padding between them (whatever a caller left there)
+uint64_t params_hash(const vclb_params& p) {
+  const size_t head = offsetof(vclb_params, nlabels) + sizeof(p.nlabels);
+  const size_t tail = offsetof(vclb_params, wall_u);
+  static_assert(offsetof(vclb_params, wall_u) % alignof(double) == 0, "layout");
+  return fnv1a(reinterpret_cast<const char*>(&p) + tail, sizeof(p) - tail, fnv1a(&p, head));
+}
 }  // namespace
 
 extern "C" {
@@ -2029,6 +2046,8 @@ int adj_check_case(const vclb_case* c) {
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
   if (visc_ratio(c->p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
   if (c->p.mass_fix > 0) return fail(VCLB_EINVAL, "the adjoint covers cases without the global volume correction");
+  for (int sd = 0; sd < 2; ++sd)
+    if (c->p.wall_cos[1][sd] != 0.0) return fail(VCLB_EINVAL, "the adjoint covers neutral walls (wall_cos = 0)");
   return VCLB_OK;
 }
 

@@ -107,6 +107,14 @@ __device__ __forceinline__ void pull(const Case& c, const typename St::S* __rest
   }
 }
 
+// phi of a stencil ghost row behind a wall, from the edge row's phi_e: the one-sided
+// difference across the half-way wall equals the wetting flux (4 / W) cos(theta)
+// phi_e (1 - phi_e), c = (4 / W) cos(theta); c = 0 gives the mirror phi_e itself
+template <class R>
+__device__ __forceinline__ R wet_ghost(R phi_e, R c) {
+  return phi_e + c * (phi_e * (R(1) - phi_e));
+}
+
 // phi = sum_i g_i (Eq. 35) of a pulled g set.  For shifted storage g_i = d_i + r_i phi_s
 // (phi_s: the phi the stored deviations refer to), and on return v holds
 // e_i = g_i - r_i phi = d_i + r_i (phi_s - phi): the deviation from this node's own rest

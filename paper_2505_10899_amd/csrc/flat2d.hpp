@@ -5,8 +5,8 @@
 // lane busy (a 200-wide case leaves no partial wave at the end of each row) and
 // successive rows run back to back.  Virtual index v = (y + 1) P + (x + 1), P = nx + 2,
 // covers x in [-1, nx] and y in [-1, ny]; ghost columns hold the periodic neighbour
-// column, ghost rows the periodic neighbour row or, behind a wall, the edge row itself
-// (mirrored stencil ghosts).  Every stencil neighbour of v is then v + cx + P cy.
+// column, ghost rows the periodic neighbour row or, behind a wall, the wetting ghost of
+// the edge row (the edge row itself for a neutral wall).  Every stencil neighbour of v is then v + cx + P cy.
 //
 // The band's window (padded rows y0 - 1 .. y1) is cut into chunks of B consecutive
 // virtual nodes, one per lane.  Iteration i pulls the populations of chunk i, forms
@@ -157,7 +157,9 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
         else if (yr >= ny) yr = wall ? ny - 1 : 0;
         R ps[Q];
         pull9_flat<St>(gsrc, phis, xr, yr, nx, ny, n, wall, e[SF], ps);
-        const R ph = phi_of_pulled<L, St>(e[SF], ps, c.np.rest);
+        R ph = phi_of_pulled<L, St>(e[SF], ps, c.np.rest);
+        if (wall && qf < 1) ph = wet_ghost<R>(ph, c.np.wet_lo);         // ghost row y = -1
+        else if (wall && qf > ny) ph = wet_ghost<R>(ph, c.np.wet_hi);   // ghost row y = ny
         sring[vf & mask] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
       }
       rf += dr;

@@ -26,13 +26,15 @@ __global__ void __launch_bounds__(256) k_init(DevCase<L, St> c, const double* __
   const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
   if (n >= c.n) return;
   const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
-  // Laplacian of phi0 (Eq. 40), mirror ghosts at walls
+  // Laplacian of phi0 (Eq. 40), wetting ghosts behind walls
   R nb[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     int xn = wrapi(x + L::cx[i], c.nx), yn = y + L::cy[i], zn = wrapi(z + L::cz[i], c.nz);
+    const int side = c.wall ? (yn < 0 ? -1 : (yn >= c.ny ? 1 : 0)) : 0;
     yn = c.wall ? (yn < 0 ? 0 : (yn >= c.ny ? c.ny - 1 : yn)) : wrapi(yn, c.ny);
     nb[i] = R(phi0[xn + long(c.nx) * (yn + long(c.ny) * zn)]);
+    if (side) nb[i] = wet_ghost<R>(nb[i], side < 0 ? c.np.wet_lo : c.np.wet_hi);
   }
   const R phi = nb[0];
   const R lphi = stencil_lap<L, R>(nb);
@@ -218,15 +220,25 @@ static void launch_mass(const DevCase<L, St>& c, int set_ref, hipStream_t s) {
   hipLaunchKernelGGL((k_mass_fold<L, St>), dim3(1), dim3(256), 0, s, c, int(nb), set_ref);
 }
 
-// gather a scratch field at x + c_i with periodic wrap / wall mirror
+// gather phi and psi of the scratch fields at x + c_i with periodic wrap; behind a wall,
+// the wetting ghost of the edge row's phi and psi (Eq. 37) of that ghost
 template <class L, class St>
-__device__ __forceinline__ void gather(const DevCase<L, St>& c, const typename St::R* __restrict__ a, int x,
-                                       int y, int z, typename St::R (&nb)[L::Q]) {
+__device__ __forceinline__ void gather_phi_psi(const DevCase<L, St>& c, int x, int y, int z,
+                                               typename St::R (&nphi)[L::Q], typename St::R (&npsi)[L::Q]) {
+  using R = typename St::R;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     int xn = wrapi(x + L::cx[i], c.nx), yn = y + L::cy[i], zn = wrapi(z + L::cz[i], c.nz);
+    const int side = c.wall ? (yn < 0 ? -1 : (yn >= c.ny ? 1 : 0)) : 0;
     yn = c.wall ? (yn < 0 ? 0 : (yn >= c.ny ? c.ny - 1 : yn)) : wrapi(yn, c.ny);
-    nb[i] = a[xn + long(c.nx) * (yn + long(c.ny) * zn)];
+    const long m = xn + long(c.nx) * (yn + long(c.ny) * zn);
+    if (side) {
+      nphi[i] = wet_ghost<R>(c.tmp_phi[m], side < 0 ? c.np.wet_lo : c.np.wet_hi);
+      npsi[i] = psi_of<R>(nphi[i], c.np.W4, c.np.xi);
+    } else {
+      nphi[i] = c.tmp_phi[m];
+      npsi[i] = c.tmp_psi[m];
+    }
   }
 }
 
@@ -242,8 +254,7 @@ __global__ void __launch_bounds__(256) k_collide_plain(DevCase<L, St> c, int red
   if (n < c.n) {
     const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
     NodeIn<L, R> in;
-    gather<L, St>(c, c.tmp_phi, x, y, z, in.nphi);
-    gather<L, St>(c, c.tmp_psi, x, y, z, in.npsi);
+    gather_phi_psi<L, St>(c, x, y, z, in.nphi, in.npsi);
     prescribed<L, St, COUPLED>(c, x, y, t, in);
     R g[L::Q], ps[L::Q], f[L::Q], J[L::D];
     pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, ps);
@@ -275,8 +286,7 @@ __global__ void __launch_bounds__(256) k_fields(DevCase<L, St> c, unsigned mask,
   const int par = int(t & 1);
   const int x = int(n % c.nx), y = int((n / c.nx) % c.ny), z = int(n / (long(c.nx) * c.ny));
   NodeIn<L, R> in;
-  gather<L, St>(c, c.tmp_phi, x, y, z, in.nphi);
-  gather<L, St>(c, c.tmp_psi, x, y, z, in.npsi);
+  gather_phi_psi<L, St>(c, x, y, z, in.nphi, in.npsi);
   prescribed<L, St, COUPLED>(c, x, y, t, in);
   R g[L::Q], ps[L::Q], f[L::Q], J[L::D];
   pull<L, St>(c, c.pop[0][par], c.phis[par], x, y, z, g, ps);

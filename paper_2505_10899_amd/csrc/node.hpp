@@ -165,6 +165,8 @@ struct NodeParams {
   R rest[L::Q];  // FP16S rest-equilibrium coefficients r_i
   R sgr[L::Q];   // s_k^g (unscaled)
   R sfr[L::Q];   // s_k^f (unscaled)
+  R wet_lo;      // (4 / W) cos(theta) of the bottom wall (0: mirror ghosts)
+  R wet_hi;      // same for the top wall
   R U0;          // vortex amplitude
   double T;      // vortex period (steps)
   double mass_fix;   // rate of the global volume correction (0: off)

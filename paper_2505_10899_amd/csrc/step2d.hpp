@@ -111,16 +111,22 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
     return o;
   };
   auto slot = [](int r) -> int { return (r + 4) & 3; };
+  // the ring holds, for a ghost row behind a wall, the wetting ghost of the edge row
+  auto ghost = [&](int r, R ph) -> R {
+    if (wall && r < 0) return wet_ghost<R>(ph, c.np.wet_lo);
+    if (wall && r >= ny) return wet_ghost<R>(ph, c.np.wet_hi);
+    return ph;
+  };
   auto phi_row = [&](int r, R (&g)[Q]) {
     const Row3 rw = row3(r);
     R ps[Q];
     pull9<St, IX, NT>(gsrc, phis, col, rw, g, ps);
-    const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
+    const R ph = ghost(r, phi_of_pulled<L, St>(g, ps, c.np.rest));
     sring[slot(r) * W + lane + 1] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
     if (halo_lane) {
       R gh[Q], hps[Q];
       pull9<St, IX, NT>(gsrc, phis, hcol, rw, gh, hps);
-      const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
+      const R hp = ghost(r, phi_of_pulled<L, St>(gh, hps, c.np.rest));
       sring[slot(r) * W + hidx] = PhiPsi{hp, psi_of<R>(hp, c.np.W4, c.np.xi)};
     }
   };

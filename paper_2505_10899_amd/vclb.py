@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("bc", (ctypes.c_int32 * 2) * 3), ("nlabels", ctypes.c_int32),
         ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
+        ("wall_cos", (ctypes.c_double * 2) * 3),
         ("W", ctypes.c_double), ("sigma", ctypes.c_double), ("mobility", ctypes.c_double),
         ("lam", ctypes.c_double), ("mass_fix", ctypes.c_double), ("xi", ctypes.c_double),
         ("eps_n", ctypes.c_double),
@@ -169,6 +170,8 @@ def to_cparams(p) -> Params:
     for a in range(3):
         c.wall_u[1][0][a] = float(p.wall_u_bottom[a])
         c.wall_u[1][1][a] = float(p.wall_u_top[a])
+    c.wall_cos[1][0] = float(getattr(p, "wall_cos_bottom", 0.0))
+    c.wall_cos[1][1] = float(getattr(p, "wall_cos_top", 0.0))
     c.W, c.sigma, c.mobility = float(p.W), float(p.sigma), float(p.mobility)
     c.lam, c.xi, c.eps_n = float(p.lam), float(p.xi), float(p.eps_n)
     c.mass_fix = float(getattr(p, "mass_fix", 0.0))

@@ -250,6 +250,26 @@ def test_boundary_faces_validated_per_axis():
     assert _rc_validate(_raw(q, lambda c: (c.bc[1].__setitem__(0, WALL), c.bc[1].__setitem__(1, WALL)))) == v.VCLB_EINVAL
 
 
+def test_wetting_validation():
+    v = _vclb()
+    WALL = v.WALL
+    p = _valid()
+
+    def ywalls(c, cb=0.0, ct=0.0):
+        c.bc[1][0] = c.bc[1][1] = WALL
+        c.wall_cos[1][0], c.wall_cos[1][1] = cb, ct
+    assert _rc_validate(_raw(p, lambda c: ywalls(c, 0.5, -1.0))) == v.VCLB_OK
+    bad = {
+        "cos above 1": lambda c: ywalls(c, 1.0000001, 0.0),
+        "cos below -1": lambda c: ywalls(c, 0.0, -1.5),
+        "non-finite cos": lambda c: ywalls(c, float("nan"), 0.0),
+        "cos on a periodic face": lambda c: c.wall_cos[1].__setitem__(0, 0.5),
+        "cos on x": lambda c: (ywalls(c), c.wall_cos[0].__setitem__(1, 0.2)),
+    }
+    for name, edit in bad.items():
+        assert _rc_validate(_raw(p, edit)) == v.VCLB_EINVAL, name
+
+
 def test_viscosity_ratio_validation():
     v = _vclb()
     p = _valid().replace(nu=0.3, nu_light=0.05)

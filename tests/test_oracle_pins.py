@@ -473,6 +473,73 @@ def test_paper_claim_small_drop_keeps_volume_better():
     assert res[0.5] < res[0.0]
 
 
+def _contact_angle(phi, y_wall=-0.5, y_min=3):
+    """Contact angle (degrees, inside phi >= 1/2) of a sessile drop on the bottom wall: a
+    least-squares circle through the phi = 1/2 crossings at least y_min rows above the
+    wall, meeting the wall line y = y_wall: cos(theta) = (y_wall - y_centre) / R."""
+    f = phi[0]
+    ny, nx = f.shape
+    pts = []
+    for x in range(nx):
+        for y in range(ny - 1):
+            a, b = f[y, x] - 0.5, f[y + 1, x] - 0.5
+            if a * b < 0:
+                pts.append((x, y + a / (a - b)))
+    for y in range(ny):
+        for x in range(nx - 1):
+            a, b = f[y, x] - 0.5, f[y, x + 1] - 0.5
+            if a * b < 0:
+                pts.append((x + a / (a - b), y))
+    P = np.array([q for q in pts if q[1] >= y_min])
+    A = np.column_stack([P[:, 0], P[:, 1], np.ones(len(P))])
+    c = np.linalg.lstsq(A, P[:, 0] ** 2 + P[:, 1] ** 2, rcond=None)[0]
+    xc, yc = c[0] / 2, c[1] / 2
+    R = np.sqrt(c[2] + xc * xc + yc * yc)
+    return float(np.degrees(np.arccos(np.clip((y_wall - yc) / R, -1.0, 1.0))))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cos_theta", [0.5, -0.5])
+def test_sessile_drop_takes_the_wall_contact_angle(cos_theta):
+    """Young's law for the wetting ghosts behind a wall: a half-disk drop (90 degrees) on
+    the bottom wall of a 64 x 32 channel relaxes to the circular cap meeting the wall at
+    the prescribed angle (60 or 120 degrees, measured in the heavy phase), within 1.5
+    degrees after 8000 steps; the total of phi is conserved.  A sign slip in the ghost
+    would give the supplementary angle, a wrong factor another angle."""
+    nx, ny, R0 = 64, 32, 11.0
+    xc = nx / 2 + 0.3
+    p = W.CaseParams(nx=nx, ny=ny, wall_y=True, wall_cos_bottom=cos_theta, wall_cos_top=cos_theta, W=4.0,
+                     sigma=0.01, mobility=0.1, nu=0.1, label_centres=[(xc, 0.0, 0.0)])
+    x = np.arange(nx)[None, None, :]
+    y = np.arange(ny)[None, :, None]
+    d = R0 - np.sqrt((x - xc) ** 2 + (y + 0.5) ** 2)
+    phi0 = 0.5 * (1.0 + np.tanh(2.0 * d / p.W)) * np.ones((1, ny, nx))
+    m = Model(p).init(phi0)
+    s0 = m.phi().sum()
+    assert abs(_contact_angle(m.phi()) - 90.0) < 1.0
+    m.step(8000)
+    theta = _contact_angle(m.phi())
+    target = float(np.degrees(np.arccos(cos_theta)))
+    assert abs(theta - target) < 1.5, (theta, target)
+    assert abs(m.phi().sum() - s0) < 1e-11 * s0
+
+
+def test_neutral_wetting_is_the_mirror():
+    """cos(theta) = 0 leaves the ghosts as mirrors of the edge rows (bit for bit the
+    default walls); a nonzero angle changes only the stencils at the wall rows."""
+    p, phi0, u0 = W.shear_droplet(nx=40, ny=16, R=5.0, U=0.02, Ca=0.2, Re=0.5)
+    a = Model(p).init(phi0, u0)
+    b = Model(p.replace(wall_cos_bottom=0.0, wall_cos_top=0.0)).init(phi0, u0)
+    a.step(20)
+    b.step(20)
+    assert np.array_equal(a.g, b.g) and np.array_equal(a.f, b.f)
+    w = Model(p.replace(wall_cos_bottom=0.7, wall_cos_top=-0.4))
+    phi = a.phi()
+    ap, wp = a._pad(phi, wet=True), w._pad(phi, wet=True)
+    assert np.array_equal(ap[:, 1:-1], wp[:, 1:-1])
+    assert not np.array_equal(ap[:, 0], wp[:, 0]) and not np.array_equal(ap[:, -1], wp[:, -1])
+
+
 def test_observables_on_known_field():
     p = W.CaseParams(nx=8, ny=6, label_centres=[(1.0, 2.0, 0.0), (6.0, 2.0, 0.0)])
     phi = np.zeros((1, 6, 8))

@@ -47,6 +47,8 @@ class CaseParams:
     wall_y: bool = False                       # bounce-back walls bounding y
     wall_u_bottom: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     wall_u_top: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    wall_cos_bottom: float = 0.0               # cos(contact angle) of the bottom wall, angle in the
+    wall_cos_top: float = 0.0                  # heavy phase (0: 90 degrees, mirror stencil ghosts)
     W: float = 4.0
     sigma: float = 0.01
     mobility: float = 0.1
