@@ -177,11 +177,25 @@ def _small_case(variant):
         p = W.CaseParams(nx=16, ny=12, nz=20, lattice="D3Q19", sigma=0.005, nu=0.05, rho_light=0.1,
                          s_g=tuple(sg), s_f=tuple(sf))
         return p, W.cylinder_phi(p, 7.5, 5.5, 4.0, 0.1, 20.0), None
+    if variant == "no_surface_tension":   # sigma = 0: no chemical potential, no force; drop in uniform flow
+        p = W.CaseParams(nx=48, ny=40, sigma=0.0, rho_light=0.3)
+        u0 = np.zeros((2, 1, 40, 48))
+        u0[0], u0[1] = 0.01, -0.005
+        return p, W.drops_phi(p, [(23.6, 19.3, 0, 8.0)]), u0
+    if variant == "tiny_2x3":             # every stencil neighbour wraps onto the case itself
+        p = W.CaseParams(nx=2, ny=3, rho_light=0.5)
+        return p, np.array([[[0.2, 0.7], [0.9, 0.4], [0.55, 0.1]]]), None
+    if variant == "d3q19_tiny":           # 3 x 2 x 4: wraps in every direction
+        p = W.CaseParams(nx=3, ny=2, nz=4, lattice="D3Q19", sigma=0.005, nu=0.05, rho_light=0.5)
+        z, y, x = np.meshgrid(np.arange(4), np.arange(2), np.arange(3), indexing="ij")
+        phi0 = (0.5 + 0.2 * np.sin(2 * np.pi * z / 4 + 0.3) + 0.1 * np.cos(2 * np.pi * x / 3 + 0.7)
+                + 0.05 * np.sin(np.pi * y + 0.2))
+        return p, phi0, None
     raise ValueError(variant)
 
 
 VARIANTS = ["periodic_ragged", "walls_moving", "vortex", "classical_lambda0", "mrt_rates", "narrow_tall", "d3q19",
-            "d3q19_rates"]
+            "d3q19_rates", "no_surface_tension", "tiny_2x3", "d3q19_tiny"]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
