@@ -236,3 +236,37 @@ def test_full_shear_case_against_central_differences():
     scale = max(abs(r[1]) for r in rows)
     for adj, fd, sp in rows:
         assert abs(adj - fd) <= 2 * sp + 1e-6 * scale
+
+
+def test_full_shear_case_against_oracle_complex_step():
+    """The 512x256 shear case over 4000 steps with a checkpoint every 200: dD/dsigma, dD/dM
+    and dD/dphi0 along the 10 PCG64(1) directions against the oracle's complex step at the
+    same size and length (stored by tests/golden/make_adjoint_golden.py, the same normal
+    cut), to 1e-6 relative; directions relative to the largest of the ten.  The forward D
+    agrees to 1e-9."""
+    import os
+    v = _vclb()
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "shear512x256_adjoint_t4000.npz"))
+    p, phi0, u0 = W.shear_droplet("fp64")
+    n, every = int(g["nsteps"]), 200
+    assert abs(float(g["normal_tau"]) - v.NORMAL_TAU) < 1e-15
+    print(f"[adjoint] case shear512x256 steps {n} every {every} against the stored complex step", flush=True)
+    c = v.Case(p)
+    c.set_reduce_every(0)
+    c.adjoint_record(phi0, u0, nsteps=n, every=every)
+    D = float(c.derived()[0, 4])
+    print(f"[adjoint] C4 D gpu {D:.15e} oracle {float(g['D']):.15e}", flush=True)
+    assert abs(D - float(g["D"])) <= 1e-9 * abs(float(g["D"]))
+    dphi, ds, dm = _grad(c, np.array([[0.0, 0.0, 0.0, 0.0, 1.0]]))
+    for name, got, ref in (("sigma", ds, float(g["dD_dsigma"])), ("M", dm, float(g["dD_dM"]))):
+        print(f"[adjoint] C4 dD/d{name}: gpu {got:.12e} cs {ref:.12e} rel {abs(got - ref) / abs(ref):.1e}", flush=True)
+        assert _close(got, ref, 0.0), (name, got, ref)
+    rng = np.random.Generator(np.random.PCG64(1))
+    refs = np.asarray(g["dD_dphi0_dir"])
+    scale = float(np.max(np.abs(refs)))
+    for k in range(len(refs)):
+        d = rng.standard_normal(phi0.shape) * 4.0 * phi0 * (1.0 - phi0)
+        got = float(dphi @ d.reshape(-1))
+        print(f"[adjoint] C4 direction {k}: gpu {got:.12e} cs {refs[k]:.12e} "
+              f"rel to largest {abs(got - refs[k]) / scale:.1e}", flush=True)
+        assert _close(got, float(refs[k]), scale), (k, got, refs[k])
