@@ -73,8 +73,9 @@ __device__ __forceinline__ void stg_nt(T* p, unsigned i, T v) {
 
 // ---------------------------------------------------------------- storage codecs
 // load / store: plain accesses; load_nt / store_nt: with the non-temporal hint
-// fold: the storage rounds coarsely enough that the writer phi stored beside a node's g
-// absorbs the sum of their rounding errors (rounding(v): stored value minus v)
+// fold: the storage rounds coarsely enough that the phis entry a node writes for itself
+// absorbs the sum of the rounding errors of the deviations it wrote (rounding(v): stored
+// value minus v)
 struct StoreF64 {
   using S = double;
   using R = double;
