@@ -164,7 +164,13 @@ typedef struct vclb_case vclb_case;
 const char* vclb_strerror(int code);
 /* Message of the calling thread's last failed call (empty string if none). */
 const char* vclb_last_error(void);
-/* Library version as MAJOR * 10000 + MINOR * 100 + PATCH. */
+/* Version of this header as MAJOR * 10000 + MINOR * 100 + PATCH.  The major part changes
+   with the layout of vclb_params or of any other struct here; a library built from this
+   header returns the same value from vclb_version, and a caller should refuse a library
+   whose major part differs. */
+#define VCLB_VERSION 20000
+/* Version of the library as MAJOR * 10000 + MINOR * 100 + PATCH (VCLB_VERSION of the
+   header it was built from). */
 int vclb_version(void);
 
 /* Achievable HBM bandwidth on this device: the practical ceiling that the step kernels'

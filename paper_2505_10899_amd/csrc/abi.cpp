@@ -444,7 +444,7 @@ const char* vclb_strerror(int code) {
 
 const char* vclb_last_error(void) { return g_last_error.c_str(); }
 
-int vclb_version(void) { return 10000; }
+int vclb_version(void) { return VCLB_VERSION; }
 
 int vclb_bandwidth_probe(int32_t mode, void* dst, const void* src, size_t bytes, int32_t reps, int32_t blocks,
                          double* gbs, void* stream) {

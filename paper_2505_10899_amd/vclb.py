@@ -132,6 +132,9 @@ SEED_FIELDS = 10
 NORMAL_TAU = 0.3   # the unit normal is differentiated where |grad psi| >= NORMAL_TAU
 
 
+VERSION = 20000   # VCLB_VERSION of include/vclb.h, whose struct layouts Params and Obs mirror
+
+
 def lib():
     """Load libvclb.so (raises if it has not been built)."""
     global _lib
@@ -143,6 +146,9 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.vclb_version() // 10000 != VERSION // 10000:
+            raise ImportError(f"{LIB_PATH} has version {L.vclb_version()}, this binding needs {VERSION} (its "
+                              "parameter layout): rebuild it with `python -m paper_2505_10899_amd.build`")
         _lib = L
     return _lib
 

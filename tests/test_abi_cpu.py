@@ -38,7 +38,10 @@ def test_strerror_and_version():
     L = v.lib()
     assert L.vclb_strerror(-1) == b"invalid argument"
     assert L.vclb_strerror(-4) == b"non-finite phi"
-    assert L.vclb_version() >= 10000
+    assert L.vclb_version() == v.VERSION
+    # the header's version, which the binding's struct layouts follow
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vclb.h")).read()
+    assert f"#define VCLB_VERSION {v.VERSION}" in hdr
 
 
 def _valid():
