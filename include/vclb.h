@@ -92,8 +92,8 @@ typedef struct {
   int32_t nx, ny, nz;       /* nodes per axis; nz = 1 for D2Q9                             */
   int32_t bc[3][2];         /* boundary type of each face: VCLB_PERIODIC | VCLB_WALL.  Both
                                faces of an axis must have the same type.  Supported: walls
-                               on the y faces of D2Q9 (ny >= 2); every other face periodic
-                               (VCLB_EINVAL otherwise).                                    */
+                               on the y faces (ny >= 2, D2Q9 and D3Q19); every other face
+                               periodic (VCLB_EINVAL otherwise).                           */
   int32_t nlabels;          /* 0: one label covering the domain; else 1..VCLB_MAX_LABELS   */
   double  wall_u[3][2][3];  /* velocity of the wall on each VCLB_WALL face (ignored on
                                periodic faces); its normal component must be 0            */

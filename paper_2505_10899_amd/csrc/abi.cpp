@@ -91,7 +91,6 @@ int validate(const vclb_params* p) {
   }
   if (p->bc[0][0] == VCLB_WALL) return fail(VCLB_EINVAL, "walls on the x faces are not supported (x is periodic)");
   if (p->bc[2][0] == VCLB_WALL) return fail(VCLB_EINVAL, "walls on the z faces are not supported (z is periodic)");
-  if (p->bc[1][0] == VCLB_WALL && p->lattice != VCLB_D2Q9) return fail(VCLB_EINVAL, "walls are D2Q9-only");
   if (p->bc[1][0] == VCLB_WALL && p->ny < 2) return fail(VCLB_EINVAL, "walls need ny >= 2");
   if (p->nlabels < 0 || p->nlabels > VCLB_MAX_LABELS) return fail(VCLB_EINVAL, "nlabels out of range");
   if (!(finite(p->W) && p->W > 0)) return fail(VCLB_EINVAL, "W must be > 0");

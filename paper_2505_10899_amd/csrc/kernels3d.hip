@@ -1,4 +1,5 @@
-// Fused D3Q19 step for gfx950 (3D workloads, periodic on every axis).
+// Fused D3Q19 step for gfx950 (3D workloads: x and z periodic, y periodic or bounded by
+// half-way walls).
 //
 // A workgroup of bx * by threads owns a bx x by column tile of the (x, y) plane and
 // marches over tz planes of z.  For each plane it pulls the next plane's g, forms
@@ -15,16 +16,21 @@
 
 namespace vclb {
 
-// Node offsets of one 3D pull (periodic on every axis): the writer of direction i sits
-// at x - c_i, reached from the node's own index s0 by one of xm / xp, ym / yp, zm / zp
-// per axis (the wrapped steps to x - 1 / x + 1 and so on).
+// Node offsets of one 3D pull: the writer of direction i sits at x - c_i, reached from
+// the node's own index s0 by one of xm / xp, ym / yp, zm / zp per axis (the wrapped steps
+// to x - 1 / x + 1 and so on; x and z are periodic).  With walls bounding y, lo / hi mark
+// the first / last row, where the directions coming from behind the wall are the node's
+// own opposite populations (half-way bounce-back).
 struct Nbr3 {
   int s0, xm, xp, ym, yp, zm, zp;
+  bool lo, hi;
 };
 
-__device__ __forceinline__ Nbr3 nbr3(int x, int y, int z, int nx, int ny, int nz, int nxy) {
+__device__ __forceinline__ Nbr3 nbr3(int x, int y, int z, int nx, int ny, int nz, int nxy, bool wall) {
   Nbr3 o;
   o.s0 = x + nx * y + nxy * z;
+  o.lo = wall && y == 0;
+  o.hi = wall && y == ny - 1;
   o.xm = x == 0 ? nx - 1 : -1;
   o.xp = x == nx - 1 ? 1 - nx : 1;
   o.ym = y == 0 ? (ny - 1) * nx : -nx;
@@ -60,7 +66,21 @@ __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, c
   using R = typename St::R;
   static_for<0, L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    out[i] = St::load(src + i * n, IX(pull_index<i>(o)));
+    int s = pull_index<i>(o);
+    const typename St::S* base = src + i * n;
+    if constexpr (L::cy[i] > 0) {   // from the row below: behind the bottom wall at y = 0
+      if (o.lo) {
+        s = o.s0;
+        base = src + L::opp[i] * n;
+      }
+    }
+    if constexpr (L::cy[i] < 0) {   // from the row above: behind the top wall at y = ny - 1
+      if (o.hi) {
+        s = o.s0;
+        base = src + L::opp[i] * n;
+      }
+    }
+    out[i] = St::load(base, IX(s));
   });
   if constexpr (St::shifted) {   // every deviation refers to this node's own phis entry
     if (ps) {
@@ -127,16 +147,28 @@ __device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const
   NodeOut<L, R> out;
   node_update_mom_s<L, R, true, St::shifted, UNIT, VISC>(c.np, st, gcur, f, J, out);
   const int dst = par ^ 1;
+  const bool wall = c.wall != 0;
   R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     R d = gcur[i];
     if constexpr (St::shifted) {   // relative to the reader's phi, read back from the ring
       const int sr = ring_slot3d(z + L::cz[i]) * PS + (ty + 1 + L::cy[i]) * PW + tx + 1 + L::cx[i];
-      d = encode_dev(gcur[i], c.np.rest[i], st.phi, sring[sr].phi);
+      d = encode_dev(gcur[i], c.np.rest[i], st.phi,
+                     leaves_through_wall<L>(i, yw, c.ny, wall) ? st.phi : sring[sr].phi);
     }
     St::store(c.pop[0][dst] + i * c.n, IX(nn), d);
     if constexpr (St::fold) res += St::rounding(d);
+  }
+  if (wall && yw == 0) {   // moving-wall term of the populations the bottom wall returns
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (L::cy[i] < 0) f[i] += c.np.wb[i] * out.rho;
+  }
+  if (wall && yw == c.ny - 1) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (L::cy[i] > 0) f[i] += c.np.wt[i] * out.rho;
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, IX(nn), f[i]);
@@ -231,7 +263,11 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
   const int z0 = int(long(bz) * c.nz / nbz), z1 = int(long(bz + 1) * c.nz / nbz);
   const int xg = x0 + tx, yg = y0 + ty;
   const bool active = xg < c.nx && yg < c.ny;
-  const int xw = xg % c.nx, yw = yg % c.ny;
+  const bool wall = c.wall != 0;
+  // a lane past the last row pulls the last row (walls: the ring holds its wetting ghost
+  // there) or the periodic image
+  const int xw = xg % c.nx, yw = wall ? min(yg, c.ny - 1) : yg % c.ny;
+  const int yside = wall && yg >= c.ny ? 1 : 0;
   const long t = c.t;
   const int par = int(t & 1);
   const typename St::S* gsrc = c.pop[0][par];
@@ -244,8 +280,9 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     const int zr = wrapi(z, c.nz);
     const int s = ring_slot3d(z) * PS;
     R ps[Q];
-    pull19<St, IX>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy), g, ps);
-    const R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
+    pull19<St, IX>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy, wall), g, ps);
+    R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
+    if (yside) ph = wet_ghost<R>(ph, c.np.wet_hi);   // a lane past a wall holds the ghost row
     sring[s + (ty + 1) * PW + tx + 1] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
     // halo cells spread evenly over the waves (thread hstep * k takes cell k), so that no
     // wave carries a second full pull while the others wait at the barrier
@@ -257,10 +294,14 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
       else if (k < 2 * PW + BY) { px = 0; py = 1 + k - 2 * PW; }
       else { px = PW - 1; py = 1 + k - 2 * PW - BY; }
       const int hx = ((x0 - 1 + px) % nx + nx) % nx;
-      const int hy = ((y0 - 1 + py) % ny + ny) % ny;
+      // rows behind a wall: the edge row's wetting ghost (its mirror for a neutral wall)
+      const int hyr = y0 - 1 + py;
+      const int hside = wall ? (hyr < 0 ? -1 : (hyr >= ny ? 1 : 0)) : 0;
+      const int hy = wall ? (hyr < 0 ? 0 : (hyr >= ny ? ny - 1 : hyr)) : ((hyr % ny) + ny) % ny;
       R gh[Q], hps[Q];
-      pull19<St, IX>(gsrc, phis, c.n, nbr3(hx, hy, zr, nx, ny, nz, nxy), gh, hps);
-      const R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
+      pull19<St, IX>(gsrc, phis, c.n, nbr3(hx, hy, zr, nx, ny, nz, nxy, wall), gh, hps);
+      R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
+      if (hside) hp = wet_ghost<R>(hp, hside < 0 ? c.np.wet_lo : c.np.wet_hi);
       sring[s + py * PW + px] = PhiPsi{hp, psi_of<R>(hp, c.np.W4, c.np.xi)};
     }
   };
@@ -299,7 +340,7 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
   for (int z = z0; z < z1; ++z) {
     // this plane's f and previous phi u are requested together with the next plane's
     // g, so that one memory round trip per plane covers both
-    const Nbr3 o = nbr3(xw, yw, z, nx, ny, nz, nxy);
+    const Nbr3 o = nbr3(xw, yw, z, nx, ny, nz, nxy, wall);
     const int nn = o.s0;
     R f[Q], J[L::D];
     if (active) {

@@ -61,7 +61,7 @@ def test_valid_params_pass():
     dict(rho_light=0.0), dict(rho_heavy=float("inf")), dict(xi=0.0), dict(lam=-0.5),
     dict(nx=0), dict(nz=2), dict(s_g=(0, 0, 0, 2.5)), dict(s_f=(0, 0, 0, 0, 0, 0, 0, -0.1)),
     dict(s_g=tuple([0.0] * 9 + [1.0])),          # rate for a moment D2Q9 does not have
-    dict(mode="vortex", T=0.0), dict(lattice="D3Q19", wall_y=True, nz=4),
+    dict(mode="vortex", T=0.0),
     dict(lattice="D3Q19", mode="vortex", nz=4), dict(wall_y=True, ny=1),
     dict(label_centres=[(0, 0, 0)] * 3),
     dict(nx=65536, ny=32768),                    # 2^31 nodes: one more than the largest case
@@ -247,10 +247,12 @@ def test_boundary_faces_validated_per_axis():
     }
     for name, edit in bad.items():
         assert _rc_validate(_raw(p, edit)) == v.VCLB_EINVAL, name
-    # D3Q19 supports no walls at all
+    # D3Q19: walls on the y faces, not on x or z
     q = W.rayleigh_plateau()[0]
     assert _rc_validate(_raw(q, lambda c: None)) == v.VCLB_OK
-    assert _rc_validate(_raw(q, lambda c: (c.bc[1].__setitem__(0, WALL), c.bc[1].__setitem__(1, WALL)))) == v.VCLB_EINVAL
+    assert _rc_validate(_raw(q, lambda c: (c.bc[1].__setitem__(0, WALL), c.bc[1].__setitem__(1, WALL)))) == v.VCLB_OK
+    assert _rc_validate(_raw(q, lambda c: (c.bc[2].__setitem__(0, WALL), c.bc[2].__setitem__(1, WALL)))) == v.VCLB_EINVAL
+    assert _rc_validate(_raw(q, lambda c: (c.bc[0].__setitem__(0, WALL), c.bc[0].__setitem__(1, WALL)))) == v.VCLB_EINVAL
 
 
 def test_wetting_validation():

@@ -259,3 +259,39 @@ def test_planted_rate_row_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(om, "default_rates", swap("g", 7, 16))
     rate, _, _ = _phase_mode((32, 4, 32), (0, 0, 1))
     assert abs(rate - 1) > 0.05
+
+
+# --------------------------------------------------------------------------- walls bounding y
+@pytest.mark.parametrize("srt", [True, False], ids=["srt", "mrt"])
+def test_d3q19_couette_between_moving_walls(srt):
+    """Walls at y = -1/2 and ny - 1/2 moving -U and +U along x (half-way bounce-back with
+    the moving-wall term): the steady flow is the linear Couette profile, exactly for a
+    single relaxation time (every rate of f at 1 / tau_f) and to the lattice's
+    second-order accuracy with the default multiple rates."""
+    ny, U = 16, 0.01
+    p = _case(3, ny, 3, wall_y=True, wall_u_bottom=(-U, 0, 0), wall_u_top=(U, 0, 0), nu=0.5, rho_light=1.0)
+    if srt:
+        tf = 0.5 + 3 * p.nu
+        p = p.replace(s_f=tuple([1 / tf] * 19))
+    m = Model(p).init(np.zeros((3, ny, 3)))
+    m.step(3000)
+    u = m.fields()["u"]
+    y = np.arange(ny)
+    exact = -U + 2 * U * (y + 0.5) / ny
+    err = np.max(np.abs(u[0] - exact[None, :, None])) / U
+    assert err < (1e-9 if srt else 2e-2)
+    assert np.max(np.abs(u[1])) < 1e-12 * U and np.max(np.abs(u[2])) < 1e-12 * U
+
+
+def test_d3q19_walls_conserve_phi_and_mirror_a_drop():
+    """A drop midway between walls at rest: the total of phi is conserved to round-off
+    (bounce-back returns every population), and the field stays mirror symmetric about
+    the channel's mid-plane."""
+    p = _case(16, 14, 12, wall_y=True, sigma=0.005, nu=0.05, rho_light=0.2)
+    phi0 = W.drops_phi(p, [(7.5, 6.5, 5.5, 4.0)])
+    m = Model(p).init(phi0)
+    s0 = m.phi().sum()
+    m.step(200)
+    phi = m.phi()
+    assert abs(phi.sum() - s0) < 2e-13 * s0
+    assert np.max(np.abs(phi - phi[:, ::-1, :])) < 1e-12
