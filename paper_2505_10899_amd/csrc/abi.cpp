@@ -165,12 +165,14 @@ Layout layout_for(const vclb_params& p) {
     off = align_up(off + bytes);
     return o;
   };
+  // planes of the populations and of J hold ns entries, so that each starts on a cache line
+  const size_t ns = size_t(vclb::plane_stride(long(n)));
   for (int s = 0; s < 2; ++s)
     for (int b = 0; b < 2; ++b) {
       const bool need = s == 0 || p.mode == VCLB_COUPLED;
-      L.pop[s][b] = need ? take(size_t(Q) * n * sb) : SIZE_MAX;
+      L.pop[s][b] = need ? take(size_t(Q) * ns * sb) : SIZE_MAX;
     }
-  L.J = take(size_t(D) * n * rb);
+  L.J = take(size_t(D) * ns * rb);
   for (int b = 0; b < 2; ++b) L.phis[b] = p.storage != VCLB_FP64 ? take(n * 4) : SIZE_MAX;
   // every launch shape uses at least 64 nodes per workgroup, plus one partial row per
   // (y, z) line for tiles that are ragged in x
@@ -235,6 +237,7 @@ vclb::DevCase<L, St> make_dev(const vclb_case& c) {
   d.ny = p.ny;
   d.nz = p.nz;
   d.n = long(p.nx) * p.ny * p.nz;
+  d.ns = vclb::plane_stride(d.n);
   d.wall = wall_y(p);
   d.visc = visc_ratio(p) ? 1 : 0;
   d.nl = std::max(1, p.nlabels);
@@ -1063,11 +1066,12 @@ struct Span { size_t off, bytes; };
 
 std::vector<Span> state_spans(const vclb_case* c, int par) {
   const size_t n = size_t(c->p.nx) * c->p.ny * c->p.nz;
+  const size_t ns = size_t(vclb::plane_stride(long(n)));   // entries per population and J plane
   const int Q = lattice_q(c->p.lattice), D = lattice_d(c->p.lattice);
   std::vector<Span> v;
-  v.push_back({c->lay.pop[0][par], size_t(Q) * n * storage_bytes(c->p.storage)});
-  if (c->p.mode == VCLB_COUPLED) v.push_back({c->lay.pop[1][par], size_t(Q) * n * storage_bytes(c->p.storage)});
-  v.push_back({c->lay.J, size_t(D) * n * arith_bytes(c->p.storage)});
+  v.push_back({c->lay.pop[0][par], size_t(Q) * ns * storage_bytes(c->p.storage)});
+  if (c->p.mode == VCLB_COUPLED) v.push_back({c->lay.pop[1][par], size_t(Q) * ns * storage_bytes(c->p.storage)});
+  v.push_back({c->lay.J, size_t(D) * ns * arith_bytes(c->p.storage)});
   if (c->p.storage != VCLB_FP64) v.push_back({c->lay.phis[par], n * 4});
   v.push_back({c->lay.mass, sizeof(double)});   // V_ref of the global volume correction
   return v;
@@ -1110,7 +1114,7 @@ int vclb_state_save(vclb_case* c, void* host_buf, size_t bytes, void* stream) {
   HIP_TRY(hipStreamSynchronize(s));
   CkptHeader h{};
   std::memcpy(h.magic, "VCLBCKP1", 8);
-  h.version = 1;
+  h.version = 2;   // 2: population and J planes padded to a multiple of 64 entries
   h.storage = uint32_t(c->p.storage);
   h.param_hash = params_hash(c->p);
   h.step = c->t_host;
@@ -1127,7 +1131,7 @@ int vclb_state_load(vclb_case* c, const void* host_buf, size_t bytes, void* stre
   if (bytes < need) return fail(VCLB_EINVAL, "checkpoint truncated");
   CkptHeader h;
   std::memcpy(&h, host_buf, sizeof(h));
-  if (std::memcmp(h.magic, "VCLBCKP1", 8) != 0 || h.version != 1) return fail(VCLB_EINVAL, "not a checkpoint");
+  if (std::memcmp(h.magic, "VCLBCKP1", 8) != 0 || h.version != 2) return fail(VCLB_EINVAL, "not a checkpoint of this layout");
   if (h.param_hash != params_hash(c->p)) return fail(VCLB_EINVAL, "checkpoint of a different case");
   if (h.payload_bytes != need - sizeof(CkptHeader) || h.step < 0) return fail(VCLB_EINVAL, "corrupt checkpoint header");
   const char* src = static_cast<const char*>(host_buf) + sizeof(CkptHeader);
@@ -1196,29 +1200,49 @@ int dispatch_storage(int storage, Fn&& fn) {
   }
 }
 
-// work items of a tile shape: per case, bands of ty rows, x strips of bx columns fastest
-// Whether case p runs as flattened bands: when one lane per column would leave more
+// whether the flattened march's LDS ring for rows of nx nodes fits 64 KiB at this lag
+bool flat_ring_fits(const vclb_params& p, int bx, int lag) {
+  return size_t(vclb::flat_ring_cap(p.nx, bx, lag)) * 2 * arith_bytes(p.storage) <= 64 * 1024;
+}
+
+// Whether case p may run as flattened bands: when one lane per column would leave more
 // than (100 - flat_pct)% of the lanes of its strips idle (strips of bx columns, each on
-// a bx-lane workgroup) and its rows fit the flattened march with bx lanes.  Below 101
-// only cases that need the short lag (a row fits in one chunk) qualify: the long lag
-// holds more populations in flight and costs the whole kernel a wave of occupancy.
-bool batch_case_flat(const vclb_params& p, int bx, int flat_pct) {
+// a bx-lane workgroup) and its rows fit the flattened march with bx lanes (a lag of at
+// most 3 chunks, and its LDS ring within 64 KiB).  Below 101 only cases that need the
+// short lag (a row fits in one chunk) qualify: the long lag holds more populations in
+// flight and costs the whole kernel a wave of occupancy.
+bool batch_case_band_candidate(const vclb_params& p, int bx, int flat_pct) {
   const long lanes = long((p.nx + bx - 1) / bx) * bx;
-  const int lag = vclb::flat_lag(p.nx + 2, bx);
-  if (lag == 0 || 100L * p.nx >= long(flat_pct) * lanes) return false;
+  const int lag = vclb::flat_lag(p.nx, bx);
+  if (lag == 0 || 100L * p.nx >= long(flat_pct) * lanes || !flat_ring_fits(p, bx, lag)) return false;
   return flat_pct > 100 || lag == 1;
+}
+
+// The lag of a batch's flattened march: the longest its band candidates need.
+int batch_flat_lag(const vclb_batch* b, int bx, int flat_pct) {
+  int lag = 1;
+  for (const vclb_case* c : b->cases)
+    if (batch_case_band_candidate(c->p, bx, flat_pct)) lag = std::max(lag, vclb::flat_lag(c->p.nx, bx));
+  return lag;
+}
+
+// Whether case p runs as flattened bands in a march of this lag: a candidate whose ring
+// still fits at the batch's lag (the ring of narrow rows grows with the lag).
+bool batch_case_flat(const vclb_params& p, int bx, int flat_pct, int lag) {
+  return batch_case_band_candidate(p, bx, flat_pct) && flat_ring_fits(p, bx, lag);
 }
 
 // Work items, case-major: flattened bands of whole rows holding about ty * 256 nodes, or
 // strips of bx columns by bands of rows holding about as many nodes (strip-major, so that
 // a run of items marches on down one strip).
-void build_items(vclb_batch* b, int bx, int ty, int flat_pct, std::vector<int4>& items, std::vector<int2>& ci) {
+void build_items(vclb_batch* b, int bx, int ty, int flat_pct, int lag, std::vector<int4>& items,
+                 std::vector<int2>& ci) {
   items.clear();
   ci.assign(size_t(b->n), int2{0, 0});
   for (int k = 0; k < b->n; ++k) {
     const vclb_params& p = b->cases[size_t(k)]->p;
     const int first = int(items.size());
-    if (batch_case_flat(p, bx, flat_pct)) {
+    if (batch_case_flat(p, bx, flat_pct, lag)) {
       const int P = p.nx + 2;
       const int rows = std::max(1, std::min(p.ny, (ty * 256 + P / 2) / P));
       for (int y0 = 0; y0 < p.ny; y0 += rows) items.push_back(int4{k, -1, y0, std::min(y0 + rows, p.ny)});
@@ -1233,15 +1257,16 @@ void build_items(vclb_batch* b, int bx, int ty, int flat_pct, std::vector<int4>&
 }
 
 // Modelled cost of a work item in march iterations: a flattened band of r rows costs
-// ceil((r + 2) P / bx) + lag chunk iterations, a strip band r + 2 row iterations (both
-// pull two halo rows); returned as a per-item overhead plus a cost per row.
+// about ((r + 2) nx + 32) / bx + lag chunk iterations, a strip band r + 2 row iterations
+// (both pull two halo rows); returned as a per-item overhead plus a cost per row.  A band
+// row also carries one extra pull (its column -1), counted as one more node.
 struct ItemCost {
   double over, row;
 };
 ItemCost item_cost(const vclb_batch* b, const int4& w, int bx, int lag) {
   if (w.y < 0) {
-    const double P = b->cases[size_t(w.x)]->p.nx + 2.0;
-    return {2.0 * P / bx + lag + 0.5, P / bx};
+    const double nx = b->cases[size_t(w.x)]->p.nx;
+    return {(2.0 * (nx + 1.0) + 32.0) / bx + lag + 0.5, (nx + 1.0) / bx};
   }
   return {2.0, 1.0};
 }
@@ -1325,18 +1350,15 @@ int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
       flat_pct > 101)
     return fail(VCLB_EINVAL, "bad batch launch shape (bx in {64, 128, 256, 512, 1024}; ty in 1..1024; flat_pct in 0..101)");
   if (bx == 1024 && b->storage == VCLB_FP64) return fail(VCLB_EINVAL, "1024-lane workgroups need FP32 or FP16S storage");
-  int pmax = 1, lag = 1;
-  for (const vclb_case* c : b->cases) {
-    if (!batch_case_flat(c->p, bx, flat_pct)) continue;
-    lag = std::max(lag, vclb::flat_lag(c->p.nx + 2, bx));
-    pmax = std::max(pmax, c->p.nx + 2);
-  }
-  const int cap = vclb::flat_ring_cap(pmax, bx, lag);
+  const int lag = batch_flat_lag(b, bx, flat_pct);
+  int cap = 1;
+  for (const vclb_case* c : b->cases)
+    if (batch_case_flat(c->p, bx, flat_pct, lag)) cap = std::max(cap, vclb::flat_ring_cap(c->p.nx, bx, lag));
   const size_t lds = dispatch_storage(b->storage, [&](auto st) { return int(vclb::batch_lds_bytes<decltype(st)>(cap, bx)); });
   if (lds > 64 * 1024) return fail(VCLB_EINVAL, "a case is too wide for the batched step with this tile");
   std::vector<int4> items;
   std::vector<int2> ci, runs;
-  build_items(b, bx, ty, flat_pct, items, ci);
+  build_items(b, bx, ty, flat_pct, lag, items, ci);
   int per_cu = dispatch_storage(b->storage, [&](auto st) {
     return vclb::batch_max_blocks_per_cu<decltype(st)>(bx, cap, lag, b->unit);
   });
@@ -2017,7 +2039,7 @@ AdjStore adj_layout(const vclb_params& p, int64_t nsteps, int32_t every) {
   a.every = every;
   a.nckpt = nsteps > 0 ? (nsteps + every - 1) / every : 0;
   a.n = size_t(p.nx) * p.ny;
-  a.state = 20 * a.n;
+  a.state = 20 * size_t(vclb::plane_stride(long(a.n)));   // g, f, J in the case's padded planes
   a.blocks = vclb::adj_blocks(long(a.n));
   size_t off = 0;
   auto take = [&](size_t doubles) {
@@ -2056,11 +2078,11 @@ int adj_check_case(const vclb_case* c) {
 
 // copy the case's current state (pulled populations of the current parity, Jprev)
 int adj_save_state(vclb_case* c, double* dst, hipStream_t s) {
-  const size_t n = c->adj->n;
+  const size_t ns = size_t(vclb::plane_stride(long(c->adj->n)));   // the case's plane stride
   const int par = int(c->t_host & 1);
-  HIP_TRY(hipMemcpyAsync(dst, c->ws + c->lay.pop[0][par], 9 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipMemcpyAsync(dst + 9 * n, c->ws + c->lay.pop[1][par], 9 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipMemcpyAsync(dst + 18 * n, c->ws + c->lay.J, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dst, c->ws + c->lay.pop[0][par], 9 * ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dst + 9 * ns, c->ws + c->lay.pop[1][par], 9 * ns * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dst + 18 * ns, c->ws + c->lay.J, 2 * ns * sizeof(double), hipMemcpyDeviceToDevice, s));
   return VCLB_OK;
 }
 
@@ -2190,6 +2212,7 @@ int vclb_adjoint_run(vclb_case* c, const double* seed, double normal_tau, double
   AdjStore& st = *c->adj;
   char* M = st.mem;
   const size_t n = st.n;
+  const size_t ns = size_t(vclb::plane_stride(long(n)));   // plane stride of the state snapshots
   auto dptr = [&](size_t off) { return reinterpret_cast<double*>(M + off); };
   HIP_TRY(hipMemcpyAsync(dptr(st.seed), seed, size_t(nl) * vclb::kSeedFields * sizeof(double),
                          hipMemcpyHostToDevice, s));
@@ -2228,24 +2251,24 @@ int vclb_adjoint_run(vclb_case* c, const double* seed, double normal_tau, double
                            hipMemcpyDeviceToDevice, s));
     // recompute the segment's states with the forward step (no reductions)
     for (int64_t k = 0; k + 1 < len && !rc; ++k) {
-      HIP_TRY(hipMemcpyAsync(slot(k + 1) + 18 * n, slot(k) + 18 * n, 2 * n * sizeof(double),
+      HIP_TRY(hipMemcpyAsync(slot(k + 1) + 18 * ns, slot(k) + 18 * ns, 2 * ns * sizeof(double),
                              hipMemcpyDeviceToDevice, s));
       auto f = base;
       f.pop[0][0] = slot(k);
-      f.pop[1][0] = slot(k) + 9 * n;
+      f.pop[1][0] = slot(k) + 9 * ns;
       f.pop[0][1] = slot(k + 1);
-      f.pop[1][1] = slot(k + 1) + 9 * n;
-      f.J = slot(k + 1) + 18 * n;
+      f.pop[1][1] = slot(k + 1) + 9 * ns;
+      f.J = slot(k + 1) + 18 * ns;
       rc = vclb::launch_step_fused<vclb::D2Q9, vclb::StoreF64, true>(f, c->tile, 0, s);
     }
     // backward through the segment
     for (int64_t k = len - 1; k >= 0 && !rc; --k) {
       auto b = base;
       b.pop[0][0] = slot(k);
-      b.pop[1][0] = slot(k) + 9 * n;
+      b.pop[1][0] = slot(k) + 9 * ns;
       b.pop[0][1] = nullptr;
       b.pop[1][1] = nullptr;
-      b.J = slot(k) + 18 * n;
+      b.J = slot(k) + 18 * ns;
       bind(cur);
       rc = vclb::launch_phi_psi<vclb::D2Q9, vclb::StoreF64>(b, s);
       if (!rc) rc = vclb::launch_adj_step(b, a, s);

@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(256) k_adj_local(DC c, AdjArgs a) {
     const R Jx = phi * ux, Jy = phi * uy;
     const R r = sqrt(gsx * gsx + gsy * gsy + p.eps2);
     const R nxn = gsx / r, nyn = gsy / r;
-    const R Vx = R(3) * (Jx - c.J[n]) + An * nxn, Vy = R(3) * (Jy - c.J[c.n + n]) + An * nyn;
+    const R Vx = R(3) * (Jx - c.J[n]) + An * nxn, Vy = R(3) * (Jy - c.J[c.ns + n]) + An * nyn;
     R gm[9];
     d2q9_moments<R>(g, gm);
     const R H = mu + p.lam * phi;

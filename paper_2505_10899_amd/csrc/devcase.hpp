@@ -19,13 +19,15 @@ struct DevCase {
   using R = typename St::R;
   int nx, ny, nz;
   long n;                       // nx * ny * nz
+  long ns;                      // entries per plane of the populations and of J: n rounded up
+                                // to a multiple of 64, so that every plane starts on a cache line
   int wall;                     // bounce-back walls bound y
   int nl;                       // labels (1..kMaxLabels)
   int unit_rates;               // every rate outside the g flux and f stress rows is 1
   int visc;                     // the phases have different viscosities (per-node tau_f)
   double cen[kMaxLabels][3];    // label centres
   S* pop[2][2];                 // [g = 0, f = 1][buffer]; f is null in vortex mode
-  R* J;                         // previous phi u, D * n
+  R* J;                         // previous phi u, D planes of ns entries
   float* phis[2];               // FP16S: phi of the node that wrote each buffer entry
   long t;                       // step index of the state this launch reads
   double* part_w;               // this launch's workgroup partials, [label * 12 + field][workgroup]
@@ -96,7 +98,7 @@ __device__ __forceinline__ void pull(const Case& c, const typename St::S* __rest
     if (L::cx[i] != 0) xs = wrapi(xs, c.nx);
     if (L::cz[i] != 0) zs = wrapi(zs, c.nz);
     const long s = xs + long(c.nx) * (ys + long(c.ny) * zs);
-    out[i] = St::load(src, long(pi) * c.n + s);
+    out[i] = St::load(src, long(pi) * c.ns + s);
   }
   if constexpr (St::shifted) {
     if (ps) {
@@ -263,7 +265,7 @@ __device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, lon
     R d = g[i];
     if constexpr (St::shifted)
       d = encode_dev(g[i], c.np.rest[i], phi, leaves_through_wall<L>(i, y, c.ny, c.wall != 0) ? phi : nphi[i]);
-    St::store(c.pop[0][dst], long(i) * c.n + n, d);
+    St::store(c.pop[0][dst], long(i) * c.ns + n, d);
     if constexpr (St::fold) res += St::rounding(d);
   }
   if constexpr (COUPLED) {
@@ -280,10 +282,10 @@ __device__ __forceinline__ void store_node(const DevCase<L, St>& c, int par, lon
       }
     }
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) St::store(c.pop[1][dst], long(i) * c.n + n, f[i]);
+    for (int i = 0; i < L::Q; ++i) St::store(c.pop[1][dst], long(i) * c.ns + n, f[i]);
   }
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) stg(c.J, d * c.n + n, J[d]);
+  for (int d = 0; d < L::D; ++d) stg(c.J, d * c.ns + n, J[d]);
   if constexpr (St::shifted) stg(c.phis[dst], n, float(phi - res));
 }
 

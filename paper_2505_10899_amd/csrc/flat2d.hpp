@@ -1,22 +1,28 @@
 // One work item of the batched D2Q9 step: a band of rows [y0, y1) of one case, marched
-// in the row-major order of the case padded by one ghost column on each side.
+// in the case's stored (row-major) order.
 //
-// Lanes walk consecutive nodes of that padded order, so a row of any width keeps every
-// lane busy (a 200-wide case leaves no partial wave at the end of each row) and
-// successive rows run back to back.  Virtual index v = (y + 1) P + (x + 1), P = nx + 2,
-// covers x in [-1, nx] and y in [-1, ny]; ghost columns hold the periodic neighbour
-// column, ghost rows the periodic neighbour row or, behind a wall, the wetting ghost of
-// the edge row (the edge row itself for a neutral wall).  Every stencil neighbour of v is then v + cx + P cy.
+// Lanes walk consecutive stored nodes, so a row of any width keeps every lane busy and
+// successive rows run back to back.  Chunks of B lanes start on multiples of 64 nodes;
+// with every plane starting on a cache line (planes of ns entries, a multiple of 64),
+// each wave then stores whole cache lines.  The band's window is the rows y0 - 1 .. y1 in
+// extended stored order e = r nx + x (r in [y0 - 1, y1]); its first and last rows are
+// halo rows, pulled for phi and not updated.  Row r = -1 or ny holds the periodic
+// neighbour row or, behind a wall, the wetting ghost of the edge row (the edge row itself
+// for a neutral wall).
 //
-// The band's window (padded rows y0 - 1 .. y1) is cut into chunks of B consecutive
-// virtual nodes, one per lane.  Iteration i pulls the populations of chunk i, forms
-// phi and psi into an LDS ring of `cap` entries (a power of two), and keeps the pulled
-// populations in a register FIFO of DL + 1 slots; it then updates chunk i - DL from the
-// FIFO, in the same lanes that pulled it, once the ring holds every stencil input of
-// that chunk (DL B >= P + 1).  Each population is read from memory once, as in the row
-// march.  One barrier per iteration suffices when cap > (DL + 2) B + P: the chunk
-// written in iteration i + 1 cannot share a ring slot with anything iteration i's
-// update still reads.
+// phi and psi go into an LDS ring of `cap` entries (a power of two) at the padded
+// position v = (r + 1) P + x + 1, P = nx + 2, so that the stencil neighbours of v are
+// v + cx + P cy.  Column -1 of a row holds the periodic image of its column nx - 1: the
+// lane of column 0 forms it with a second pull, so that it is ready as early as the row's
+// first node.  A neighbour past column nx - 1 is read from column 0 of its row.
+//
+// Iteration i pulls the populations of chunk i, forms phi and psi into the ring, and
+// keeps the pulled populations in a register FIFO of DL + 1 slots; it then updates chunk
+// i - DL from the FIFO, in the same lanes that pulled it, once the ring holds every
+// stencil input of that chunk.  Node e needs the ring up to stored node e + nx + 1, so
+// DL B >= nx + 1.  Each population is read from memory once, as in the row march.  One
+// barrier per iteration suffices when the ring spans the reads of iteration i together
+// with the writes of iteration i + 1 (flat_ring_cap).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -28,30 +34,17 @@
 
 namespace vclb {
 
-// v = q P + r with 0 <= r < P (v < 2^24, P >= 3), without an integer division
-__device__ __forceinline__ void divmod_pitch(int v, int P, float rcpP, int& q, int& r) {
-  q = int(float(v) * rcpP);
-  r = v - q * P;
-  if (r < 0) {
-    --q;
-    r += P;
-  } else if (r >= P) {
-    ++q;
-    r -= P;
-  }
-}
-
 // Pull of the 9 populations arriving at node (x, y) of an nx x ny case from the stored
 // direction planes src[i] (uniform over the wave): periodic wrap and, behind a wall, the
 // node's own opposite population.  Every offset is a non-negative 32-bit index from a
 // uniform base, so each address is one shift-add with no sign extension: directions
 // 2, 5, 6 index from their own planes (a bounce from the bottom wall reads plane
 // opp(i) = i + 2 at s0 + 2n), directions 4, 7, 8 from the plane of opp(i) = i - 2 (their
-// own entry lies 2n further on; a bounce from the top wall reads s0 there).  ps (shifted
-// storage): the phi the stored deviations refer to, this node's own phis entry.
+// own entry lies 2 ns further on; a bounce from the top wall reads s0 there).  ps
+// (shifted storage): the phi the stored deviations refer to, this node's own phis entry.
 template <class St>
 __device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9], const float* __restrict__ phis,
-                                           int x, int y, int nx, int ny, int n, bool wall,
+                                           int x, int y, int nx, int ny, int ns, bool wall,
                                            typename St::R (&v)[9], typename St::R* ps) {
   using R = typename St::R;
   const unsigned s0 = unsigned(x + nx * y);
@@ -61,7 +54,7 @@ __device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9]
   const int yp = y == ny - 1 ? (1 - ny) * nx : nx;     // to row y + 1
   // writer of direction i sits at (x - cx_i, y - cy_i)
   unsigned nd[9] = {s0, s0 + xm, s0 + ym, s0 + xp, s0 + yp, s0 + xm + ym, s0 + xp + ym, s0 + xp + yp, s0 + xm + yp};
-  const unsigned n2 = 2u * unsigned(n);
+  const unsigned n2 = 2u * unsigned(ns);
   unsigned off[9] = {nd[0], nd[1], nd[2], nd[3], nd[4] + n2, nd[5], nd[6], nd[7] + n2, nd[8] + n2};
   if (wall && y == 0) {        // c_y = +1 directions 2, 5, 6 come back from 4, 7, 8 of this node
     nd[2] = nd[5] = nd[6] = s0;
@@ -96,11 +89,10 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
   static_assert((DEPTH & (DEPTH - 1)) == 0, "FIFO depth must be a power of two");
   const int B = blockDim.x;
   const int lane = threadIdx.x;
-  const int nx = c.nx, ny = c.ny, n = int(c.n);
+  const int nx = c.nx, ny = c.ny, ns = int(c.ns);
   const int P = nx + 2;
-  const float rcpP = 1.0f / float(P);
   const int mask = cap - 1;
-  // phi and psi of a virtual node side by side: one 2-word LDS access per stencil point
+  // phi and psi of a node side by side: one 2-word LDS access per stencil point
   struct alignas(2 * sizeof(R)) PhiPsi {
     R phi, psi;
   };
@@ -111,24 +103,45 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
   const S* fsrc[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    gsrc[i] = c.pop[0][par] + long(i) * n;
-    fsrc[i] = c.pop[1][par] + long(i) * n;
+    gsrc[i] = c.pop[0][par] + long(i) * ns;
+    fsrc[i] = c.pop[1][par] + long(i) * ns;
   }
   const float* phis = c.phis[par];
   const bool wall = c.wall != 0;
-  const int f_begin = y0 * P, f_end = (y1 + 2) * P;   // padded rows y0 - 1 .. y1
-  const int nchunk = (f_end - f_begin + B - 1) / B;
+  // the window's extended stored range [e_begin, e_end) and the first chunk's start, the
+  // multiple of 64 at or below e_begin
+  const int e_begin = (y0 - 1) * nx, e_end = (y1 + 1) * nx;
+  const int e_first = e_begin - (((e_begin % 64) + 64) % 64);
+  const int nchunk = (e_end - e_first + B - 1) / B;
   const int niter = nchunk + DL;
   R e[DEPTH][Q];          // pulled populations of the last DEPTH chunks (static indices only)
-  int ex[DEPTH], ey[DEPTH];   // their padded coordinates (x, y in [-1, nx] x [-1, ny])
+  int ex[DEPTH], ey[DEPTH];   // their nodes' column and row (row -2: the lane has no node)
 #pragma unroll
-  for (int k = 0; k < DEPTH; ++k) ex[k] = ey[k] = -1;
+  for (int k = 0; k < DEPTH; ++k) {
+    ex[k] = 0;
+    ey[k] = -2;
+  }
   double a0 = 0.0, ax = 0.0, ay = 0.0, axx = 0.0, ayy = 0.0, axy = 0.0;   // one label per case
   int acnt = 0, abad = 0;
-  // padded coordinates of this lane's front node, advanced by B nodes per iteration
-  int qf, rf;
-  divmod_pitch(f_begin + lane, P, rcpP, qf, rf);
-  const int dq = B / P, dr = B - dq * P;
+  // row and column of this lane's front node, advanced by B nodes per iteration
+  int rf, xf;
+  {
+    const int e0 = e_first + lane;
+    rf = e0 / nx;
+    xf = e0 - rf * nx;
+    if (xf < 0) {   // floor division for the rows above row 0
+      xf += nx;
+      --rf;
+    }
+  }
+  const int dq = B / nx, dr = B - dq * nx;
+  // phi and psi of a pulled node of ring row r (stored row yr) into ring position v
+  auto form = [&](R (&g)[Q], const R (&ps)[Q], int r, int v) {
+    R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
+    if (wall && r < 0) ph = wet_ghost<R>(ph, c.np.wet_lo);          // ghost row y = -1
+    else if (wall && r >= ny) ph = wet_ghost<R>(ph, c.np.wet_hi);   // ghost row y = ny
+    sring[v & mask] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
+  };
 
   auto iteration = [&](int i, auto front_slot) {
     constexpr int SF = decltype(front_slot)::value;
@@ -137,36 +150,39 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
     // its f and previous phi u are requested first, so that they are in flight while the
     // front's phi is formed
     const int x = ex[SU], y = ey[SU];
-    const bool act = i >= DL && x >= 0 && x < nx && y >= y0 && y < y1;
+    const bool act = i >= DL && y >= y0 && y < y1;
     R f[Q], J[2];
     const unsigned nn = unsigned(x + nx * y);
     if (act) {
-      pull9_flat<St>(fsrc, phis, x, y, nx, ny, n, wall, f, nullptr);
+      pull9_flat<St>(fsrc, phis, x, y, nx, ny, ns, wall, f, nullptr);
       J[0] = ldg(c.J, nn);
-      J[1] = ldg(c.J + n, nn);
+      J[1] = ldg(c.J + ns, nn);
     }
     // front: chunk i
     {
-      const int vf = f_begin + i * B + lane;
-      ex[SF] = rf - 1;
-      ey[SF] = qf - 1;
-      if (i < nchunk && vf < f_end) {
-        int xr = rf - 1, yr = qf - 1;
-        xr = xr < 0 ? nx - 1 : (xr >= nx ? 0 : xr);
+      const int ef = e_first + i * B + lane;
+      const bool valid = i < nchunk && ef >= e_begin && ef < e_end;
+      ex[SF] = xf;
+      ey[SF] = valid ? rf : -2;
+      if (valid) {
+        int yr = rf;
         if (yr < 0) yr = wall ? 0 : ny - 1;
         else if (yr >= ny) yr = wall ? ny - 1 : 0;
+        const int vf = (rf + 1) * P + xf + 1;
         R ps[Q];
-        pull9_flat<St>(gsrc, phis, xr, yr, nx, ny, n, wall, e[SF], ps);
-        R ph = phi_of_pulled<L, St>(e[SF], ps, c.np.rest);
-        if (wall && qf < 1) ph = wet_ghost<R>(ph, c.np.wet_lo);         // ghost row y = -1
-        else if (wall && qf > ny) ph = wet_ghost<R>(ph, c.np.wet_hi);   // ghost row y = ny
-        sring[vf & mask] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
+        pull9_flat<St>(gsrc, phis, xf, yr, nx, ny, ns, wall, e[SF], ps);
+        form(e[SF], ps, rf, vf);
+        if (xf == 0) {   // column -1 of this row: the periodic image of column nx - 1
+          R gh[Q], hps[Q];
+          pull9_flat<St>(gsrc, phis, nx - 1, yr, nx, ny, ns, wall, gh, hps);
+          form(gh, hps, rf, vf - 1);
+        }
       }
-      rf += dr;
-      qf += dq;
-      if (rf >= P) {
-        rf -= P;
-        ++qf;
+      xf += dr;
+      rf += dq;
+      if (xf >= nx) {
+        xf -= nx;
+        ++rf;
       }
     }
     __syncthreads();
@@ -175,8 +191,9 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
       NodeIn<L, R> in;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const int s = (vu + L::cx[j] + P * L::cy[j]) & mask;
-        const PhiPsi v = sring[s];
+        int s = vu + L::cx[j] + P * L::cy[j];
+        if (L::cx[j] > 0 && x == nx - 1) s -= nx;   // past the last column: column 0
+        const PhiPsi v = sring[s & mask];
         in.nphi[j] = v.phi;
         in.npsi[j] = v.psi;
       }
@@ -189,7 +206,7 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
         if constexpr (St::shifted)   // relative to the reader's phi (encode_dev)
           d = encode_dev(e[SU][j], c.np.rest[j], in.nphi[0],
                          leaves_through_wall<L>(j, y, ny, wall) ? in.nphi[0] : in.nphi[j]);
-        St::store(c.pop[0][dst] + long(j) * n, nn, d);
+        St::store(c.pop[0][dst] + long(j) * ns, nn, d);
         if constexpr (St::fold) res += St::rounding(d);
       }
       if (wall && y == 0) {
@@ -203,9 +220,9 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
           if (L::cy[j] > 0) f[j] += c.np.wt[j] * out.rho;
       }
 #pragma unroll
-      for (int j = 0; j < Q; ++j) St::store(c.pop[1][dst] + long(j) * n, nn, f[j]);
+      for (int j = 0; j < Q; ++j) St::store(c.pop[1][dst] + long(j) * ns, nn, f[j]);
       stg(c.J, nn, J[0]);
-      stg(c.J + n, nn, J[1]);
+      stg(c.J + ns, nn, J[1]);
       if constexpr (St::shifted) stg(c.phis[dst], nn, float(in.nphi[0] - res));
       if (reduce) {
         const double ph = double(in.nphi[0]);

@@ -79,11 +79,11 @@ __global__ void __launch_bounds__(256) k_init(DevCase<L, St> c, const double* __
     R gv = geq;
     // shifted storage: relative to the reader's phis entry, phi0 at this node n
     if constexpr (St::shifted) gv -= R(float(phi0[n])) * c.np.rest[pi];
-    St::store(c.pop[0][0], long(pi) * c.n + s, gv);
-    if constexpr (COUPLED) St::store(c.pop[1][0], long(pi) * c.n + s, feq);
+    St::store(c.pop[0][0], long(pi) * c.ns + s, gv);
+    if constexpr (COUPLED) St::store(c.pop[1][0], long(pi) * c.ns + s, feq);
   }
 #pragma unroll
-  for (int d = 0; d < D; ++d) c.J[d * c.n + n] = phi * u[d];
+  for (int d = 0; d < D; ++d) c.J[d * c.ns + n] = phi * u[d];
   if constexpr (St::shifted) c.phis[0][n] = float(phi0[n]);
 }
 
@@ -114,11 +114,11 @@ __global__ void __launch_bounds__(256) k_set_state(DevCase<L, St> c, const doubl
       for (int k = 0; k < L::Q; ++k) ps += g[long(k) * c.n + n];
       gv -= R(float(ps)) * c.np.rest[pi];
     }
-    St::store(c.pop[0][par], long(pi) * c.n + s, gv);
-    if constexpr (COUPLED) St::store(c.pop[1][par], long(pi) * c.n + s, R(f[long(i) * c.n + n]));
+    St::store(c.pop[0][par], long(pi) * c.ns + s, gv);
+    if constexpr (COUPLED) St::store(c.pop[1][par], long(pi) * c.ns + s, R(f[long(i) * c.n + n]));
   }
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) c.J[d * c.n + n] = R(J[d * c.n + n]);
+  for (int d = 0; d < L::D; ++d) c.J[d * c.ns + n] = R(J[d * c.n + n]);
   if constexpr (St::shifted) {
     double ps = 0.0;
     for (int k = 0; k < L::Q; ++k) ps += g[long(k) * c.n + n];
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(256) k_get_state(DevCase<L, St> c, double* __r
     for (int i = 0; i < L::Q; ++i) f[long(i) * c.n + n] = double(v[i]);
   }
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) J[d * c.n + n] = double(c.J[d * c.n + n]);
+  for (int d = 0; d < L::D; ++d) J[d * c.n + n] = double(c.J[d * c.ns + n]);
 }
 
 // ---------------------------------------------------------------- plain path, pass 1
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(256) k_collide_plain(DevCase<L, St> c, int red
     (void)phi_of_pulled<L, St>(g, ps, c.np.rest);
     if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, nullptr);
 #pragma unroll
-    for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
+    for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.ns + n];
     NodeOut<L, R> out;
     node_update_any<L, R, COUPLED, St::shifted>(c.np, c.visc != 0, in, g, f, J, out);
     if (c.mfix) {   // g_i += w_i kappa delta(phi_c): the global correction's source
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) k_fields(DevCase<L, St> c, unsigned mask,
   (void)phi_of_pulled<L, St>(g, ps, c.np.rest);
   if constexpr (COUPLED) pull<L, St>(c, c.pop[1][par], c.phis[par], x, y, z, f, nullptr);
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.n + n];
+  for (int d = 0; d < L::D; ++d) J[d] = c.J[d * c.ns + n];
   NodeOut<L, R> o;
   node_update_any<L, R, COUPLED, St::shifted>(c.np, c.visc != 0, in, g, f, J, o);
   long off = 0;

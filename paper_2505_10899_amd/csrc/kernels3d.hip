@@ -56,28 +56,28 @@ __device__ __forceinline__ int pull_index(const Nbr3& o) {
 }
 
 // The 19 pulls at one node: 32-bit node offsets from the uniform base of each
-// direction's plane (the case has fewer than 2^31 nodes), accessed with index type IX
+// direction's plane (planes of ns entries; the case has fewer than 2^31 nodes), accessed with index type IX
 // (unsigned: 32-bit byte offsets, when n times the element size fits them).  ps (shifted
 // storage): the phi the stored deviations refer to, this node's own phis entry.
 template <class St, class IX>
 __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, const float* __restrict__ phis,
-                                       long n, const Nbr3& o, typename St::R (&out)[19], typename St::R* ps) {
+                                       long ns, const Nbr3& o, typename St::R (&out)[19], typename St::R* ps) {
   using L = D3Q19;
   using R = typename St::R;
   static_for<0, L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     int s = pull_index<i>(o);
-    const typename St::S* base = src + i * n;
+    const typename St::S* base = src + i * ns;
     if constexpr (L::cy[i] > 0) {   // from the row below: behind the bottom wall at y = 0
       if (o.lo) {
         s = o.s0;
-        base = src + L::opp[i] * n;
+        base = src + L::opp[i] * ns;
       }
     }
     if constexpr (L::cy[i] < 0) {   // from the row above: behind the top wall at y = ny - 1
       if (o.hi) {
         s = o.s0;
-        base = src + L::opp[i] * n;
+        base = src + L::opp[i] * ns;
       }
     }
     out[i] = St::load(base, IX(s));
@@ -157,7 +157,7 @@ __device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const
       d = encode_dev(gcur[i], c.np.rest[i], st.phi,
                      leaves_through_wall<L>(i, yw, c.ny, wall) ? st.phi : sring[sr].phi);
     }
-    St::store(c.pop[0][dst] + i * c.n, IX(nn), d);
+    St::store(c.pop[0][dst] + i * c.ns, IX(nn), d);
     if constexpr (St::fold) res += St::rounding(d);
   }
   if (wall && yw == 0) {   // moving-wall term of the populations the bottom wall returns
@@ -171,9 +171,9 @@ __device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const
       if (L::cy[i] > 0) f[i] += c.np.wt[i] * out.rho;
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.n, IX(nn), f[i]);
+  for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.ns, IX(nn), f[i]);
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) stg(c.J + d * c.n, IX(nn), J[d]);
+  for (int d = 0; d < L::D; ++d) stg(c.J + d * c.ns, IX(nn), J[d]);
   if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi - res));
   if (reduce) {
     const double ph = double(st.phi);
@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     const int zr = wrapi(z, c.nz);
     const int s = ring_slot3d(z) * PS;
     R ps[Q];
-    pull19<St, IX>(gsrc, phis, c.n, nbr3(xw, yw, zr, nx, ny, nz, nxy, wall), g, ps);
+    pull19<St, IX>(gsrc, phis, c.ns, nbr3(xw, yw, zr, nx, ny, nz, nxy, wall), g, ps);
     R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     if (yside) ph = wet_ghost<R>(ph, c.np.wet_hi);   // a lane past a wall holds the ghost row
     sring[s + (ty + 1) * PW + tx + 1] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
       const int hside = wall ? (hyr < 0 ? -1 : (hyr >= ny ? 1 : 0)) : 0;
       const int hy = wall ? (hyr < 0 ? 0 : (hyr >= ny ? ny - 1 : hyr)) : ((hyr % ny) + ny) % ny;
       R gh[Q], hps[Q];
-      pull19<St, IX>(gsrc, phis, c.n, nbr3(hx, hy, zr, nx, ny, nz, nxy, wall), gh, hps);
+      pull19<St, IX>(gsrc, phis, c.ns, nbr3(hx, hy, zr, nx, ny, nz, nxy, wall), gh, hps);
       R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       if (hside) hp = wet_ghost<R>(hp, hside < 0 ? c.np.wet_lo : c.np.wet_hi);
       sring[s + py * PW + px] = PhiPsi{hp, psi_of<R>(hp, c.np.W4, c.np.xi)};
@@ -344,9 +344,9 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     const int nn = o.s0;
     R f[Q], J[L::D];
     if (active) {
-      pull19<St, IX>(fsrc, phis, c.n, o, f, nullptr);
+      pull19<St, IX>(fsrc, phis, c.ns, o, f, nullptr);
 #pragma unroll
-      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.n, IX(nn));
+      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.ns, IX(nn));
     }
     plane(z + 1, gnext);
     if constexpr (STAGE) stage_put(z + 1, gnext);

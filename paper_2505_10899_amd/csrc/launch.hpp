@@ -70,18 +70,28 @@ int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s);
 template <class St>
 int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit);
 
-// Lag (in chunks of B lanes) of the flattened batched march for rows of padded pitch
-// P = nx + 2: 1 or 3 (the register FIFO holds lag + 1 chunks), 0 if the rows are too
-// wide for B lanes.
-inline int flat_lag(int P, int B) {
-  const int need = (P + 1 + B - 1) / B;
+// Entries per plane of the populations and of J for a case of n nodes: n rounded up to a
+// multiple of 64, so that every plane starts on a cache line.
+inline long plane_stride(long n) { return (n + 63) / 64 * 64; }
+
+// Lag (in chunks of B lanes) of the flattened batched march for rows of nx nodes: the
+// update of stored node e needs phi up to node e + nx + 1, so lag B >= nx + 1; 1 or 3 (the
+// register FIFO holds lag + 1 chunks), 0 if the rows are too wide for B lanes.
+inline int flat_lag(int nx, int B) {
+  const int need = (nx + 1 + B - 1) / B;
   return need <= 1 ? 1 : (need <= 3 ? 3 : 0);
 }
 
-// LDS ring entries (a power of two) of the flattened march: more than (lag + 2) B + P
-inline int flat_ring_cap(int P, int B, int lag) {
+// LDS ring entries (a power of two) of the flattened march.  The oldest stencil input
+// read in iteration i lies at most P + nx ring positions before chunk i - lag (a row's
+// last node reads column 0 of the row above), and the newest entry written in iteration
+// i + 1 ends chunk i + 1: (lag + 2) B stored nodes further on, plus two ring positions
+// (the padding columns) per row they cross.
+inline int flat_ring_cap(int nx, int B, int lag) {
+  const long span = long(lag + 2) * B;
+  const long need = span + 2 * (span / nx + 1) + 2 * nx + 3;
   int cap = 1;
-  while (cap <= (lag + 2) * B + P) cap <<= 1;
+  while (cap <= need) cap <<= 1;
   return cap;
 }
 

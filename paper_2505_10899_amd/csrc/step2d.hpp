@@ -76,7 +76,7 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
     R phi, psi;
   };
   PhiPsi* sring = reinterpret_cast<PhiPsi*>(smem_raw);
-  const int nx = c.nx, ny = c.ny, n = int(c.n);
+  const int nx = c.nx, ny = c.ny, ns = int(c.ns);   // ns: entries per plane
   const int lane = threadIdx.x;
   const int xg = x0 + lane;
   const bool active_x = xg < nx;
@@ -92,8 +92,8 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
   const S* fsrc[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    gsrc[i] = c.pop[0][par] + long(i) * n;
-    fsrc[i] = COUPLED ? c.pop[1][par] + long(i) * n : nullptr;
+    gsrc[i] = c.pop[0][par] + long(i) * ns;
+    fsrc[i] = COUPLED ? c.pop[1][par] + long(i) * ns : nullptr;
   }
   const float* phis = c.phis[par];
   const bool wall = c.wall != 0;
@@ -150,7 +150,7 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
     R f[Q], J[2];
     if constexpr (COUPLED) pull9<St, IX, NT>(fsrc, phis, col, row3(y), f, nullptr);
     J[0] = ldg(c.J, IX(nn));
-    J[1] = ldg(c.J + n, IX(nn));
+    J[1] = ldg(c.J + ns, IX(nn));
     phi_row(y + 1, gnext);
     __syncthreads();
     if (active_x) {
@@ -177,8 +177,8 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
         if constexpr (St::shifted)   // relative to the reader's phi (encode_dev)
           d = encode_dev(gcur[i], c.np.rest[i], in.nphi[0],
                          leaves_through_wall<L>(i, y, ny, wall) ? in.nphi[0] : in.nphi[i]);
-        if constexpr (NT) St::store_nt(c.pop[0][dst] + long(i) * n, IX(nn), d);
-        else St::store(c.pop[0][dst] + long(i) * n, IX(nn), d);
+        if constexpr (NT) St::store_nt(c.pop[0][dst] + long(i) * ns, IX(nn), d);
+        else St::store(c.pop[0][dst] + long(i) * ns, IX(nn), d);
         if constexpr (St::fold) res += St::rounding(d);
       }
       if constexpr (COUPLED) {
@@ -194,12 +194,12 @@ __device__ __forceinline__ void step2d_tile(const DevCase<D2Q9, St>& c, long t, 
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          if constexpr (NT) St::store_nt(c.pop[1][dst] + long(i) * n, IX(nn), f[i]);
-          else St::store(c.pop[1][dst] + long(i) * n, IX(nn), f[i]);
+          if constexpr (NT) St::store_nt(c.pop[1][dst] + long(i) * ns, IX(nn), f[i]);
+          else St::store(c.pop[1][dst] + long(i) * ns, IX(nn), f[i]);
         }
       }
       stg(c.J, IX(nn), J[0]);
-      stg(c.J + n, IX(nn), J[1]);
+      stg(c.J + ns, IX(nn), J[1]);
       if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(in.nphi[0] - res));
       if (reduce) {
         const double ph = double(in.nphi[0]);
