@@ -77,13 +77,21 @@ def log(msg):
 BATCH_SOURCES = ("batch.hip", "flat2d.hpp", "step2d.hpp", "node.hpp", "devcase.hpp", "lattice.hpp", "launch.hpp")
 
 
+def _code_only(text: str) -> str:
+    """A source without its // comments, trailing blanks and empty lines (the sources hold
+    no other comment form): editing a comment does not change the compiled kernel."""
+    lines = (line.split("//", 1)[0].rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line.strip())
+
+
 def source_hash() -> str:
-    """Fingerprint of the sources the batched step kernel is built from: counter figures
-    taken on other sources are stale."""
+    """Fingerprint of the code of the sources the batched step kernel is built from:
+    counter figures taken on other code are stale."""
     h = hashlib.sha256()
     for name in BATCH_SOURCES:
         h.update(name.encode())
-        h.update(open(os.path.join(ROOT, "paper_2505_10899_amd", "csrc", name), "rb").read())
+        with open(os.path.join(ROOT, "paper_2505_10899_amd", "csrc", name), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
