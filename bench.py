@@ -296,6 +296,8 @@ def run_single(name: str, storage: str, steps: int, warmup: int, tune: bool = Tr
     from paper_2505_10899_amd import vclb
     if name == "two_droplets_4096":
         p, phi0, u0 = W.two_droplets(storage, scale=32)
+    elif name == "rayleigh_plateau_96x96x48":   # the z slab one of eight GPUs would hold
+        p, phi0, u0 = W.rayleigh_plateau(storage, nz=48)
     else:
         p, phi0, u0 = W.rayleigh_plateau(storage)
     c = vclb.Case(p).init(phi0, u0)

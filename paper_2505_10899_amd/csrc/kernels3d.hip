@@ -274,7 +274,11 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
   const typename St::S* fsrc = c.pop[1][par];
   const float* phis = c.phis[par];
   const int nx = c.nx, ny = c.ny, nz = c.nz, nxy = nx * ny;
-  const int ring = 2 * PW + 2 * BY;
+  // a section spanning the whole (periodic) x extent holds its own x halo: the columns
+  // beside it are the images of its last and first columns, so only the two halo rows
+  // are pulled
+  const bool own_x_halo = BX == nx;
+  const int ring = own_x_halo ? 2 * PW : 2 * PW + 2 * BY;
   // pull plane z into g, form phi and psi into the ring (with the halo ring)
   auto plane = [&](int z, R (&g)[Q]) {
     const int zr = wrapi(z, c.nz);
@@ -283,7 +287,12 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     pull19<St, IX>(gsrc, phis, c.ns, nbr3(xw, yw, zr, nx, ny, nz, nxy, wall), g, ps);
     R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     if (yside) ph = wet_ghost<R>(ph, c.np.wet_hi);   // a lane past a wall holds the ghost row
-    sring[s + (ty + 1) * PW + tx + 1] = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
+    const PhiPsi own = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
+    sring[s + (ty + 1) * PW + tx + 1] = own;
+    if (own_x_halo) {
+      if (tx == BX - 1) sring[s + (ty + 1) * PW] = own;
+      if (tx == 0) sring[s + (ty + 1) * PW + PW - 1] = own;
+    }
     // halo cells spread evenly over the waves (thread hstep * k takes cell k), so that no
     // wave carries a second full pull while the others wait at the barrier
     const int hstep = nthr >= ring ? nthr / ring : 1;
