@@ -12,9 +12,11 @@
 //
 // phi and psi go into an LDS ring of `cap` entries (a power of two) at the padded
 // position v = (r + 1) P + x + 1, P = nx + 2, so that the stencil neighbours of v are
-// v + cx + P cy.  Column -1 of a row holds the periodic image of its column nx - 1: the
-// lane of column 0 forms it with a second pull, so that it is ready as early as the row's
-// first node.  A neighbour past column nx - 1 is read from column 0 of its row.
+// v + cx + P cy.  Column -1 of a row holds the periodic image of its column nx - 1,
+// formed with a second pull in the iteration whose chunk holds the row's first node, so
+// that it is ready as early as that node (by the chunk's first threads, one row each, or
+// by the lane of column 0).  A neighbour past column nx - 1 is read from column 0 of its
+// row.
 //
 // Iteration i pulls the populations of chunk i, forms phi and psi into the ring, and
 // keeps the pulled populations in a register FIFO of DL + 1 slots; it then updates chunk
@@ -87,6 +89,12 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
   constexpr int Q = 9;
   constexpr int DEPTH = DL + 1;
   static_assert((DEPTH & (DEPTH - 1)) == 0, "FIFO depth must be a power of two");
+  // Column -1 of a row (the periodic image of its column nx - 1) needs a second pull in
+  // the iteration whose chunk holds the row's first node.  COMPACT_COL: the chunk's first
+  // threads take one such row each, so that the fewest waves run these pulls with their
+  // lanes busy (FP16S and FP64, 4% and 3% faster); else the lane of column 0 pulls it
+  // (FP32, memory-bound: 1% faster than either compact or one row per wave)
+  constexpr bool COMPACT_COL = !std::is_same<St, StoreF32>::value;
   // population stores (whole cache lines) with the non-temporal hint for 4-byte arithmetic
   // (FP32 and FP16S storage: measured 2% faster there, and no faster in FP64); the pulls,
   // which straddle cache lines, stay plain (with the hint on them too the step was 3-5%
@@ -128,18 +136,30 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
   }
   double a0 = 0.0, ax = 0.0, ay = 0.0, axx = 0.0, ayy = 0.0, axy = 0.0;   // one label per case
   int acnt = 0, abad = 0;
-  // row and column of this lane's front node, advanced by B nodes per iteration
-  int rf, xf;
-  {
-    const int e0 = e_first + lane;
-    rf = e0 / nx;
-    xf = e0 - rf * nx;
-    if (xf < 0) {   // floor division for the rows above row 0
-      xf += nx;
-      --rf;
+  // row and column of stored node e (floor division: e < 0 lies in the rows above row 0)
+  auto node_of = [&](int e, int& r, int& x) {
+    r = e / nx;
+    x = e - r * nx;
+    if (x < 0) {
+      x += nx;
+      --r;
     }
-  }
+  };
+  // this lane's front node, and the first and last nodes of the front chunk (the same for
+  // every lane), each advanced by B nodes per iteration
+  int rf, xf, ra, xa, rb, xb;
+  node_of(e_first + lane, rf, xf);
+  node_of(e_first, ra, xa);
+  node_of(e_first + B - 1, rb, xb);
   const int dq = B / nx, dr = B - dq * nx;
+  auto advance = [&](int& r, int& x) {
+    x += dr;
+    r += dq;
+    if (x >= nx) {
+      x -= nx;
+      ++r;
+    }
+  };
   // phi and psi of a pulled node of ring row r (stored row yr) into ring position v
   auto form = [&](R (&g)[Q], const R (&ps)[Q], int r, int v) {
     R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
@@ -177,18 +197,28 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
         R ps[Q];
         pull9_flat<St>(gsrc, phis, xf, yr, nx, ny, ns, wall, e[SF], ps);
         form(e[SF], ps, rf, vf);
-        if (xf == 0) {   // column -1 of this row: the periodic image of column nx - 1
+        if (!COMPACT_COL && xf == 0) {   // column -1 of this row, in the lane of column 0
           R gh[Q], hps[Q];
           pull9_flat<St>(gsrc, phis, nx - 1, yr, nx, ny, ns, wall, gh, hps);
           form(gh, hps, rf, vf - 1);
         }
       }
-      xf += dr;
-      rf += dq;
-      if (xf >= nx) {
-        xf -= nx;
-        ++rf;
+      if constexpr (COMPACT_COL) {
+        // column -1 of every window row that starts in this chunk, one row per thread
+        // from thread 0
+        const int rh = ra + (xa != 0 ? 1 : 0) + lane;
+        if (i < nchunk && rh <= rb && rh >= y0 - 1 && rh <= y1) {
+          int yh = rh;
+          if (yh < 0) yh = wall ? 0 : ny - 1;
+          else if (yh >= ny) yh = wall ? ny - 1 : 0;
+          R gh[Q], hps[Q];
+          pull9_flat<St>(gsrc, phis, nx - 1, yh, nx, ny, ns, wall, gh, hps);
+          form(gh, hps, rh, (rh + 1) * P);
+        }
+        advance(ra, xa);
+        advance(rb, xb);
       }
+      advance(rf, xf);
     }
     __syncthreads();
     if (act) {

@@ -1,7 +1,8 @@
 """CPU check of the schedule of the batched band march (the flattened D2Q9 march of the
 batched step): lanes walk the case's stored order in chunks of B that start on multiples
 of 64 nodes; phi and psi go to an LDS ring at padded positions v = (r + 1)(nx + 2) + x + 1
-(column -1 of a row formed by the lane of column 0, column nx read from column 0);
+(column -1 of a row formed in the chunk that holds the row's first node, column nx read
+from column 0);
 iteration i writes chunk i and then updates chunk i - lag.
 
 The lag and ring-size rules below are the ones the library applies when it sets a
