@@ -168,7 +168,7 @@ const char* vclb_last_error(void);
    with the layout of vclb_params or of any other struct here; a library built from this
    header returns the same value from vclb_version, and a caller should refuse a library
    whose major part differs. */
-#define VCLB_VERSION 20000
+#define VCLB_VERSION 20100
 /* Version of the library as MAJOR * 10000 + MINOR * 100 + PATCH (VCLB_VERSION of the
    header it was built from). */
 int vclb_version(void);
@@ -367,8 +367,11 @@ int vclb_adjoint_run(vclb_case* c, const double* seed, double normal_tau, double
    batch owns one device allocation holding every case. */
 typedef struct vclb_batch vclb_batch;
 
-/* Validate every case (all VCLB_D2Q9, VCLB_COUPLED, one storage, nlabels <= 1) and
-   allocate the batch. */
+/* Validate every case (all VCLB_D2Q9, VCLB_COUPLED, one storage, nlabels <= 1, no global
+   correction) and allocate the batch.  Cases may have unequal viscosities (Eq. 27 per
+   node); if any case has, every case relaxes its f stress rows at the per-node rate (its
+   constant tau_f when its viscosities are equal), and a case whose f stress rates are set
+   by hand is refused (VCLB_EINVAL). */
 int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out);
 void vclb_batch_destroy(vclb_batch* b);
 

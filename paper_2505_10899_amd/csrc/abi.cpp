@@ -1179,6 +1179,7 @@ struct vclb_batch {
   bool ticking = false;               // launches record per-slot ticks
   int reduce_every = 1;
   bool unit = true;                   // every case has unit rates outside the g flux / f stress rows
+  bool visc = false;                  // some case has unequal viscosities (per-node tau_f)
   int64_t nodes = 0;
   bool pend = false;
   int pend_buf = 0;
@@ -1360,7 +1361,7 @@ int batch_set_tile(vclb_batch* b, int bx, int ty, int flat_pct) {
   std::vector<int2> ci, runs;
   build_items(b, bx, ty, flat_pct, lag, items, ci);
   int per_cu = dispatch_storage(b->storage, [&](auto st) {
-    return vclb::batch_max_blocks_per_cu<decltype(st)>(bx, cap, lag, b->unit);
+    return vclb::batch_max_blocks_per_cu<decltype(st)>(bx, cap, lag, b->unit, b->visc);
   });
   int dev = 0, ncu = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -1414,6 +1415,7 @@ vclb::BatchArgs batch_args(const vclb_batch* b, int64_t t, int reduce) {
   a.cap = b->cap;
   a.lag = b->lag;
   a.unit = b->unit ? 1 : 0;
+  a.visc = b->visc ? 1 : 0;
   a.ticks = b->ticking ? b->d_ticks : nullptr;
   return a;
 }
@@ -1461,6 +1463,8 @@ extern "C" {
 int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out) {
   if (!cases || !out || ncases < 1) return fail(VCLB_EINVAL, "bad batch arguments");
   *out = nullptr;
+  bool any_visc = false;
+  for (int k = 0; k < ncases; ++k) any_visc = any_visc || visc_ratio(cases[k]);
   for (int k = 0; k < ncases; ++k) {
     int rc = validate(&cases[k]);
     if (rc) return fail(rc, "case " + std::to_string(k) + ": " + g_last_error);
@@ -1468,7 +1472,14 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
       return fail(VCLB_EINVAL, "batches hold coupled D2Q9 cases");
     if (cases[k].storage != cases[0].storage) return fail(VCLB_EINVAL, "every case of a batch has one storage");
     if (cases[k].nlabels > 1) return fail(VCLB_EINVAL, "batched cases have one observation label");
-    if (visc_ratio(cases[k])) return fail(VCLB_EINVAL, "batched cases have one viscosity (nu_heavy = nu_light)");
+    // with unequal viscosities in any case, every case relaxes its f stress rows at the
+    // per-node rate of Eq. 27 (its constant tau_f when its viscosities are equal)
+    if (any_visc)
+      for (int r = 0; r < 9; ++r)
+        if (vclb::D2Q9::f_stress_row[r] && cases[k].s_f[r] != 0.0)
+          return fail(VCLB_EINVAL, "case " + std::to_string(k) +
+                                       ": in a batch with unequal viscosities the f stress rates follow Eq. 27 per "
+                                       "node: leave them 0");
     if (cases[k].mass_fix > 0) return fail(VCLB_EINVAL, "batched cases take no global volume correction");
     if (double(cases[k].nx + 2) * (cases[k].ny + 2) >= double(1 << 24))
       return fail(VCLB_EINVAL, "batched cases hold fewer than 2^24 padded nodes");
@@ -1539,6 +1550,7 @@ int vclb_batch_create(const vclb_params* cases, int32_t ncases, vclb_batch** out
     for (int k = 0; k < ncases; ++k) {
       auto d = make_dev<vclb::D2Q9, St>(*b->cases[size_t(k)]);
       b->unit = b->unit && d.unit_rates != 0;
+      b->visc = b->visc || d.visc != 0;
       std::memcpy(table.data() + b->dcase_stride * size_t(k), &d, sizeof(d));
     }
     // the device reads entry k as cases[k]: check that indexing the table that way finds

@@ -52,7 +52,9 @@ constexpr int batch_min_blocks() {
   return waves / per_block > 0 ? waves / per_block : 1;
 }
 
-template <class St, int DL, int BS, bool UNIT>
+// VISC: some case of the batch has unequal viscosities (per-node tau_f, Eq. 27); the
+// others then take the same per-node form, which gives their constant tau_f
+template <class St, int DL, int BS, bool UNIT, bool VISC>
 __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS, UNIT>()))
     k_batch_step2d(const DevCase<D2Q9, St>* __restrict__ cases, BatchArgs a) {
   extern __shared__ unsigned char smem_raw[];
@@ -66,10 +68,11 @@ __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS, UNIT>()))
   for (int it = run.x; it < run.x + run.y; ++it) {
     const int4 w = a.items[it];
     if (w.y < 0)   // a band of whole rows, marched in padded row-major order
-      step2d_flat<St, DL, UNIT>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it, smem_raw);
+      step2d_flat<St, DL, UNIT, VISC>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it,
+                                      smem_raw);
     else           // a strip of columns [w.y, w.y + blockDim.x), one lane per column
-      step2d_tile<St, true, unsigned, UNIT>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems, it,
-                                            smem_raw);
+      step2d_tile<St, true, unsigned, UNIT, VISC>(cases[w.x], a.t, w.y, w.z, w.w, a.reduce != 0, a.part_w, a.nitems,
+                                                  it, smem_raw);
     __syncthreads();
   }
   // balancing launches record how long this slot took over its run (constant-rate clock)
@@ -88,16 +91,21 @@ size_t batch_lds_bytes(int cap, int bx) {
   return flat > rows ? flat : rows;
 }
 
-// the kernel instantiation for a launch shape (bx lanes, lag, unit rates); fn receives a
-// pointer to it.  1024-lane workgroups (4 waves per SIMD in one workgroup per CU) exist
-// for 4-byte arithmetic only: FP64 needs more than the 128 registers they leave a lane.
+// the kernel instantiation for a launch shape (bx lanes, lag, unit rates, unequal
+// viscosities); fn receives a pointer to it.  1024-lane workgroups (4 waves per SIMD in
+// one workgroup per CU) exist for 4-byte arithmetic only: FP64 needs more than the 128
+// registers they leave a lane.
 template <class St, class Fn>
-int with_batch_kernel(int bx, int lag, bool unit, Fn&& fn) {
+int with_batch_kernel(int bx, int lag, bool unit, bool visc, Fn&& fn) {
   if (lag != 1 && lag != 3) return -1;
   auto pick = [&](auto bs) -> int {
     constexpr int BS = decltype(bs)::value;
-    if (lag == 1) return unit ? fn(k_batch_step2d<St, 1, BS, true>) : fn(k_batch_step2d<St, 1, BS, false>);
-    return unit ? fn(k_batch_step2d<St, 3, BS, true>) : fn(k_batch_step2d<St, 3, BS, false>);
+    auto by_rates = [&](auto v) -> int {
+      constexpr bool V = decltype(v)::value;
+      if (lag == 1) return unit ? fn(k_batch_step2d<St, 1, BS, true, V>) : fn(k_batch_step2d<St, 1, BS, false, V>);
+      return unit ? fn(k_batch_step2d<St, 3, BS, true, V>) : fn(k_batch_step2d<St, 3, BS, false, V>);
+    };
+    return visc ? by_rates(std::true_type{}) : by_rates(std::false_type{});
   };
   if (bx > 512) {
     if constexpr (sizeof(typename St::R) == 4) return pick(std::integral_constant<int, 1024>{});
@@ -110,7 +118,7 @@ template <class St>
 int launch_batch_step(const void* cases, const BatchArgs& a, int blocks, int bx, hipStream_t s) {
   const size_t lds = batch_lds_bytes<St>(a.cap, bx);
   const auto* cs = static_cast<const DevCase<D2Q9, St>*>(cases);
-  const int rc = with_batch_kernel<St>(bx, a.lag, a.unit != 0, [&](auto kern) {
+  const int rc = with_batch_kernel<St>(bx, a.lag, a.unit != 0, a.visc != 0, [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(bx), lds, s, cs, a);
     return 0;
   });
@@ -126,10 +134,10 @@ int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s) {
 }
 
 template <class St>
-int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit) {
+int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit, bool visc) {
   int nb = 0;
   const size_t lds = batch_lds_bytes<St>(cap, bx);
-  const int rc = with_batch_kernel<St>(bx, lag, unit, [&](auto kern) {
+  const int rc = with_batch_kernel<St>(bx, lag, unit, visc, [&](auto kern) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, bx, lds) == hipSuccess ? 0 : -1;
   });
   return rc ? 0 : nb;
@@ -141,9 +149,9 @@ template int launch_batch_step<StoreF16S>(const void*, const BatchArgs&, int, in
 template int launch_batch_fold<StoreF64>(const void*, const BatchArgs&, hipStream_t);
 template int launch_batch_fold<StoreF32>(const void*, const BatchArgs&, hipStream_t);
 template int launch_batch_fold<StoreF16S>(const void*, const BatchArgs&, hipStream_t);
-template int batch_max_blocks_per_cu<StoreF64>(int, int, int, bool);
-template int batch_max_blocks_per_cu<StoreF32>(int, int, int, bool);
-template int batch_max_blocks_per_cu<StoreF16S>(int, int, int, bool);
+template int batch_max_blocks_per_cu<StoreF64>(int, int, int, bool, bool);
+template int batch_max_blocks_per_cu<StoreF32>(int, int, int, bool, bool);
+template int batch_max_blocks_per_cu<StoreF16S>(int, int, int, bool, bool);
 template size_t batch_lds_bytes<StoreF64>(int, int);
 template size_t batch_lds_bytes<StoreF32>(int, int);
 template size_t batch_lds_bytes<StoreF16S>(int, int);

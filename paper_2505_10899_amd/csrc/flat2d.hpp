@@ -78,8 +78,9 @@ __device__ __forceinline__ void pull9_flat(const typename St::S* const (&src)[9]
   }
 }
 
-// UNIT: the case's rates outside the g flux and f stress rows are all 1
-template <class St, int DL, bool UNIT>
+// UNIT: the case's rates outside the g flux and f stress rows are all 1; VISC: the f
+// stress rows relax at the node's own rate (unequal viscosities, Eq. 27)
+template <class St, int DL, bool UNIT, bool VISC = false>
 __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, int y0, int y1, bool reduce,
                                             int cap, double* __restrict__ part, long part_stride, long part_index,
                                             unsigned char* smem_raw) {
@@ -233,7 +234,7 @@ __device__ __forceinline__ void step2d_flat(const DevCase<D2Q9, St>& c, long t, 
         in.npsi[j] = v.psi;
       }
       NodeOut<L, R> out;
-      node_update_d2q9<R, true, St::shifted, UNIT>(c.np, in, e[SU], f, J, out);
+      node_update_d2q9<R, true, St::shifted, UNIT, VISC>(c.np, in, e[SU], f, J, out);
       R res = R(0);   // rounding of the stored g deviations, taken off the stored phi
 #pragma unroll
       for (int j = 0; j < Q; ++j) {

@@ -57,6 +57,7 @@ struct BatchArgs {
   int cap;                  // LDS ring entries of the flattened march (power of two)
   int lag;                  // its lag in chunks (1 or 3)
   int unit;                 // every case has unit rates outside the g flux and f stress rows
+  int visc;                 // some case has unequal viscosities (per-node tau_f)
   unsigned* ticks;          // if set: per run slot, the wall-clock ticks its workgroup spent
                             // on its run (balancing launches only)
 };
@@ -68,7 +69,7 @@ size_t batch_lds_bytes(int cap, int bx);
 template <class St>
 int launch_batch_fold(const void* cases, const BatchArgs& a, hipStream_t s);
 template <class St>
-int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit);
+int batch_max_blocks_per_cu(int bx, int cap, int lag, bool unit, bool visc);
 
 // Entries per plane of the populations and of J for a case of n nodes: n rounded up to a
 // multiple of 64, so that every plane starts on a cache line.

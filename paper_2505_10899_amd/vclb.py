@@ -132,7 +132,7 @@ SEED_FIELDS = 10
 NORMAL_TAU = 0.3   # the unit normal is differentiated where |grad psi| >= NORMAL_TAU
 
 
-VERSION = 20000   # VCLB_VERSION of include/vclb.h, whose struct layouts Params and Obs mirror
+VERSION = 20100   # VCLB_VERSION of include/vclb.h, whose struct layouts Params and Obs mirror
 
 
 def lib():

@@ -289,10 +289,16 @@ def test_viscosity_ratio_validation():
         assert e.value.code == v.VCLB_EINVAL, change
     # rates outside the stress rows stay free
     v.validate(p.replace(s_f=(0, 1.3, 0, 0, 0, 0, 0, 0, 0)))
-    # batches and the adjoint hold one viscosity; both refuse before touching HIP
-    arr = (v.Params * 2)(v.to_cparams(_valid()), v.to_cparams(p))
+    # a batch with unequal viscosities in one case relaxes every case's f stress rows per
+    # node, so a case beside it with a stress rate fixed by hand is refused (before HIP)
+    one = [(5.0, 5.0, 0.0)]   # batched cases have one observation label
+    fixed = _valid().replace(s_f=(0, 0, 0, 0, 0, 0, 0, 1.2, 1.2), label_centres=one)
+    v.validate(fixed)
+    arr = (v.Params * 2)(v.to_cparams(fixed), v.to_cparams(p.replace(label_centres=one)))
     h = ctypes.c_void_p()
     assert v.lib().vclb_batch_create(arr, 2, ctypes.byref(h)) == v.VCLB_EINVAL and not h.value
+    assert "stress" in v.lib().vclb_last_error().decode()
+    # the adjoint holds one viscosity
     nb = ctypes.c_size_t()
     assert v.lib().vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p)), 10, 2, ctypes.byref(nb)) == v.VCLB_EINVAL
 

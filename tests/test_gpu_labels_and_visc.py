@@ -7,7 +7,8 @@
 - unequal viscosities of the two phases (per-node tau_f, Eq. 27): one step from the
   oracle's exact state matches the oracle node by node (fused and plain paths, D2Q9 and
   D3Q19), and 1000 free FP64 steps of an off-node drop match it to 1e-12 on phi, rho, u;
-  the FP32 and FP16S storages keep the volume.
+  the FP32 and FP16S storages keep the volume; the batched step matches the oracle for
+  cases of different viscosity ratios side by side.
 """
 import sys
 
@@ -185,3 +186,46 @@ def test_viscosity_ratio_reduced_precision(lattice, storage):
     say(f"case: viscosity ratio {lattice} {storage}, {steps} steps: |dphi| {dphi:.2e}, |du| {du:.2e}, drift {drift:.2e}")
     tol = {"fp32": (1e-5, 1e-6, 1e-6), "fp16s": (2e-3, 1e-4, 1e-4)}[storage]
     assert dphi <= tol[0] and du <= tol[1] and drift <= tol[2]
+
+
+def _visc_batch_cases(storage="fp64"):
+    """Three cases of one batch: the walled shear drop with viscosity ratio 3.75, a periodic
+    drop with the light phase the more viscous (ratio 0.25), and a case of equal viscosities
+    (which the batch then relaxes with the per-node form too)."""
+    p1, phi1, u1 = _visc_case("d2q9", storage)
+    p2 = W.CaseParams(nx=52, ny=37, W=4.0, sigma=0.01, rho_light=0.2, nu=0.03, nu_light=0.12, storage=storage,
+                      label_centres=[(25.37, 18.21, 0.0)])
+    phi2 = W.drops_phi(p2, [(25.37, 18.21, 0.0, 8.0)])
+    p3 = W.CaseParams(nx=40, ny=29, W=4.0, sigma=0.01, rho_light=0.5, nu=0.1, storage=storage,
+                      label_centres=[(19.63, 14.29, 0.0)])
+    phi3 = W.drops_phi(p3, [(19.63, 14.29, 0.0, 6.0)])
+    return [(p1, phi1, u1), (p2, phi2, None), (p3, phi3, None)]
+
+
+@pytest.mark.parametrize("tile", [(64, 16, 0), (128, 1024, 101), (1024, 1024, 101)],
+                         ids=["strips", "bands", "bands1024"])
+def test_viscosity_ratio_batch_matches_the_oracle(tile):
+    """Batched cases with unequal (and, beside them, equal) viscosities: 200 FP64 steps of
+    the batched step match the oracle to 1e-12 on phi and u, in strips and in bands; FP32
+    in 1024-lane bands stays within 2e-5 of it."""
+    v = _v()
+    if tile[0] == 1024:
+        storage = "fp32"   # 1024-lane workgroups hold 4-byte arithmetic only
+    else:
+        storage = "fp64"
+    cases = _visc_batch_cases(storage)
+    b = v.Batch([p for p, _, _ in cases]).init([(phi0, u0) for _, phi0, u0 in cases])
+    b.set_tile(tile[0], tile[1])
+    b.set_schedule(tile[2])
+    steps = 200
+    b.step(steps)
+    tol = 1e-12 if storage == "fp64" else 2e-5
+    for k, (p, phi0, u0) in enumerate(cases):
+        m = Model(p.replace(storage="fp64")).init(phi0, u0)
+        m.step(steps)
+        F0 = m.fields()
+        F = b.cases[k].observe(v.FIELD_PHI | v.FIELD_U)
+        e = max(float(np.max(np.abs(F["phi"] - F0["phi"]))), float(np.max(np.abs(F["u"] - F0["u"]))))
+        ratio = p.nu / (p.nu_light or p.nu)
+        say(f"case: batch {tile} {storage}, case {k} viscosity ratio {ratio:.2f}: max-abs {e:.2e}")
+        assert e <= tol, (k, e)
