@@ -3,11 +3,12 @@
 // A fixed number of resident workgroups each take one run of consecutive work items,
 // the runs cut on the host so that every workgroup has about the same number of
 // iterations, or iterations in proportion to the speed its slot was measured at (items
-// are split between rows where a run ends).  An item is either a strip of columns marched row by row (step2d_tile, one lane per
-// column: best when the width is close to a multiple of the wave size) or a band of
-// whole rows marched in padded row-major order (step2d_flat: every lane busy for any
-// width, at some extra index arithmetic); the host picks per case.  The n launches of a call are captured in one hipGraph and
-// replayed as one launch.  Per-case volume reductions: every item writes its partial
+// are split between rows where a run ends).  An item is either a strip of columns marched
+// row by row (step2d_tile, one lane per column: best when the width is close to a
+// multiple of the wave size) or a band of whole rows marched in the case's stored
+// row-major order (step2d_flat: every lane busy for any width, every wave storing whole
+// cache lines); the host picks per case.  The n launches of a call are captured in one
+// hipGraph and replayed as one launch.  Per-case volume reductions: every item writes its partial
 // sums; the next launch (or a fold-only launch at the end of a call) sums each case's
 // items in a fixed order into that case's observation history.
 #include <hip/hip_runtime.h>
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(BS, (batch_min_blocks<St, DL, BS, UNIT>()))
   const unsigned long long t_begin = a.ticks ? wall_clock64() : 0ull;
   for (int it = run.x; it < run.x + run.y; ++it) {
     const int4 w = a.items[it];
-    if (w.y < 0)   // a band of whole rows, marched in padded row-major order
+    if (w.y < 0)   // a band of whole rows, marched in stored row-major order
       step2d_flat<St, DL, UNIT, VISC>(cases[w.x], a.t, w.z, w.w, a.reduce != 0, a.cap, a.part_w, a.nitems, it,
                                       smem_raw);
     else           // a strip of columns [w.y, w.y + blockDim.x), one lane per column
