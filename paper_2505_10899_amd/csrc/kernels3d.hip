@@ -336,17 +336,22 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     s0[k] = s1[k] = s2[k] = 0.0;
     cnt[k] = bad[k] = 0;
   }
+  // Segments march up (even bz) and down (odd bz) in turn, so that the two segments on
+  // either side of a cut reach it together, both first or both last: the planes each
+  // pulls across the cut are the other's own planes of the same moment, found in L2.
+  const int dir = (bz & 1) ? -1 : 1;
+  const int zs = dir > 0 ? z0 : z1 - 1, ze = dir > 0 ? z1 : z0 - 1;   // first plane, one past the last
   R gcur[Q], gnext[Q];
   if constexpr (STAGE) {
-    plane(z0 - 1, gnext);
-    stage_put(z0 - 1, gnext);
-    plane(z0, gnext);
-    stage_put(z0, gnext);
+    plane(zs - dir, gnext);
+    stage_put(zs - dir, gnext);
+    plane(zs, gnext);
+    stage_put(zs, gnext);
   } else {
-    plane(z0 - 1, gnext);
-    plane(z0, gcur);
+    plane(zs - dir, gnext);
+    plane(zs, gcur);
   }
-  for (int z = z0; z < z1; ++z) {
+  for (int z = zs; z != ze; z += dir) {
     // this plane's f and previous phi u are requested together with the next plane's
     // g, so that one memory round trip per plane covers both
     const Nbr3 o = nbr3(xw, yw, z, nx, ny, nz, nxy, wall);
@@ -357,8 +362,8 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
 #pragma unroll
       for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.ns, IX(nn));
     }
-    plane(z + 1, gnext);
-    if constexpr (STAGE) stage_put(z + 1, gnext);
+    plane(z + dir, gnext);
+    if constexpr (STAGE) stage_put(z + dir, gnext);
     __syncthreads();
     if (active) {
       if constexpr (STAGE) stage_get(z, gcur);
