@@ -108,7 +108,7 @@ typedef struct {
                                phi_g = phi_e + (4 / W) cos(theta) phi_e (1 - phi_e) of the
                                edge row's phi_e, and psi (Eq. 37) of phi_g.  0, the
                                default (theta = 90 degrees), makes the ghost the edge
-                               row's mirror.  Not supported by the adjoint.              */
+                               row's mirror.                                             */
   double  W;                /* interface width (Eq. 4), > 0                                 */
   double  sigma;            /* surface tension, >= 0 (beta = 12 sigma / W, kappa = 3 sigma W / 2) */
   double  mobility;         /* M > 0; tau_g = 1/2 + M / c_s^2 (Eq. 34)                      */
@@ -327,7 +327,8 @@ int vclb_obs_seed(const vclb_obs* obs, int32_t nlabels, const double* weights, d
    adjoint of the time step: the reverse of the streaming (with bounce-back and the
    moving-wall term), of the collisions Eqs. 25 and 33 with their equilibria and sources
    (Eqs. 21-23, 31-32), of u and p (Eqs. 28-29), mu (Eq. 2), psi (Eq. 37) and the
-   stencils Eqs. 39-40, and of the initial state.  FP64 D2Q9 coupled cases only
+   stencils Eqs. 39-40 (with the wetting ghosts behind walls), and of the initial state.
+   FP64 D2Q9 coupled cases of one viscosity without the global correction only
    (VCLB_EINVAL otherwise).  The derivative of the clip of phi to [0, 1] is taken as 1
    inside the interval and 0 outside.
 

@@ -2083,8 +2083,6 @@ int adj_check_case(const vclb_case* c) {
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
   if (visc_ratio(c->p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
   if (c->p.mass_fix > 0) return fail(VCLB_EINVAL, "the adjoint covers cases without the global volume correction");
-  for (int sd = 0; sd < 2; ++sd)
-    if (c->p.wall_cos[1][sd] != 0.0) return fail(VCLB_EINVAL, "the adjoint covers neutral walls (wall_cos = 0)");
   return VCLB_OK;
 }
 

@@ -13,7 +13,8 @@
 //                  and the adjoints of what the node read through stencils: its own phi,
 //                  the Laplacian and gradient of phi and the gradient of psi (Eqs. 39-40).
 //                  Accumulates dJ/dsigma and dJ/dM per workgroup.
-//   k_adj_stencil  per node y: the transposed stencils (walls mirror the edge row),
+//   k_adj_stencil  per node y: the transposed stencils (behind a wall, the ghost row is
+//                  the wetting ghost of the edge row: its slope joins the chain),
 //                  dpsi/dphi from Eq. 37, giving lphi of step t.
 // Away from the interface psi saturates and |grad psi| falls to rounding level; the
 // derivative of the unit normal there has a gain of order lambda / |grad psi| per step
@@ -73,8 +74,10 @@ __device__ __forceinline__ void add_params(const AdjArgs& a, double sig, double 
   if (threadIdx.x < 2) a.param_part[long(threadIdx.x) * gridDim.x + blockIdx.x] += s;
 }
 
-// sum over the stencil readers m of node (x, y), m + c_i = (x, y), with the row behind a
-// wall read as the edge row
+// sum over the stencil readers m of node (x, y), m + c_i = (x, y): fn(i, m, side), with
+// side 0 for a reader of the node itself and -1 / +1 for a reader of the ghost row behind
+// the bottom / top wall, which holds the wetting ghost of this edge node (its mirror for
+// a neutral wall)
 template <class Fn>
 __device__ __forceinline__ void stencil_readers(const DC& c, int x, int y, Fn&& fn) {
   const int nx = c.nx, ny = c.ny;
@@ -82,11 +85,24 @@ __device__ __forceinline__ void stencil_readers(const DC& c, int x, int y, Fn&& 
   for (int i = 1; i < 9; ++i) {
     const int xs = xwrap(x - D2Q9::cx[i], nx);
     const int ys = y - D2Q9::cy[i];
-    if (ys >= 0 && ys < ny) fn(i, xs + long(nx) * ys);
-    else if (!c.wall) fn(i, xs + long(nx) * (ys < 0 ? ys + ny : ys - ny));
-    if (c.wall && y == 0 && D2Q9::cy[i] < 0) fn(i, xs + long(nx) * y);
-    if (c.wall && y == ny - 1 && D2Q9::cy[i] > 0) fn(i, xs + long(nx) * y);
+    if (ys >= 0 && ys < ny) fn(i, xs + long(nx) * ys, 0);
+    else if (!c.wall) fn(i, xs + long(nx) * (ys < 0 ? ys + ny : ys - ny), 0);
+    if (c.wall && y == 0 && D2Q9::cy[i] < 0) fn(i, xs + long(nx) * y, -1);
+    if (c.wall && y == ny - 1 && D2Q9::cy[i] > 0) fn(i, xs + long(nx) * y, 1);
   }
+}
+
+// the wetting-ghost coefficient of the wall on this side: phi_g = phi_e + w phi_e (1 - phi_e)
+__device__ __forceinline__ R wet_coef(const DC& c, int side) { return side < 0 ? c.np.wet_lo : c.np.wet_hi; }
+
+// d(phi_g)/d(phi_e) of the wetting ghost
+__device__ __forceinline__ R wet_slope(R w, R phi) { return R(1) + w * (R(1) - R(2) * phi); }
+
+// dpsi/dphi of Eq. 37 on the clipped range (zero where the clip holds psi fixed)
+__device__ __forceinline__ R dpsi_dphi(const DC& c, R phi) {
+  if (!(phi >= R(0) && phi <= R(1))) return R(0);
+  const R aa = phi + c.np.xi, bb = (R(1) - phi) + c.np.xi;
+  return c.np.W4 * (R(1) / aa + R(1) / bb);
 }
 
 }  // namespace
@@ -132,8 +148,15 @@ __global__ void __launch_bounds__(256) k_adj_local(DC c, AdjArgs a) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const long m = xwrap(x + D2Q9::cx[i], nx) + long(nx) * stencil_row(y, D2Q9::cy[i], ny, wall);
-      q[i] = c.tmp_phi[m];
-      s[i] = c.tmp_psi[m];
+      const int yn = y + D2Q9::cy[i];
+      const int side = wall ? (yn < 0 ? -1 : (yn >= ny ? 1 : 0)) : 0;
+      if (side) {   // the ghost row behind a wall: the wetting ghost of the edge row
+        q[i] = wet_ghost<R>(c.tmp_phi[m], wet_coef(c, side));
+        s[i] = psi_of<R>(q[i], p.W4, p.xi);
+      } else {
+        q[i] = c.tmp_phi[m];
+        s[i] = c.tmp_psi[m];
+      }
     }
     R g[9], f[9];
     pull<D2Q9, StoreF64>(c, c.pop[0][0], nullptr, x, y, 0, g, nullptr);
@@ -320,15 +343,27 @@ __global__ void __launch_bounds__(256) k_adj_stencil(DC c, AdjArgs a) {
   // own node: the centre weight of the Laplacian, -sum_i 6 w_i = -6 (1 - w_0)
   R lphi = lph[n] + R(-6.0 * (1.0 - D2Q9::w[0])) * llap[n];
   R lpsi = R(0);
-  stencil_readers(c, x, y, [&](int i, long m) {
+  R gphi[2] = {R(0), R(0)}, gpsi[2] = {R(0), R(0)};   // through the ghost rows (bottom, top)
+  stencil_readers(c, x, y, [&](int i, long m, int side) {
     const R ax = R(3.0 * D2Q9::w[i] * D2Q9::cx[i]), ay = R(3.0 * D2Q9::w[i] * D2Q9::cy[i]);
-    lphi += ax * lgpx[m] + ay * lgpy[m] + R(6.0 * D2Q9::w[i]) * llap[m];
-    lpsi += ax * lgsx[m] + ay * lgsy[m];
+    const R dphi = ax * lgpx[m] + ay * lgpy[m] + R(6.0 * D2Q9::w[i]) * llap[m];
+    const R dpsi = ax * lgsx[m] + ay * lgsy[m];
+    if (side == 0) {
+      lphi += dphi;
+      lpsi += dpsi;
+    } else {
+      gphi[side > 0] += dphi;
+      gpsi[side > 0] += dpsi;
+    }
   });
   const R phi = c.tmp_phi[n];
-  if (phi >= R(0) && phi <= R(1)) {
-    const R aa = phi + c.np.xi, bb = (R(1) - phi) + c.np.xi;
-    lphi += lpsi * c.np.W4 * (R(1) / aa + R(1) / bb);   // dpsi/dphi of Eq. 37
+  lphi += lpsi * dpsi_dphi(c, phi);
+  // the ghost value phi_g (and psi of it) depends on this edge node's phi
+  for (int k = 0; k < 2; ++k) {
+    if (gphi[k] == R(0) && gpsi[k] == R(0)) continue;
+    const R w = wet_coef(c, k ? 1 : -1);
+    const R phig = wet_ghost<R>(phi, w);
+    lphi += wet_slope(w, phi) * (gphi[k] + gpsi[k] * dpsi_dphi(c, phig));
   }
   a.lphi[n] = lphi;
 }
@@ -346,8 +381,11 @@ __global__ void __launch_bounds__(256) k_adj_init_local(DC c, AdjArgs a, const d
     const auto& p = c.np;
     R q[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < 9; ++i) {
       q[i] = phi0[xwrap(x + D2Q9::cx[i], nx) + long(nx) * stencil_row(y, D2Q9::cy[i], ny, c.wall)];
+      const int yn = y + D2Q9::cy[i];
+      if (c.wall && (yn < 0 || yn >= ny)) q[i] = wet_ghost<R>(q[i], wet_coef(c, yn < 0 ? -1 : 1));
+    }
     const R phi = q[0];
     const R lap = R(2.0 / 3.0) * (((q[1] + q[3]) + (q[2] + q[4])) - R(4) * q[0]) +
                   R(1.0 / 6.0) * (((q[5] + q[7]) + (q[6] + q[8])) - R(4) * q[0]);
@@ -382,13 +420,17 @@ __global__ void __launch_bounds__(256) k_adj_init_local(DC c, AdjArgs a, const d
   add_params(a, acc_sig, 0.0);
 }
 
-__global__ void __launch_bounds__(256) k_adj_init_stencil(DC c, AdjArgs a, double* __restrict__ dphi0) {
+__global__ void __launch_bounds__(256) k_adj_init_stencil(DC c, AdjArgs a, const double* __restrict__ phi0,
+                                                          double* __restrict__ dphi0) {
   const long n = blockIdx.x * long(blockDim.x) + threadIdx.x;
   if (n >= c.n) return;
   const int x = int(n % c.nx), y = int(n / c.nx);
   const double* llap = a.aux + c.n;
   R v = a.aux[n] + R(-6.0 * (1.0 - D2Q9::w[0])) * llap[n];
-  stencil_readers(c, x, y, [&](int i, long m) { v += R(6.0 * D2Q9::w[i]) * llap[m]; });
+  stencil_readers(c, x, y, [&](int i, long m, int side) {
+    const R t = R(6.0 * D2Q9::w[i]) * llap[m];
+    v += side ? wet_slope(wet_coef(c, side), phi0[n]) * t : t;   // a ghost read: d(phi_g)/d(phi_e)
+  });
   dphi0[n] = v;
 }
 
@@ -436,7 +478,7 @@ int launch_adj_step(const DC& c, const AdjArgs& a, hipStream_t s) {
 int launch_adj_init(const DC& c, const AdjArgs& a, const double* phi0, const double* u0, double* dphi0,
                     hipStream_t s) {
   hipLaunchKernelGGL(k_adj_init_local, dim3(blocks_for(c.n)), dim3(256), 0, s, c, a, phi0, u0);
-  hipLaunchKernelGGL(k_adj_init_stencil, dim3(blocks_for(c.n)), dim3(256), 0, s, c, a, dphi0);
+  hipLaunchKernelGGL(k_adj_init_stencil, dim3(blocks_for(c.n)), dim3(256), 0, s, c, a, phi0, dphi0);
   return last_status();
 }
 

@@ -6,7 +6,8 @@ the exact values conservation fixes (d sum(phi) / d phi0 = 1 at every node, zero
 derivative with respect to sigma and M).  phi0 directions are r 4 phi0 (1 - phi0) with
 r standard normal from PCG64(1): changes that stay off the clipped bulk, where the map
 has a kink.  Both sides differentiate the unit normal only where |grad psi| >= 0.3
-(the default cut; tau = 0 is the exact derivative, checked on the small case).
+(the default cut; tau = 0 is the exact derivative, checked on the small case).  The
+cases include walls with wetting ghosts (a sessile drop).
 """
 import sys
 
@@ -39,7 +40,15 @@ def _drops():
     return "drops64x48", p, phi0, None, 60, 0
 
 
-CASES = [_shear, _drops]
+def _wetting():
+    """A drop on the bottom wall of a 64 x 32 channel, walls moving -+0.01 and wetting at
+    contact angles acos(0.5) and acos(-0.3): the wetting ghosts enter the derivative."""
+    from test_oracle_gradient import _sessile
+    p, phi0, u0, n = _sessile()
+    return "sessile64x32", p, phi0, u0, n, 10
+
+
+CASES = [_shear, _drops, _wetting]
 
 
 def _direction(phi0, k=0):

@@ -7,8 +7,8 @@ behind it; the paper states no boundary conditions, so the condition is a readin
   rho and u, fused and plain;
 - the batched step (strips and bands) gives the oracle's state for cases of different
   angles;
-- FP32 and FP16S storage stay close to the FP64 oracle and keep the total of phi;
-- the adjoint refuses wetting walls.
+- FP32 and FP16S storage stay close to the FP64 oracle and keep the total of phi.
+The adjoint through wetting walls is checked in test_gpu_adjoint.py.
 """
 import sys
 
@@ -122,12 +122,3 @@ def test_wetting_reduced_precision(storage):
     say(f"case: wetting walls {storage}, {steps} steps: |dphi| {dphi:.2e}, |du| {du:.2e}, drift {drift:.2e}")
     tol = {"fp32": (2e-5, 2e-6, 1e-6), "fp16s": (3e-3, 3e-4, 1e-5)}[storage]
     assert dphi <= tol[0] and du <= tol[1] and drift <= tol[2]
-
-
-def test_adjoint_refuses_wetting_walls():
-    v = _v()
-    p, phi0, u0 = _sessile()
-    c = v.Case(p)
-    with pytest.raises(v.VclbError) as e:
-        c.adjoint_record(phi0, u0, nsteps=10, every=0)
-    assert e.value.code == v.VCLB_EINVAL

@@ -21,6 +21,19 @@ def _drops():
     return p, phi0, None, 60
 
 
+def _sessile():
+    """A drop on the bottom wall of a 64 x 32 channel whose walls move -+0.01 and wet at
+    contact angles acos(0.5) (bottom) and acos(-0.3) (top): the interface meets the wall,
+    so the wetting ghosts enter the map."""
+    p = W.CaseParams(nx=64, ny=32, wall_y=True, wall_u_bottom=(-0.01, 0.0, 0.0), wall_u_top=(0.01, 0.0, 0.0),
+                     wall_cos_bottom=0.5, wall_cos_top=-0.3, rho_light=0.5, sigma=0.01, nu=0.1,
+                     label_centres=[(32.37, 2.0, 0.0)])
+    x = np.arange(p.nx)[None, None, :]
+    y = np.arange(p.ny)[None, :, None]
+    d = 10.0 - np.sqrt((x - 32.37) ** 2 + (y + 0.5 - 1.13) ** 2)
+    return p, 0.5 * (1.0 + np.tanh(2.0 * d / p.W)) * np.ones((1, p.ny, p.nx)), None, 80
+
+
 def _direction(phi0, seed=1):
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal(phi0.shape) * 4.0 * phi0 * (1.0 - phi0)
@@ -47,7 +60,23 @@ def test_complex_step_matches_central_difference_phi0():
         assert abs(fd[0, k] - cs[0, k]) <= 1e-6 * abs(cs[0, k]), (k, fd[0, k], cs[0, k])
 
 
-@pytest.mark.parametrize("case", [_shear, _drops])
+def test_complex_step_matches_central_difference_wetting_walls():
+    """The wetting ghost is a polynomial of the edge phi, so the complex step stays exact:
+    against central differences on the sessile drop, for sigma, M and a phi0 direction
+    (the exact derivative, tau = 0, which the differences approximate).  This map is more
+    curved than the shear case's, so the differences take smaller steps (their error
+    falls as the step squared, to 1e-8 relative at these steps)."""
+    p, phi0, u0, n = _sessile()
+    d = _direction(phi0)
+    for wrt, eps in (("sigma", 1e-6 * p.sigma), ("mobility", 1e-5 * p.mobility), ("phi0", 1e-6)):
+        cs = G.complex_step(p, phi0, u0, n, wrt, direction=d, tau=0.0)
+        fd = G.central_difference(p, phi0, u0, n, wrt, eps, direction=d)
+        for k in (1, 2, 4):                # centroid x, y, D
+            assert abs(cs[0, k]) > 1e-4, (wrt, k)
+            assert abs(fd[0, k] - cs[0, k]) <= 1e-6 * abs(cs[0, k]), (wrt, k, fd[0, k], cs[0, k])
+
+
+@pytest.mark.parametrize("case", [_shear, _drops, _sessile])
 def test_total_phi_gradients_fixed_by_conservation(case):
     p, phi0, u0, n = case()
     total = lambda v: v[:, 0].sum()
