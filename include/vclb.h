@@ -135,9 +135,9 @@ typedef struct {
                                between rho_light nu_light and rho_heavy nu_heavy, and each
                                node relaxes the stress moments of f at 1 / tau_f with
                                tau_f = 1/2 + mu(phi) / (rho(phi) c_s^2) (Eq. 27).  Equal
-                               viscosities give one uniform tau_f.  Unequal ones are
-                               supported by the single-case steps (not by batches or the
-                               adjoint) and need the stress rates of s_f left at 0.       */
+                               viscosities give one uniform tau_f.  Unequal ones need the
+                               stress rates of s_f left at 0; every step, batches and the
+                               adjoint support them.                                      */
   double  s_g[19];          /* MRT rates of g in (0, 2); 0 selects the default              */
   double  s_f[19];          /* MRT rates of f in (0, 2); 0 selects the default              */
   double  U0;               /* vortex amplitude (Eqs. 43-44)                                 */
@@ -328,8 +328,8 @@ int vclb_obs_seed(const vclb_obs* obs, int32_t nlabels, const double* weights, d
    moving-wall term), of the collisions Eqs. 25 and 33 with their equilibria and sources
    (Eqs. 21-23, 31-32), of u and p (Eqs. 28-29), mu (Eq. 2), psi (Eq. 37) and the
    stencils Eqs. 39-40 (with the wetting ghosts behind walls), and of the initial state.
-   FP64 D2Q9 coupled cases of one viscosity without the global correction only
-   (VCLB_EINVAL otherwise).  The derivative of the clip of phi to [0, 1] is taken as 1
+   With unequal viscosities the per-node stress rate (Eq. 27) is differentiated too.  FP64
+   D2Q9 coupled cases without the global correction only (VCLB_EINVAL otherwise).  The derivative of the clip of phi to [0, 1] is taken as 1
    inside the interval and 0 outside.
 
    Device bytes of the checkpoint store and adjoint fields (no HIP call); every = 0

@@ -2081,7 +2081,6 @@ AdjStore adj_layout(const vclb_params& p, int64_t nsteps, int32_t every) {
 int adj_check_case(const vclb_case* c) {
   if (c->p.lattice != VCLB_D2Q9 || c->p.storage != VCLB_FP64 || c->p.mode != VCLB_COUPLED)
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
-  if (visc_ratio(c->p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
   if (c->p.mass_fix > 0) return fail(VCLB_EINVAL, "the adjoint covers cases without the global volume correction");
   return VCLB_OK;
 }
@@ -2153,7 +2152,6 @@ int vclb_adjoint_bytes(const vclb_params* p, int64_t nsteps, int32_t every, size
   if (!bytes || nsteps < 0 || every < 0) return fail(VCLB_EINVAL, "bad argument");
   if (p->lattice != VCLB_D2Q9 || p->storage != VCLB_FP64 || p->mode != VCLB_COUPLED)
     return fail(VCLB_EINVAL, "the adjoint covers FP64 D2Q9 coupled cases");
-  if (visc_ratio(*p)) return fail(VCLB_EINVAL, "the adjoint covers cases of one viscosity (nu_heavy = nu_light)");
   if (p->mass_fix > 0) return fail(VCLB_EINVAL, "the adjoint covers cases without the global volume correction");
   if (every == 0) every = adj_default_every(nsteps);
   *bytes = adj_layout(*p, nsteps, every).total;

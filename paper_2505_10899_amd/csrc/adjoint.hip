@@ -220,16 +220,31 @@ __global__ void __launch_bounds__(256) k_adj_local(DC c, AdjArgs a) {
 
     // ---- f collision (Eq. 25) in reverse: f* = M^-1 [(1 - s) m + s m_eq + (1 - s/2) m_F],
     // M^-T = diag(1/|M_k|^2) M
+    // With unequal viscosities the stress rows relax at the node's own rate
+    // s = 1 / (1/2 + 3 mu / rho) (Eq. 27), mu = mu_l + phi dmu: their adjoint also reaches
+    // phi and rho through s, with dm*_k/ds = m_eq,k - m_k - m_F,k / 2.
+    const bool visc = c.visc != 0;
+    const R irho = R(1) / rho;
+    const R s_st = visc ? stress_rate<D2Q9, R>(p, phi, irho) : R(0);
+    const R meq_st[2] = {rho * (ux * ux - uy * uy), rho * ux * uy};
+    const R mF_st[2] = {R(2.0 / 3.0) * (ux * grx - uy * gry), R(1.0 / 3.0) * (ux * gry + uy * grx)};
+    R ls_st = R(0);   // adjoint of s
     R lmf[9];
     d2q9_moments<R>(lfs, lmf);
     R lfm[9], leqf[9], lsrcf[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       const R lms = lmf[k] / R(row_norm<D2Q9>(k));
-      lfm[k] = (R(1) - p.sfr[k]) * lms;
-      leqf[k] = p.sfr[k] * lms;
-      lsrcf[k] = (R(1) - R(0.5) * p.sfr[k]) * lms;
+      const bool st = visc && D2Q9::f_stress_row[k];
+      const R sk = st ? s_st : p.sfr[k];
+      lfm[k] = (R(1) - sk) * lms;
+      leqf[k] = sk * lms;
+      lsrcf[k] = (R(1) - R(0.5) * sk) * lms;
+      if (st) ls_st += lms * (meq_st[k - 7] - fm[k] - R(0.5) * mF_st[k - 7]);
     }
+    // s = 1 / (1/2 + 3 mu / rho): ds/dphi = -3 s^2 dmu / rho (through mu), ds/drho = 3 s^2 mu / rho^2
+    const R lphi_st = visc ? ls_st * (R(-3) * s_st * s_st * p.dmu * irho) : R(0);
+    if (visc) lrho += ls_st * (R(3) * s_st * s_st * (p.mu_l + phi * p.dmu) * irho * irho);
     // equilibrium moments (0, 6p + 3 rho uu, -9p - 3 rho uu, rho ux, -rho ux, rho uy, -rho uy,
     // rho (ux^2 - uy^2), rho ux uy)
     const R lpress = R(6) * leqf[1] - R(9) * leqf[2];
@@ -261,7 +276,7 @@ __global__ void __launch_bounds__(256) k_adj_local(DC c, AdjArgs a) {
       if ((a.mobility_rows >> k) & 1) acc_mob += lms * (geq[k] - gm[k] - R(0.5) * gsrc[k]) * (R(-3) * sk * sk);
     }
     const R lH = R(2) * leqg[1] - R(3) * leqg[2];
-    R lphi = leqg[0] - R(4) * leqg[1] + R(4) * leqg[2] + p.lam * lH;
+    R lphi = leqg[0] - R(4) * leqg[1] + R(4) * leqg[2] + p.lam * lH + lphi_st;
     R lmu = lH;
     R lJx = leqg[3] - leqg[4], lJy = leqg[5] - leqg[6];
     const R lVx = (lsrcg[3] - lsrcg[4]) * R(1.0 / 3.0), lVy = (lsrcg[5] - lsrcg[6]) * R(1.0 / 3.0);

@@ -298,9 +298,9 @@ def test_viscosity_ratio_validation():
     h = ctypes.c_void_p()
     assert v.lib().vclb_batch_create(arr, 2, ctypes.byref(h)) == v.VCLB_EINVAL and not h.value
     assert "stress" in v.lib().vclb_last_error().decode()
-    # the adjoint holds one viscosity
+    # the adjoint takes unequal viscosities too (its store size needs no HIP call)
     nb = ctypes.c_size_t()
-    assert v.lib().vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p)), 10, 2, ctypes.byref(nb)) == v.VCLB_EINVAL
+    assert v.lib().vclb_adjoint_bytes(ctypes.byref(v.to_cparams(p)), 10, 2, ctypes.byref(nb)) == 0 and nb.value > 0
 
 
 def test_global_correction_validation():

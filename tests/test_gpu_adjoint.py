@@ -7,7 +7,7 @@ derivative with respect to sigma and M).  phi0 directions are r 4 phi0 (1 - phi0
 r standard normal from PCG64(1): changes that stay off the clipped bulk, where the map
 has a kink.  Both sides differentiate the unit normal only where |grad psi| >= 0.3
 (the default cut; tau = 0 is the exact derivative, checked on the small case).  The
-cases include walls with wetting ghosts (a sessile drop).
+cases include walls with wetting ghosts (a sessile drop) and unequal viscosities.
 """
 import sys
 
@@ -48,7 +48,15 @@ def _wetting():
     return "sessile64x32", p, phi0, u0, n, 10
 
 
-CASES = [_shear, _drops, _wetting]
+def _visc():
+    """The 66 x 24 walled shear drop with unequal viscosities (ratio 3.75): the per-node
+    stress rate of f (Eq. 27) enters the derivative."""
+    from test_oracle_gradient import _visc as visc_case
+    p, phi0, u0, n = visc_case()
+    return "visc66x24", p, phi0, u0, n, 10
+
+
+CASES = [_shear, _drops, _wetting, _visc]
 
 
 def _direction(phi0, k=0):
