@@ -215,6 +215,37 @@ def test_batch_1024_lanes_with_wide_and_tiny_cases(flat_pct):
         assert err == 0.0, k        # the same node arithmetic in both marches: bit for bit
 
 
+@pytest.mark.parametrize("storage,bx", [("fp32", 1024), ("fp64", 512)])
+def test_band_lag_and_ring_boundaries(storage, bx):
+    """Widths at the band march's limits for bx lanes: the one-chunk lag holds up to
+    nx + 1 = bx (bx - 1 columns), one more column needs the three-chunk lag; the ring grows
+    past 4096 entries at 512 columns with 1024 lanes; narrow rows cross many row starts
+    per chunk.  Every case, marched in bands beside the others (flat_pct 101), equals the
+    same case stepped alone in strips bit for bit."""
+    v = _v()
+    widths = [bx - 1, bx, bx + 1, bx // 2 - 1, bx // 2, 65, 64, 63, 5]
+    cases = []
+    for k, nx in enumerate(widths):
+        ny = 5 + k % 3
+        wall = k % 2 == 1
+        p = W.CaseParams(nx=nx, ny=ny, rho_light=0.25, wall_y=wall, storage=storage,
+                         wall_u_bottom=(-0.02, 0.0, 0.0) if wall else (0.0, 0.0, 0.0),
+                         wall_u_top=(0.02, 0.0, 0.0) if wall else (0.0, 0.0, 0.0))
+        cx, cy = nx * 0.37 + 0.21, ny * 0.5 + 0.13
+        cases.append((p, W.drops_phi(p, [(cx, cy, 0.0, max(1.5, 0.4 * min(nx, ny)))]), None))
+    say("case: band lag and ring boundaries", storage, bx, widths)
+    b = v.Batch([p for p, _, _ in cases]).init([(phi0, u0) for _, phi0, u0 in cases])
+    b.set_tile(bx, 1024)
+    b.set_schedule(101)
+    b.step(10)
+    for k, (p, phi0, u0) in enumerate(cases):
+        alone = v.Case(p, tile=(64, 16)).init(phi0, u0)
+        alone.step(10)
+        err = max(np.max(np.abs(a_ - b_)) for a_, b_ in zip(alone.get_state(), b.cases[k].get_state()))
+        say(f"  case {k} {p.nx}x{p.ny}: max |batch - alone| = {err:.3e}")
+        assert err == 0.0, k
+
+
 def test_batch_rejects_1024_lanes_in_fp64():
     v = _v()
     b = v.Batch([p for p, _, _ in small_batch("fp64", n=2)])
