@@ -55,15 +55,78 @@ __device__ __forceinline__ int pull_index(const Nbr3& o) {
   return s;
 }
 
+// Buffer-resource access, for periodic cases whose arrays each span less than 2 GiB: one
+// resource per array (uniform), the plane's byte offset as the scalar offset (the same
+// scalar for every array of equal plane stride) and the node's byte offset as the vector
+// offset, so that an access needs one 32-bit offset per lane and no 64-bit address.
+struct Bufs3 {
+  __amdgpu_buffer_rsrc_t g, f, phis, gd, fd, phisd, J;   // read: g, f, phis; written: gd, fd, phisd; J both
+  int pb;   // bytes per population plane (ns entries of the stored type)
+  int jb;   // bytes per plane of J
+};
+// fourth word of a raw (unswizzled, unstrided) buffer resource on gfx9-family GPUs:
+// 32-bit data format, every destination selector zero
+constexpr int kRawBufferWord3 = 0x00020000;
+
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const T* p, long entries) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), short(0), int(entries * long(sizeof(T))),
+                                           kRawBufferWord3);
+}
+template <class T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <class T>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, T v) {
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  else {
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, voff, soff, 0);
+  }
+}
+// a population in the storage's form: decoded to / encoded from the arithmetic type
+template <class St>
+__device__ __forceinline__ typename St::R buf_load_pop(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  if constexpr (sizeof(typename St::S) == 2)
+    return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+  else return buf_ld<typename St::S>(r, voff, soff);
+}
+template <class St>
+__device__ __forceinline__ void buf_store_pop(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff,
+                                              typename St::R v) {
+  if constexpr (sizeof(typename St::S) == 2)
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, 0);
+  else buf_st<typename St::S>(r, voff, soff, typename St::S(v));
+}
+
 // The 19 pulls at one node: 32-bit node offsets from the uniform base of each
 // direction's plane (planes of ns entries; the case has fewer than 2^31 nodes), accessed with index type IX
 // (unsigned: 32-bit byte offsets, when n times the element size fits them).  ps (shifted
 // storage): the phi the stored deviations refer to, this node's own phis entry.
-template <class St, class IX>
+// BUF: through the buffer resources rs (the set) and rph (phis), planes pb bytes apart;
+// periodic cases only (no pull is redirected at a wall).
+template <class St, class IX, bool BUF>
 __device__ __forceinline__ void pull19(const typename St::S* __restrict__ src, const float* __restrict__ phis,
-                                       long ns, const Nbr3& o, typename St::R (&out)[19], typename St::R* ps) {
+                                       long ns, __amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rph, int pb,
+                                       const Nbr3& o, typename St::R (&out)[19], typename St::R* ps) {
   using L = D3Q19;
   using R = typename St::R;
+  if constexpr (BUF) {
+    static_for<0, L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      out[i] = buf_load_pop<St>(rs, unsigned(pull_index<i>(o)) * unsigned(sizeof(typename St::S)), i * pb);
+    });
+    if constexpr (St::shifted) {
+      if (ps) {
+        const R own = R(buf_ld<float>(rph, unsigned(o.s0) * 4u, 0));
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) ps[i] = own;
+      }
+    }
+    return;
+  }
   static_for<0, L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     int s = pull_index<i>(o);
@@ -111,6 +174,19 @@ template <class St>
 constexpr bool periodic3d_kernel() {
   return !std::is_same<St, StoreF32>::value;
 }
+// Periodic kernels with buffer-resource access (32-bit offsets, scalar plane offsets)
+template <class St>
+constexpr bool buf3d_kernel() {
+  return std::is_same<St, StoreF16S>::value;
+}
+// every array of the case spans less than 2 GiB (the byte offsets and sizes of a buffer
+// resource are 32-bit)
+template <class St>
+bool buf3d_fits(const DevCase<D3Q19, St>& c) {
+  const long lim = (1L << 31) - 1;
+  return long(D3Q19::Q) * c.ns * long(sizeof(typename St::S)) <= lim &&
+         long(D3Q19::D) * c.ns * long(sizeof(typename St::R)) <= lim && c.ns * 4 <= lim;
+}
 
 // phi and psi of a node side by side: one 2-word LDS access per stencil point
 template <class R>
@@ -125,8 +201,9 @@ __device__ __forceinline__ int ring_slot3d(int z) { return (z + 4) & 3; }
 // deviations from the node's own rest state for shifted storage), f and the previous
 // phi u in registers, phi and psi of the 18 neighbours in the ring of PS = PW x (BY + 2)
 // nodes per plane.  Stores the post-collision state and accumulates the reductions.
-template <class St, int NL, bool UNIT, bool VISC, bool WALL, class IX>
-__device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const PhiPsi3<typename St::R>* sring,
+template <class St, int NL, bool UNIT, bool VISC, bool WALL, class IX, bool BUF>
+__device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const Bufs3& bf,
+                                              const PhiPsi3<typename St::R>* sring,
                                               int PS, int PW, int tx, int ty, int xw, int yw, int z, int nn, int par,
                                               typename St::R (&gcur)[19], typename St::R (&f)[19],
                                               typename St::R (&J)[3], bool reduce, double (&s0)[NL], double (&s1)[NL],
@@ -164,7 +241,8 @@ __device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const
       d = encode_dev(gcur[i], c.np.rest[i], st.phi,
                      leaves_through_wall<L>(i, yw, c.ny, wall) ? st.phi : sring[sr].phi);
     }
-    St::store(c.pop[0][dst] + i * c.ns, IX(nn), d);
+    if constexpr (BUF) buf_store_pop<St>(bf.gd, unsigned(nn) * unsigned(sizeof(typename St::S)), i * bf.pb, d);
+    else St::store(c.pop[0][dst] + i * c.ns, IX(nn), d);
     if constexpr (St::fold) res += St::rounding(d);
   }
   if (wall && yw == 0) {   // moving-wall term of the populations the bottom wall returns
@@ -177,11 +255,20 @@ __device__ __forceinline__ void update_node3d(const DevCase<D3Q19, St>& c, const
     for (int i = 0; i < Q; ++i)
       if (L::cy[i] > 0) f[i] += c.np.wt[i] * out.rho;
   }
+  if constexpr (BUF) {
+    const unsigned vo = unsigned(nn) * unsigned(sizeof(typename St::S));
 #pragma unroll
-  for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.ns, IX(nn), f[i]);
+    for (int i = 0; i < Q; ++i) buf_store_pop<St>(bf.fd, vo, i * bf.pb, f[i]);
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) stg(c.J + d * c.ns, IX(nn), J[d]);
-  if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi - res));
+    for (int d = 0; d < L::D; ++d) buf_st<R>(bf.J, unsigned(nn) * unsigned(sizeof(R)), d * bf.jb, J[d]);
+    if constexpr (St::shifted) buf_st<float>(bf.phisd, unsigned(nn) * 4u, 0, float(st.phi - res));
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) St::store(c.pop[1][dst] + i * c.ns, IX(nn), f[i]);
+#pragma unroll
+    for (int d = 0; d < L::D; ++d) stg(c.J + d * c.ns, IX(nn), J[d]);
+    if constexpr (St::shifted) stg(c.phis[dst], IX(nn), float(st.phi - res));
+  }
   if (reduce) {
     const double ph = double(st.phi);
     int lab = 0;
@@ -244,9 +331,12 @@ __device__ __forceinline__ void finish_section3d(const DevCase<D3Q19, St>& c, in
 // VISC: the phases have different viscosities (per-node tau_f of the stress rows)
 // WALL: the case may have walls bounding y (c.wall decides); without it every axis is
 // periodic and no pull is redirected
-template <class St, int NL, bool UNIT, class IX, int BS, bool VISC, bool WALL>
+// BUF: arrays accessed through buffer resources (periodic cases whose arrays each span
+// less than 2 GiB)
+template <class St, int NL, bool UNIT, class IX, int BS, bool VISC, bool WALL, bool BUF>
 __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(DevCase<D3Q19, St> c, int BX, int BY,
                                                                             int nby, int nbz, int reduce) {
+  static_assert(!(BUF && WALL), "buffer access serves periodic cases only");
   using L = D3Q19;
   using R = typename St::R;
   constexpr int Q = L::Q;
@@ -283,6 +373,16 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
   const typename St::S* fsrc = c.pop[1][par];
   const float* phis = c.phis[par];
   const int nx = c.nx, ny = c.ny, nz = c.nz, nxy = nx * ny;
+  Bufs3 bf;
+  bf.pb = int(c.ns * long(sizeof(typename St::S)));
+  bf.jb = int(c.ns * long(sizeof(R)));
+  bf.g = raw_rsrc(gsrc, Q * c.ns);
+  bf.f = raw_rsrc(fsrc, Q * c.ns);
+  bf.gd = raw_rsrc(c.pop[0][par ^ 1], Q * c.ns);
+  bf.fd = raw_rsrc(c.pop[1][par ^ 1], Q * c.ns);
+  bf.phis = raw_rsrc(phis, St::shifted ? c.ns : 0);
+  bf.phisd = raw_rsrc(c.phis[par ^ 1], St::shifted ? c.ns : 0);
+  bf.J = raw_rsrc(c.J, L::D * c.ns);
   // a section spanning the whole (periodic) x extent holds its own x halo: the columns
   // beside it are the images of its last and first columns, so only the two halo rows
   // are pulled
@@ -293,7 +393,7 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     const int zr = wrapi(z, c.nz);
     const int s = ring_slot3d(z) * PS;
     R ps[Q];
-    pull19<St, IX>(gsrc, phis, c.ns, nbr3(xw, yw, zr, nx, ny, nz, nxy, wall), g, ps);
+    pull19<St, IX, BUF>(gsrc, phis, c.ns, bf.g, bf.phis, bf.pb, nbr3(xw, yw, zr, nx, ny, nz, nxy, wall), g, ps);
     R ph = phi_of_pulled<L, St>(g, ps, c.np.rest);
     if (yside) ph = wet_ghost<R>(ph, c.np.wet_hi);   // a lane past a wall holds the ghost row
     const PhiPsi own = PhiPsi{ph, psi_of<R>(ph, c.np.W4, c.np.xi)};
@@ -317,7 +417,8 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
       const int hside = wall ? (hyr < 0 ? -1 : (hyr >= ny ? 1 : 0)) : 0;
       const int hy = wall ? (hyr < 0 ? 0 : (hyr >= ny ? ny - 1 : hyr)) : ((hyr % ny) + ny) % ny;
       R gh[Q], hps[Q];
-      pull19<St, IX>(gsrc, phis, c.ns, nbr3(hx, hy, zr, nx, ny, nz, nxy, wall), gh, hps);
+      pull19<St, IX, BUF>(gsrc, phis, c.ns, bf.g, bf.phis, bf.pb, nbr3(hx, hy, zr, nx, ny, nz, nxy, wall), gh,
+                          hps);
       R hp = phi_of_pulled<L, St>(gh, hps, c.np.rest);
       if (hside) hp = wet_ghost<R>(hp, hside < 0 ? c.np.wet_lo : c.np.wet_hi);
       sring[s + py * PW + px] = PhiPsi{hp, psi_of<R>(hp, c.np.W4, c.np.xi)};
@@ -367,17 +468,20 @@ __global__ void __launch_bounds__(BS, (step3d_min_blocks<St, BS>())) k_step3d(De
     const int nn = o.s0;
     R f[Q], J[L::D];
     if (active) {
-      pull19<St, IX>(fsrc, phis, c.ns, o, f, nullptr);
+      pull19<St, IX, BUF>(fsrc, phis, c.ns, bf.f, bf.phis, bf.pb, o, f, nullptr);
 #pragma unroll
-      for (int d = 0; d < L::D; ++d) J[d] = ldg(c.J + d * c.ns, IX(nn));
+      for (int d = 0; d < L::D; ++d) {
+        if constexpr (BUF) J[d] = buf_ld<R>(bf.J, unsigned(nn) * unsigned(sizeof(R)), d * bf.jb);
+        else J[d] = ldg(c.J + d * c.ns, IX(nn));
+      }
     }
     plane(z + dir, gnext);
     if constexpr (STAGE) stage_put(z + dir, gnext);
     __syncthreads();
     if (active) {
       if constexpr (STAGE) stage_get(z, gcur);
-      update_node3d<St, NL, UNIT, VISC, WALL, IX>(c, sring, PS, PW, tx, ty, xw, yw, z, nn, par, gcur, f, J,
-                                                  reduce != 0, s0, s1, s2, cnt, bad);
+      update_node3d<St, NL, UNIT, VISC, WALL, IX, BUF>(c, bf, sring, PS, PW, tx, ty, xw, yw, z, nn, par, gcur, f,
+                                                       J, reduce != 0, s0, s1, s2, cnt, bad);
     }
     if constexpr (!STAGE) {
 #pragma unroll
@@ -409,19 +513,20 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   const size_t lds = step3d_lds_bytes<St>(tile.bx, tile.by3);
   const dim3 grid(nbx * nby * nbz), block(lanes);
   int rc = 0;
-  auto go = [&](auto nl, auto unit, auto ix, auto visc, auto wall) {
+  auto go = [&](auto nl, auto unit, auto ix, auto visc, auto wall, auto buf) {
     constexpr bool V = decltype(visc)::value;
     constexpr bool WL = decltype(wall)::value;
+    constexpr bool BF = decltype(buf)::value;
     constexpr int NL = decltype(nl)::value;
     constexpr bool U = decltype(unit)::value;
     if (lanes <= 256) {
-      hipLaunchKernelGGL((k_step3d<St, NL, U, decltype(ix), 256, V, WL>), grid, block, lds, s, c, tile.bx, tile.by3,
+      hipLaunchKernelGGL((k_step3d<St, NL, U, decltype(ix), 256, V, WL, BF>), grid, block, lds, s, c, tile.bx, tile.by3,
                          nby, nbz, reduce);
     } else if constexpr (stage3d<St>()) {
       // wide sections stage more than the default 64 KiB of dynamic LDS: raise this
       // instantiation's limit to the device maximum once per device (the tile check has
       // compared the section with that maximum)
-      auto kern = k_step3d<St, NL, U, decltype(ix), 768, V, WL>;
+      auto kern = k_step3d<St, NL, U, decltype(ix), 768, V, WL, BF>;
       static int raised[64] = {};   // per instantiation and device; a repeated raise is harmless
       int dev = 0, max_lds = 0;
       if (hipGetDevice(&dev) != hipSuccess) {
@@ -447,11 +552,17 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   auto pick_wall = [&](auto nl, auto unit, auto ix, auto visc) {
     if constexpr (periodic3d_kernel<St>()) {
       if (!c.wall) {
-        go(nl, unit, ix, visc, std::false_type{});
+        if constexpr (buf3d_kernel<St>()) {
+          if (buf3d_fits(c)) {
+            go(nl, unit, ix, visc, std::false_type{}, std::true_type{});
+            return;
+          }
+        }
+        go(nl, unit, ix, visc, std::false_type{}, std::false_type{});
         return;
       }
     }
-    go(nl, unit, ix, visc, std::true_type{});
+    go(nl, unit, ix, visc, std::true_type{}, std::false_type{});
   };
   auto pick_ix = [&](auto nl, auto unit) {
     if (c.visc) pick_wall(nl, unit, 0L, std::true_type{});
