@@ -473,7 +473,8 @@ def main(argv=None):
     if not a.no_single:
         single = {}
         for name, st in (("two_droplets_4096", "fp32"), ("two_droplets_4096", "fp64"),
-                         ("two_droplets_4096", "fp16s"), ("rayleigh_plateau_96x96x384", "fp32")):
+                         ("two_droplets_4096", "fp16s"), ("rayleigh_plateau_96x96x384", "fp32"),
+                         ("rayleigh_plateau_96x96x384", "fp16s"), ("rayleigh_plateau_96x96x384", "fp64")):
             single[f"{name}_{st}"] = run_single(name, st, min(a.steps, 100), 10, tune=not a.no_single_tune)
             log(f"single {name} {st}: {single[f'{name}_{st}']}")
         out["single_case"] = single
