@@ -1,4 +1,6 @@
-"""GPU check at the largest sizes one case takes: 2^30 nodes (32768 x 32768, D2Q9).
+"""GPU checks at the largest sizes one case takes, 2^30 nodes (32768 x 32768, D2Q9), and
+on either side of the 2 GiB array size up to which the periodic D3Q19 FP16S step uses
+buffer resources (further below).
 
 Such a case has planes of more than 2^29 entries, so its fused step addresses them with
 64-bit offsets, and FP32 planes span more than 4 GiB.  The initial field tiles a 64 x 64
@@ -88,3 +90,60 @@ def test_two_to_the_thirty_nodes_tile_by_tile(storage):
     # the stored phi carries FP32 rounding, the same in every tile (measured 2.3e-8 in
     # FP16S); one missing tile would be 3.8e-6
     assert vtile <= 2e-7 and drift <= 1e-6, (vtile, drift)
+
+
+# D3Q19 FP16S: a periodic case whose arrays each span less than 2 GiB is stepped through
+# buffer resources (32-bit offsets throughout); a larger one falls back to 64-bit plane
+# addresses.  376 x 384 x 384 nodes put the population arrays at 2.1e9 bytes, just below
+# the limit (the largest plane offset, 18 planes of ns entries, near 2^31), and
+# 384 x 384 x 384 just above it.  Both tile a small periodic column 8 x 8 x 8 times: every
+# tile must equal the small case stepped alone bit for bit (the two forms of the kernel
+# differ only in how they address memory).
+BUF3D = {"below_2GiB": ((376, 384, 384), (47, 48, 48)), "above_2GiB": ((384, 384, 384), (48, 48, 48))}
+
+
+@pytest.mark.parametrize("which", list(BUF3D))
+def test_d3q19_fp16s_either_side_of_the_buffer_limit(which):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_10899_amd import vclb
+    (NX, NY, NZ), (sx, sy, sz) = BUF3D[which]
+    reps = (NZ // sz, NY // sy, NX // sx)
+    assert reps == (8, 8, 8)
+    free = torch.cuda.mem_get_info()[0] / 2 ** 30
+    if free < 20:
+        pytest.skip(f"needs about 20 GB of free device memory, {free:.0f} GB free")
+    small = W.CaseParams(nx=sx, ny=sy, nz=sz, lattice="D3Q19", sigma=0.005, nu=0.05, rho_light=0.1,
+                         storage="fp16s", label_centres=[(sx / 2.0 + 0.31, sy / 2.0 + 0.27, 0.0)])
+    phi_small = W.cylinder_phi(small, sx / 2.0 + 0.31, sy / 2.0 + 0.27, 9.0, 0.1, float(sz))
+    big = small.replace(nx=NX, ny=NY, nz=NZ, label_centres=[(NX / 2.0, NY / 2.0, 0.0)])
+    pop_bytes = 19 * ((NX * NY * NZ + 63) // 64 * 64) * 2
+    say(f"case: D3Q19 FP16S {NX} x {NY} x {NZ} ({which}: population arrays {pop_bytes / 2 ** 31:.4f} x 2 GiB), "
+        f"tiled {sx} x {sy} x {sz} column, {STEPS} fused steps")
+    assert (pop_bytes < 2 ** 31) == (which == "below_2GiB")
+    cs = vclb.Case(small).init(phi_small)
+    cs.step(STEPS)
+    Fs = cs.observe(vclb.FIELD_PHI | vclb.FIELD_U)
+    del cs
+    c = vclb.Case(big)
+    phi0 = torch.as_tensor(phi_small, device="cuda").repeat(*reps).contiguous()
+    vclb.check(vclb.lib().vclb_case_init(c.h, ctypes.c_void_p(phi0.data_ptr()), ctypes.c_void_p(0), vclb.DEVICE,
+                                         vclb._stream_handle(None)))
+    torch.cuda.synchronize()
+    del phi0
+    c.step(STEPS)
+    n = NX * NY * NZ
+    out = torch.empty(4 * n, dtype=torch.float64, device="cuda")
+    vclb.check(vclb.lib().vclb_observe(c.h, vclb.FIELD_PHI | vclb.FIELD_U, ctypes.c_void_p(out.data_ptr()),
+                                       vclb.DEVICE, vclb._stream_handle(None)))
+    torch.cuda.synchronize()
+    del c
+    fields = out.view(4, reps[0], sz, reps[1], sy, reps[2], sx)
+    ref = torch.as_tensor(np.concatenate([Fs["phi"][None], Fs["u"]]), device="cuda").view(4, 1, sz, 1, sy, 1, sx)
+    same = bool(torch.equal(fields, ref.expand_as(fields)))
+    spread = float((fields - ref).abs().max())
+    say(f"  every tile bitwise equal to the small case stepped alone: {same} (max difference {spread:.1e})")
+    del out, fields
+    torch.cuda.empty_cache()
+    assert same, spread
