@@ -547,8 +547,8 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
   };
   using One = std::integral_constant<int, 1>;
   using Two = std::integral_constant<int, 2>;
-  // 64-bit indexing: the 32-bit byte-offset form (unsigned IX) measured 0.5% slower in
-  // FP32 and 5.6% slower in FP16S on this kernel (and equal in FP64)
+  // periodic cases in FP16S and FP64: the kernels with no wall tests (FP16S through buffer
+  // resources while its arrays fit them)
   auto pick_wall = [&](auto nl, auto unit, auto ix, auto visc) {
     if constexpr (periodic3d_kernel<St>()) {
       if (!c.wall) {
@@ -564,13 +564,15 @@ int launch_step3d(const DevCase<D3Q19, St>& c, const Tile& tile, int reduce, hip
     }
     go(nl, unit, ix, visc, std::true_type{}, std::false_type{});
   };
-  auto pick_ix = [&](auto nl, auto unit) {
+  // 64-bit indexing (IX = long): the 32-bit byte-offset form (unsigned IX) measured 0.5%
+  // slower in FP32 and 5.6% slower in FP16S on this kernel (and equal in FP64)
+  auto pick_visc = [&](auto nl, auto unit) {
     if (c.visc) pick_wall(nl, unit, 0L, std::true_type{});
     else pick_wall(nl, unit, 0L, std::false_type{});
   };
   auto pick_unit = [&](auto nl) {
-    if (c.unit_rates) pick_ix(nl, std::true_type{});
-    else pick_ix(nl, std::false_type{});
+    if (c.unit_rates) pick_visc(nl, std::true_type{});
+    else pick_visc(nl, std::false_type{});
   };
   if (c.nl > 1) pick_unit(Two{});
   else pick_unit(One{});
